@@ -1,0 +1,223 @@
+"""Seeded synthetic inputs shared by the oracle tests and the GPU path.
+
+This module draws random numbers and lays them out; it holds none of the
+method's arithmetic (no projection, no chunking, no compositing).  Every
+generator takes an explicit seed and uses NumPy's PCG64, so the same call
+gives the same arrays on every machine.
+
+Parameter block layout (the interface both sides read; see ``include/dcgs.h``):
+one float32 array ``params[R, n]`` with R = 11 + 3*K, K = (deg+1)^2 rows
+
+    0..2    mean x, y, z (world, metres)
+    3..5    log-scale along the three local axes
+    6..9    quaternion w, x, y, z (not normalised)
+    10      opacity logit
+    11+3k+c SH coefficient k (k = l*l + l + m) of colour channel c
+
+Cameras are dicts of float64 values: ``R`` (3x3, world->camera rotation),
+``t`` (3, world->camera translation), ``fx, fy, cx, cy``, ``width``,
+``height``, ``z_near``, ``z_far``.  Camera axes: x right, y down, z forward.
+
+The workloads follow the shapes of the paper's indoor and driving
+experiments (synthetic stand-ins for the datasets the paper evaluates on).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ROW_MEAN = 0
+ROW_LOG_SCALE = 3
+ROW_QUAT = 6
+ROW_OPACITY = 10
+ROW_SH = 11
+
+# The degree-0 coefficient that makes a Gaussian's colour exactly `rgb`
+# is (rgb - 0.5) * 2*sqrt(pi): a distribution parameter of the generator.
+_DC_FROM_RGB = 2.0 * math.sqrt(math.pi)
+
+
+def n_rows(sh_degree: int) -> int:
+    return 11 + 3 * (sh_degree + 1) ** 2
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _fill_common(rng, params, n, log_scale_mu, log_scale_sd, sh_degree, rest_sd):
+    params[ROW_LOG_SCALE:ROW_LOG_SCALE + 3] = rng.normal(log_scale_mu, log_scale_sd, (3, n))
+    q = rng.normal(0.0, 1.0, (4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    params[ROW_QUAT:ROW_QUAT + 4] = q
+    params[ROW_OPACITY] = rng.normal(0.0, 1.0, n)
+    rgb = rng.uniform(0.0, 1.0, (3, n))
+    params[ROW_SH:ROW_SH + 3] = (rgb - 0.5) * _DC_FROM_RGB
+    k = (sh_degree + 1) ** 2
+    if k > 1:
+        params[ROW_SH + 3:ROW_SH + 3 * k] = rng.normal(0.0, rest_sd, (3 * (k - 1), n))
+
+
+def camera(R, t, fx, fy, cx, cy, width, height, z_near=0.2, z_far=1000.0) -> dict:
+    return dict(R=np.asarray(R, np.float64).reshape(3, 3), t=np.asarray(t, np.float64).reshape(3),
+                fx=float(fx), fy=float(fy), cx=float(cx), cy=float(cy),
+                width=int(width), height=int(height), z_near=float(z_near), z_far=float(z_far))
+
+
+def look_camera(position, yaw, pitch, fx, fy, width, height, z_near=0.2, z_far=1000.0, cx=None, cy=None):
+    """Camera at `position` (world, z up) looking along yaw/pitch (radians)."""
+    f = np.array([math.cos(pitch) * math.cos(yaw), math.cos(pitch) * math.sin(yaw), math.sin(pitch)])
+    right = np.cross(f, [0.0, 0.0, 1.0])
+    right /= np.linalg.norm(right)
+    down = np.cross(f, right)
+    R_wc = np.stack([right, down, f], axis=1)
+    R = R_wc.T
+    t = -R @ np.asarray(position, np.float64)
+    return camera(R, t, fx, fy, width / 2.0 if cx is None else cx, height / 2.0 if cy is None else cy,
+                  width, height, z_near, z_far)
+
+
+# --------------------------------------------------------------------------
+# Tiny scene: one view, one chunk, SH degree 0.
+# --------------------------------------------------------------------------
+def tiny_scene(n: int = 10_000, seed: int = 0, width: int = 256, height: int = 192,
+               focal: float = 200.0) -> dict:
+    """Means uniform in [-2,2]^2 x [2,6] in front of an identity-pose camera;
+    log-scales N(-3.5, 0.5); uniform unit quaternions; logits N(0,1);
+    colour U(0,1) through the degree-0 coefficient."""
+    rng = _rng(seed)
+    params = np.zeros((n_rows(0), n), np.float64)
+    params[0] = rng.uniform(-2.0, 2.0, n)
+    params[1] = rng.uniform(-2.0, 2.0, n)
+    params[2] = rng.uniform(2.0, 6.0, n)
+    _fill_common(rng, params, n, -3.5, 0.5, 0, 0.0)
+    cam = camera(np.eye(3), np.zeros(3), focal, focal, width / 2.0, height / 2.0, width, height)
+    return dict(params=params.astype(np.float32), sh_degree=0, camera=cam, chunk_size=16.0)
+
+
+def target_image(width: int, height: int, seed: int = 1, channels: int = 3) -> np.ndarray:
+    """Seeded U(0,1) target image, planar [channels, H, W] float32."""
+    return _rng(seed).uniform(0.0, 1.0, (channels, height, width)).astype(np.float32)
+
+
+def upstream_grad(width: int, height: int, seed: int, channels: int = 3, scale: float = 1.0) -> np.ndarray:
+    """Seeded N(0, scale^2) array shaped like an image: an upstream gradient."""
+    return (_rng(seed).normal(0.0, 1.0, (channels, height, width)) * scale).astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Indoor room: floor and four walls of an 8 x 8 x 3 m room.
+# --------------------------------------------------------------------------
+ROOM = (8.0, 8.0, 3.0)
+
+
+def room_scene(n: int, seed: int = 10, sh_degree: int = 3, jitter: float = 0.02,
+               log_scale_mu: float = -3.5, log_scale_sd: float = 0.5, rest_sd: float = 0.05) -> dict:
+    """Gaussians on the floor (z=0) and four walls, allocated by area, with
+    N(0, jitter^2) offsets off the planes."""
+    rng = _rng(seed)
+    Lx, Ly, Lz = ROOM
+    areas = np.array([Lx * Ly, Ly * Lz, Ly * Lz, Lx * Lz, Lx * Lz])
+    counts = np.floor(n * areas / areas.sum()).astype(np.int64)
+    counts[0] += n - counts.sum()
+    pts = []
+    for plane, c in enumerate(counts):
+        a = rng.uniform(0.0, 1.0, c)
+        b = rng.uniform(0.0, 1.0, c)
+        p = np.zeros((3, c))
+        if plane == 0:
+            p[0], p[1], p[2] = a * Lx, b * Ly, 0.0
+        elif plane in (1, 2):
+            p[0], p[1], p[2] = (0.0 if plane == 1 else Lx), a * Ly, b * Lz
+        else:
+            p[0], p[1], p[2] = a * Lx, (0.0 if plane == 3 else Ly), b * Lz
+        pts.append(p)
+    mean = np.concatenate(pts, axis=1) + rng.normal(0.0, jitter, (3, n))
+    params = np.zeros((n_rows(sh_degree), n), np.float64)
+    params[0:3] = mean
+    _fill_common(rng, params, n, log_scale_mu, log_scale_sd, sh_degree, rest_sd)
+    return dict(params=params.astype(np.float32), sh_degree=sh_degree)
+
+
+def perturb(params: np.ndarray, seed: int = 12, dc_sd: float = 0.1, logit_sd: float = 0.5,
+            mean_sd: float = 0.01) -> np.ndarray:
+    """A perturbed copy of a scene, the starting point of optimisation."""
+    rng = _rng(seed)
+    out = params.astype(np.float64).copy()
+    n = out.shape[1]
+    out[0:3] += rng.normal(0.0, mean_sd, (3, n))
+    out[ROW_OPACITY] += rng.normal(0.0, logit_sd, n)
+    out[ROW_SH:ROW_SH + 3] += rng.normal(0.0, dc_sd, (3, n))
+    return out.astype(np.float32)
+
+
+def room_trajectory(n_frames: int, seed: int = 11, width: int = 1200, height: int = 680,
+                    focal: float = 600.0, z_far: float = 6.0, z_near: float = 0.2,
+                    max_step: float = 0.05) -> list:
+    """Smooth random walk: AR(1)-smoothed velocity capped at `max_step` m per
+    frame, x, y in [1, 7], z in [1.2, 1.8], smooth yaw, pitch within +-10 deg."""
+    rng = _rng(seed)
+    pos = np.array([4.0, 4.0, 1.5])
+    vel = np.zeros(3)
+    yaw = rng.uniform(-math.pi, math.pi)
+    yaw_rate = 0.0
+    cams = []
+    for _ in range(n_frames):
+        vel = 0.9 * vel + 0.1 * rng.normal(0.0, max_step, 3) * np.array([1.0, 1.0, 0.3])
+        sp = np.linalg.norm(vel)
+        if sp > max_step:
+            vel *= max_step / sp
+        pos = pos + vel
+        for ax, lo, hi in ((0, 1.0, 7.0), (1, 1.0, 7.0), (2, 1.2, 1.8)):
+            if pos[ax] < lo or pos[ax] > hi:
+                pos[ax] = min(max(pos[ax], lo), hi)
+                vel[ax] = -vel[ax]
+        yaw_rate = 0.95 * yaw_rate + 0.05 * rng.normal(0.0, 0.05)
+        yaw += yaw_rate
+        pitch = math.radians(10.0) * math.sin(0.01 * len(cams) + seed)
+        cams.append(look_camera(pos.copy(), yaw, pitch, focal, focal, width, height, z_near, z_far))
+    return cams
+
+
+# --------------------------------------------------------------------------
+# Small chunk grids for visibility tests.
+# --------------------------------------------------------------------------
+def random_cameras(n: int, seed: int, extent: float, width: int = 64, height: int = 48,
+                   focal: float = 40.0, z_near: float = 0.2, z_far: float = 3.0) -> list:
+    """Cameras at random positions in [-extent, extent]^3 with random
+    orientation (SciPy's uniform random rotation)."""
+    from scipy.spatial.transform import Rotation
+
+    rng = _rng(seed)
+    cams = []
+    for _ in range(n):
+        R = Rotation.random(random_state=rng).as_matrix()
+        C = rng.uniform(-extent, extent, 3)
+        cams.append(camera(R, -R @ C, focal * rng.uniform(0.5, 2.0), focal * rng.uniform(0.5, 2.0),
+                           width / 2.0, height / 2.0, width, height, z_near,
+                           z_far * rng.uniform(0.5, 2.0)))
+    return cams
+
+
+def grid_coords(n_side: int, offset: int = -3) -> np.ndarray:
+    """All integer chunk coordinates of an n_side^3 block, int64 [m, 3]."""
+    r = np.arange(n_side) + offset
+    cx, cy, cz = np.meshgrid(r, r, r, indexing="ij")
+    return np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1).astype(np.int64)
+
+
+def adam_inputs(n_rows_: int, n: int, seed: int, n_slots: int | None = None) -> dict:
+    """Random parameters, gradients, moments and step counters for optimiser
+    tests; `src` is a random injective map from n compacted entries into
+    n_slots pool slots."""
+    rng = _rng(seed)
+    n_slots = n if n_slots is None else n_slots
+    src = rng.permutation(n_slots)[:n].astype(np.int32)
+    return dict(
+        params=rng.normal(0.0, 1.0, (n_rows_, n_slots)).astype(np.float32),
+        m=rng.normal(0.0, 1e-3, (n_rows_, n_slots)).astype(np.float32),
+        v=np.abs(rng.normal(0.0, 1e-6, (n_rows_, n_slots))).astype(np.float32),
+        step=rng.integers(0, 50, n_slots).astype(np.int32),
+        grad=(rng.normal(0.0, 1e-4, (n_rows_, n)) * (rng.uniform(0, 1, (n_rows_, n)) > 0.1)).astype(np.float32),
+        src=src)
