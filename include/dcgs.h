@@ -1,0 +1,252 @@
+/*
+ * dcgs.h -- C ABI of the DiskChunGS mapping-step hot path on MI355X (gfx950).
+ *
+ * The paper (DiskChunGS, arXiv 2511.23030) optimises a chunked 3D Gaussian
+ * Splatting map one keyframe at a time (Sec. III-E "Optimization"): the chunks
+ * the keyframe sees are found by frustum culling (Sec. III-D "Frustum
+ * Culling"), loaded into device memory under an LRU budget (Sec. III-E, "LRU
+ * Eviction Strategy"), the visible Gaussians are indexed into one buffer, the
+ * rasterizer renders RGB and depth, and the losses of Eqs. (2)-(4) drive an
+ * optimiser step.  Each call below is one of those steps.
+ *
+ * Conventions
+ *  - Every call returns a dcgs_status.  No C++ exception or abort crosses the
+ *    ABI; after an error dcgs_last_error(ctx) holds a message.
+ *  - "device" pointers are HIP device memory (e.g. a torch tensor's
+ *    data_ptr()); "host" pointers are CPU memory.  The caller owns every
+ *    pointer it passes; the library never frees caller memory.  The context,
+ *    render states and pools own their internal scratch.
+ *  - `stream` is a hipStream_t passed as void*.  Calls are asynchronous on
+ *    it unless marked SYNC (the call waits for the stream and returns after
+ *    the work it names is complete).
+ *  - A context and everything created from it belong to one host thread and
+ *    one device.
+ *
+ * Parameter block (SoA, float32): rows of length >= n with a row stride
+ *    row 0..2   mean x, y, z (world metres)
+ *    row 3..5   log-scale of the three local axes
+ *    row 6..9   quaternion w, x, y, z (need not be normalised)
+ *    row 10     opacity logit
+ *    row 11+3k+c  SH coefficient k = l*l + l + m of colour channel c
+ *  R = 11 + 3 (deg + 1)^2 rows; deg in {0, 1, 2, 3}.
+ *
+ * Rendering model (the paper cites 3D Gaussian Splatting for it and states
+ * no formula of its own; this library implements this exact reading):
+ *  s = exp(log_scale), o = sigmoid(logit), Sigma = R(q/|q|) S S^T R^T;
+ *  camera (X, Y, Z) = R_cw mu + t_cw, u = fx X/Z + cx, v = fy Y/Z + cy,
+ *  pixel (i, j) centred at (i + .5, j + .5);
+ *  Sigma2 = J R_cw Sigma R_cw^T J^T + 0.3 I (EWA, J the pinhole Jacobian);
+ *  culled if Z <= z_near, |X/Z| > 1.3 (W/2)/fx, |Y/Z| > 1.3 (H/2)/fy,
+ *  o < 1/255 or an empty pixel box; pixel box = axis-aligned box of the
+ *  ellipse where o exp(-d^T Sigma2^-1 d / 2) >= 1/255, clipped to the image;
+ *  colour = max(sum_k f_k Y_k(d) + 0.5, 0), d from the camera centre to mu,
+ *  real orthonormal SH without Condon-Shortley phase;
+ *  per pixel, Gaussians whose box holds it in (float32 depth, index) order:
+ *  alpha = min(0.99, o e^{-d^T Q d / 2}), skipped below 1/255, compositing
+ *  stops before T would fall below 1e-4; C = sum c alpha T + T bg,
+ *  D = sum Z alpha T.
+ */
+#ifndef DCGS_H
+#define DCGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dcgs_status {
+  DCGS_OK = 0,
+  DCGS_E_INVALID = 1,      /* null pointer, bad size or shape, bad enum    */
+  DCGS_E_CAPACITY = 2,     /* an output buffer is too small; see *_required */
+  DCGS_E_BUDGET = 3,       /* visible set exceeds the residency budget      */
+  DCGS_E_NOT_RESIDENT = 4, /* a chunk id is not resident / not in the pool  */
+  DCGS_E_HIP = 5,          /* a HIP runtime call failed                     */
+  DCGS_E_RANGE = 6         /* a chunk coordinate outside Eq. (6)'s range   */
+} dcgs_status;
+
+typedef struct dcgs_ctx dcgs_ctx;
+typedef struct dcgs_state dcgs_state;
+typedef struct dcgs_pool dcgs_pool;
+
+/* Pinhole camera, world -> camera.  R is row-major 3x3. */
+typedef struct dcgs_camera {
+  double R[9];
+  double t[3];
+  double fx, fy, cx, cy;
+  int32_t width, height;
+  double z_near, z_far;
+} dcgs_camera;
+
+/* Adam settings: learning rate per parameter group (0 means, 1 log-scales,
+ * 2 quaternions, 3 opacity logit, 4 SH degree 0, 5 higher SH). */
+typedef struct dcgs_adam_config {
+  float lr[6];
+  float beta1, beta2, eps;
+} dcgs_adam_config;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Library version string (static storage). */
+const char *dcgs_version(void);
+
+/* Create a context on HIP device `device`.  *out is set on success. */
+int dcgs_create(dcgs_ctx **out, int device);
+void dcgs_destroy(dcgs_ctx *ctx);
+/* Message of the last failed call on `ctx` (static until the next call). */
+const char *dcgs_last_error(const dcgs_ctx *ctx);
+
+/* ---- chunks: Sec. III-D, Eqs. (5) and (6) --------------------------------- */
+
+/* EncodedID of the chunk of each Gaussian: c_i = floor((p_i + s/2)/s)
+ * (Eq. 5, float64), ID = (cx+2^20) 2^42 + (cy+2^20) 2^21 + (cz+2^20)
+ * (Eq. 6).  mean: device [3][stride]; out_ids: device [n].  A coordinate
+ * outside [-2^20, 2^20-1] gives id UINT64_MAX and, SYNC, DCGS_E_RANGE. */
+int dcgs_chunk_ids(dcgs_ctx *ctx, const float *mean, int64_t n, int64_t stride,
+                   double chunk_size, uint64_t *out_ids, void *stream);
+
+/* Visible chunks (Sec. III-D "Frustum Culling", Sec. III-E): chunk c is
+ * visible in a view iff its closed cubic cell [c s - s/2, c s + s/2]^3 meets
+ * the closed frustum {z_near <= Z <= z_far, 0 <= u <= W, 0 <= v <= H}
+ * (separating-axis test in float64; the paper's hierarchical plane test is
+ * a faster route to the same set).  The distance filter is the z_far plane.
+ *   cams: host [n_views], 1 <= n_views <= 16
+ *   ids:  device [n_chunks] ascending EncodedIDs of the occupied chunks
+ *   out_ids: device [n_chunks] visible ids, ascending (union over views)
+ *   out_mask: device [n_chunks] bit v set when view v sees the chunk
+ *   out_count: device int32, number of visible ids written. */
+int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
+                       const uint64_t *ids, int n_chunks, double chunk_size,
+                       uint64_t *out_ids, uint16_t *out_mask,
+                       int32_t *out_count, void *stream);
+
+/* ---- residency pool: Sec. III-E "Optimization" / "LRU Eviction Strategy" --- */
+
+/* A chunk store in pinned host memory plus a device pool holding at most
+ * `budget` Gaussians (the paper's VRAM budget, counted in Gaussians).  Each
+ * Gaussian carries its parameters, Adam moments m and v, and a step count. */
+int dcgs_pool_create(dcgs_ctx *ctx, int sh_degree, int64_t budget,
+                     dcgs_pool **out);
+void dcgs_pool_destroy(dcgs_pool *pool);
+
+/* SYNC.  Add a scene: params is a HOST parameter block [R][n] (row stride n).
+ * Each Gaussian goes to the chunk of Eqs. (5)-(6) (ids computed on the
+ * device); within a chunk Gaussians keep their input order.  Moments and
+ * steps start at zero.  May be called once per pool. */
+int dcgs_pool_ingest(dcgs_pool *pool, const float *params, int64_t n,
+                     double chunk_size, void *stream);
+
+/* Occupied chunks in ascending id order.  ids/counts: host, capacity
+ * entries; *n_out gets the number of chunks (DCGS_E_CAPACITY if larger). */
+int dcgs_pool_chunks(dcgs_pool *pool, uint64_t *ids, int64_t *counts,
+                     int capacity, int *n_out);
+
+/* Device array of the occupied chunk ids (ascending), for select_chunks. */
+const uint64_t *dcgs_pool_device_ids(dcgs_pool *pool, int *n_out);
+
+/* SYNC.  Make the chunks `ids` (host, n) resident: load = ids \ resident;
+ * if the budget would be exceeded, evict the evictable (resident, not in
+ * ids) chunks oldest access first (ties: lower id), the shortest such prefix
+ * that fits, writing their state back to the host store.  The chunks in ids
+ * get access time `now`.  DCGS_E_BUDGET if ids alone do not fit (nothing is
+ * changed then).  *loaded / *evicted (nullable) get the chunk counts. */
+int dcgs_pool_require(dcgs_pool *pool, const uint64_t *ids, int n,
+                      int64_t now, int *loaded, int *evicted, void *stream);
+
+/* SYNC.  Current state of one chunk (from the device if resident, else the
+ * host store), into host arrays params/m/v [R][count] and step [count];
+ * any of them may be null. */
+int dcgs_pool_read_chunk(dcgs_pool *pool, uint64_t id, float *params,
+                         float *m, float *v, int32_t *step);
+
+/* Resident chunk ids (host, capacity) and Gaussians resident. */
+int dcgs_pool_resident(dcgs_pool *pool, uint64_t *ids, int capacity,
+                       int *n_out, int64_t *gaussians_out);
+
+/* ---- compaction: Sec. III-E ("index only the visible Gaussians") ---------- */
+
+/* Concatenate the Gaussians of the resident chunks `ids` (host, n_ids, any
+ * order; processed ascending) into out [R][out_stride] (device) and write
+ * each one's pool slot to out_src (device int32).  Optional out_gmask
+ * (device uint16 [n]) gets the view mask of the Gaussian's chunk taken from
+ * masks (host uint16 [n_ids], parallel to ids; null -> all ones).  *n_out
+ * (host) gets the number of Gaussians; DCGS_E_CAPACITY if > capacity;
+ * DCGS_E_NOT_RESIDENT if a chunk is not resident. */
+int dcgs_compact(dcgs_pool *pool, const uint64_t *ids, const uint16_t *masks,
+                 int n_ids, float *out, int64_t out_stride, int32_t *out_src,
+                 uint16_t *out_gmask, int64_t capacity, int64_t *n_out,
+                 void *stream);
+
+/* ---- differentiable rendering ------------------------------------------- */
+
+/* A render state holds what a backward pass needs from its forward: per
+ * Gaussian projection records, the depth order, the (tile, Gaussian) pairs
+ * sorted by (tile, float32 depth bits, index), per-tile ranges, and per
+ * pixel the final transmittance and the position of the last composited
+ * Gaussian.  A state serves one forward/backward pair at a time. */
+int dcgs_state_create(dcgs_ctx *ctx, dcgs_state **out);
+void dcgs_state_destroy(dcgs_state *st);
+
+/* SYNC (reads the pair count back once).  Render one view.
+ *   params: device [R][stride], n Gaussians, SH degree sh_degree
+ *   cam: host; bg: host float[3]; tile_w x tile_h in {8x8, 16x16, 32x16}
+ *   rgb: device [3][H][W]; depth: device [H][W]; T: device [H][W] or null.
+ * Outputs are overwritten.  The state keeps what render_bwd needs. */
+int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params,
+                    int64_t n, int64_t stride, int sh_degree,
+                    const dcgs_camera *cam, const float *bg, int tile_w,
+                    int tile_h, float *rgb, float *depth, float *T,
+                    void *stream);
+
+/* Backward of the last render_fwd on `st` (same params): the adjoint of the
+ * compositing runs back to front from each pixel's last composited Gaussian,
+ * recovering each earlier transmittance by division, then chains through
+ * the projection to the raw parameters.
+ *   dl_drgb: device [3][H][W]; dl_ddepth: device [H][W] or null
+ *   grad: device [R][grad_stride]; accumulate != 0 adds into it, 0
+ *   overwrites rows for all n Gaussians (culled ones get 0).
+ *   grad2d: device [10][n] or null: per-Gaussian dL/d(u, v, Q00, Q01, Q11,
+ *   o, r, g, b, Z) of the screen-space record (Q01 counted once). */
+int dcgs_render_bwd(dcgs_ctx *ctx, dcgs_state *st, const float *params,
+                    int64_t n, int64_t stride, const float *dl_drgb,
+                    const float *dl_ddepth, float *grad, int64_t grad_stride,
+                    int accumulate, float *grad2d, void *stream);
+
+/* Eqs. (2)-(4) without SSIM: dl_drgb = sign(rgb - target) / count (0 at
+ * equality); stats (device double[2]) gets sum |rgb - target| and the sum of
+ * squared error with rgb clipped to [0, 1] (for PSNR). */
+int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target,
+                 int64_t count, float *dl_drgb, double *stats, void *stream);
+
+/* ---- optimiser: per-Gaussian Adam state (Sec. III-G resets it) ----------- */
+
+/* One Adam step for the n compacted Gaussians: row r of grad (device
+ * [R][grad_stride]) updates pool slot src[i] (device int32) in place:
+ * t += 1, m, v moments, bias-corrected update with the group learning rate.
+ * Every listed Gaussian is updated (zero gradients included). */
+int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad,
+                   int64_t n, int64_t grad_stride,
+                   const dcgs_adam_config *cfg, void *stream);
+
+/* ---- inspection (for tests and tools) ------------------------------------ */
+
+/* Sizes of the last forward on st: Gaussians, pairs, tiles in x and y. */
+int dcgs_state_info(const dcgs_state *st, int64_t *n, int64_t *n_pairs,
+                    int32_t *tiles_x, int32_t *tiles_y);
+
+/* Copy results of the last forward into device buffers (null to skip):
+ *   keys [n_pairs] uint64 (tile << 32 | float32 depth bits), values [n_pairs]
+ *   int32 Gaussian index, ranges [tiles][2] int32, counts [n] int32 tiles
+ *   touched per Gaussian, records [10][n] float (u, v, Q00, Q01, Q11, o, r,
+ *   g, b, Z), box [4][n] int32 (i0, i1, j0, j1; culled: count 0), last
+ *   [H][W] int32 (position in the sorted pairs, -1 if none). */
+int dcgs_state_export(const dcgs_state *st, uint64_t *keys, int32_t *values,
+                      int32_t *ranges, int32_t *counts, float *records,
+                      int32_t *box, int32_t *last, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DCGS_H */

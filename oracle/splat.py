@@ -162,24 +162,29 @@ def preprocess(params: np.ndarray, sh_degree: int, cam: dict, tile=(16, 16),
         zf = Zd.astype(np.float32)
         zbits = zf.view(np.int32).astype(np.int64)
 
-        # Margins of every integer decision (relative); 1e-9 is far above the
-        # float64 disagreement of two correct implementations (~1e-15).
+        # Margins of every integer decision that is actually reached
+        # (relative); 1e-11 is far above the float64 disagreement of two
+        # correct implementations (~1e-15).
         def frac_margin(x):
             return np.abs(x - np.round(x)) / np.maximum(1.0, np.abs(x))
+        inf = np.full(Zd.shape, np.inf)
         with np.errstate(divide="ignore", invalid="ignore"):
-            m = np.minimum.reduce([
-                np.abs(Zd - cam["z_near"]) / cam["z_near"],
-                np.abs(rx - lim_x) / lim_x, np.abs(ry - lim_y) / lim_y,
-                np.abs(255.0 * od - 1.0),
-                frac_margin(e0), frac_margin(e1), frac_margin(f0), frac_margin(f1),
-            ])
+            front = Zd > cam["z_near"]
+            m_near = np.abs(Zd - cam["z_near"]) / cam["z_near"]
+            m_guard = np.where(front, np.minimum(np.abs(rx - lim_x) / lim_x, np.abs(ry - lim_y) / lim_y), inf)
+            m_opac = np.abs(255.0 * od - 1.0)
+            reach_box = front & (rx <= lim_x) & (ry <= lim_y) & (od >= ALPHA_MIN) & (dd > 0)
+            m_box = np.where(reach_box, np.minimum.reduce([frac_margin(e0), frac_margin(e1),
+                                                           frac_margin(f0), frac_margin(f1)]), inf)
+            m = np.minimum.reduce([m_near, m_guard, m_opac, m_box])
             ulp = np.abs(np.nextafter(zf, np.float32(np.inf)).astype(np.float64) - zf.astype(np.float64))
-            mz = np.abs(np.abs(Zd - zf.astype(np.float64)) - 0.5 * ulp) / np.abs(Zd)
-        m = np.where(np.isfinite(m), m, 0.0)
-        key_tie = (m < 1e-9) | (mz < 1e-9)
+            mz = np.where(culled, inf, np.abs(np.abs(Zd - zf.astype(np.float64)) - 0.5 * ulp) / np.abs(Zd))
+        key_tie = (m < 1e-11) | (mz < 1e-11)
         rgb_margin = np.abs(raw.numpy()).min(axis=1)
 
-    return Records(params=P, u=u, v=v, conic=conic, opacity=opac, rgb=rgb, z=Z, zbits=zbits,
+    # The composited depth is its own graph node, so its gradient is the
+    # depth-channel term alone (Z also reaches u, v and the conic).
+    return Records(params=P, u=u, v=v, conic=conic, opacity=opac, rgb=rgb, z=Z.clone(), zbits=zbits,
                    culled=culled, box=box, tile_rect=rect, raw_rgb_margin=rgb_margin,
                    key_tie=key_tie, width=W, height=H, tile=tuple(tile))
 

@@ -1,0 +1,279 @@
+// C ABI of libdcgs: argument checks, error capture, and dispatch to the
+// kernels and the host runtime.  No C++ exception leaves this file.
+#include <cstring>
+
+#include "internal.h"
+
+namespace dcgs {
+void pool_create(dcgs_ctx *ctx, int deg, int64_t budget, dcgs_pool **out);
+void pool_destroy(dcgs_pool *p);
+void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStream_t st);
+void pool_require(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *loaded,
+                  int *evicted, hipStream_t st);
+void pool_read_chunk(dcgs_pool *p, uint64_t id, float *params, float *m, float *v,
+                     int32_t *step);
+void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                  float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
+                  int64_t capacity, int64_t *n_out, hipStream_t st);
+}  // namespace dcgs
+
+namespace {
+
+template <typename F>
+int guarded(dcgs_ctx *ctx, F &&f) {
+  try {
+    f();
+    if (ctx) ctx->err.clear();
+    return DCGS_OK;
+  } catch (const dcgs::Error &e) {
+    if (ctx) ctx->err = e.msg;
+    return e.status;
+  } catch (const std::exception &e) {
+    if (ctx) ctx->err = e.what();
+    return DCGS_E_HIP;
+  } catch (...) {
+    if (ctx) ctx->err = "unknown error";
+    return DCGS_E_HIP;
+  }
+}
+
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_cam(const dcgs_camera *c) {
+  DCGS_CHECK(c != nullptr, DCGS_E_INVALID, "null camera");
+  DCGS_CHECK(c->width > 0 && c->height > 0 && c->width < 65536 && c->height < 65536,
+             DCGS_E_INVALID, "camera size out of range");
+  DCGS_CHECK(c->fx > 0 && c->fy > 0 && c->z_near > 0 && c->z_far > c->z_near, DCGS_E_INVALID,
+             "camera intrinsics or clip planes invalid");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dcgs_version(void) { return "dcgs 0.1 gfx950"; }
+
+int dcgs_create(dcgs_ctx **out, int device) {
+  if (!out) return DCGS_E_INVALID;
+  *out = nullptr;
+  auto *ctx = new dcgs_ctx();
+  int st = guarded(ctx, [&] {
+    DCGS_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    DCGS_HIP(hipGetDeviceProperties(&prop, device));
+    ctx->device = device;
+    ctx->n_cu = prop.multiProcessorCount;
+  });
+  if (st != DCGS_OK) {
+    delete ctx;
+    return st;
+  }
+  *out = ctx;
+  return DCGS_OK;
+}
+
+void dcgs_destroy(dcgs_ctx *ctx) { delete ctx; }
+
+const char *dcgs_last_error(const dcgs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int dcgs_chunk_ids(dcgs_ctx *ctx, const float *mean, int64_t n, int64_t stride, double chunk_size,
+                   uint64_t *out_ids, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(n >= 0 && stride >= n && chunk_size > 0 && (n == 0 || (mean && out_ids)),
+               DCGS_E_INVALID, "chunk_ids: bad args");
+    int *flag = ctx->flag.need(1);
+    DCGS_HIP(hipMemsetAsync(flag, 0, sizeof(int), S(stream)));
+    dcgs::launch_chunk_ids(mean, n, stride, chunk_size, out_ids, flag, S(stream));
+    int h = 0;
+    DCGS_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, S(stream)));
+    DCGS_HIP(hipStreamSynchronize(S(stream)));
+    DCGS_CHECK(h == 0, DCGS_E_RANGE, "chunk_ids: coordinate outside the range of Eq. (6)");
+  });
+}
+
+int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views, const uint64_t *ids,
+                       int n_chunks, double chunk_size, uint64_t *out_ids, uint16_t *out_mask,
+                       int32_t *out_count, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(cams && n_views >= 1 && n_views <= dcgs::kMaxViews, DCGS_E_INVALID,
+               "select_chunks: 1..16 views required");
+    for (int v = 0; v < n_views; ++v) check_cam(&cams[v]);
+    DCGS_CHECK(n_chunks >= 0 && chunk_size > 0 && out_count &&
+                   (n_chunks == 0 || (ids && out_ids && out_mask)),
+               DCGS_E_INVALID, "select_chunks: bad buffers");
+    uint16_t *tmp = ctx->sel_mask.need((size_t)n_chunks + 1);
+    dcgs::launch_select(cams, n_views, ids, n_chunks, chunk_size, tmp, out_ids, out_mask,
+                        out_count, S(stream));
+  });
+}
+
+int dcgs_pool_create(dcgs_ctx *ctx, int sh_degree, int64_t budget, dcgs_pool **out) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] { dcgs::pool_create(ctx, sh_degree, budget, out); });
+}
+
+void dcgs_pool_destroy(dcgs_pool *pool) { dcgs::pool_destroy(pool); }
+
+int dcgs_pool_ingest(dcgs_pool *pool, const float *params, int64_t n, double chunk_size,
+                     void *stream) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] { dcgs::pool_ingest(pool, params, n, chunk_size, S(stream)); });
+}
+
+int dcgs_pool_chunks(dcgs_pool *pool, uint64_t *ids, int64_t *counts, int capacity, int *n_out) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] {
+    DCGS_CHECK(n_out, DCGS_E_INVALID, "pool_chunks: null n_out");
+    *n_out = (int)pool->chunks.size();
+    DCGS_CHECK((int)pool->chunks.size() <= capacity, DCGS_E_CAPACITY, "pool_chunks: capacity");
+    for (size_t c = 0; c < pool->chunks.size(); ++c) {
+      if (ids) ids[c] = pool->chunks[c].id;
+      if (counts) counts[c] = pool->chunks[c].n;
+    }
+  });
+}
+
+const uint64_t *dcgs_pool_device_ids(dcgs_pool *pool, int *n_out) {
+  if (!pool) return nullptr;
+  if (n_out) *n_out = (int)pool->chunks.size();
+  return pool->d_ids.p;
+}
+
+int dcgs_pool_require(dcgs_pool *pool, const uint64_t *ids, int n, int64_t now, int *loaded,
+                      int *evicted, void *stream) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx,
+                 [&] { dcgs::pool_require(pool, ids, n, now, loaded, evicted, S(stream)); });
+}
+
+int dcgs_pool_read_chunk(dcgs_pool *pool, uint64_t id, float *params, float *m, float *v,
+                         int32_t *step) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] { dcgs::pool_read_chunk(pool, id, params, m, v, step); });
+}
+
+int dcgs_pool_resident(dcgs_pool *pool, uint64_t *ids, int capacity, int *n_out,
+                       int64_t *gaussians_out) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] {
+    int k = 0;
+    for (auto &c : pool->chunks)
+      if (c.resident) {
+        if (ids && k < capacity) ids[k] = c.id;
+        ++k;
+      }
+    if (n_out) *n_out = k;
+    if (gaussians_out) *gaussians_out = pool->resident_g;
+    DCGS_CHECK(!ids || k <= capacity, DCGS_E_CAPACITY, "pool_resident: capacity");
+  });
+}
+
+int dcgs_compact(dcgs_pool *pool, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                 float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
+                 int64_t capacity, int64_t *n_out, void *stream) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] {
+    dcgs::pool_compact(pool, ids, masks, n_ids, out, out_stride, out_src, out_gmask, capacity,
+                       n_out, S(stream));
+  });
+}
+
+int dcgs_state_create(dcgs_ctx *ctx, dcgs_state **out) {
+  if (!ctx || !out) return DCGS_E_INVALID;
+  auto *s = new dcgs_state();
+  s->ctx = ctx;
+  *out = s;
+  return DCGS_OK;
+}
+
+void dcgs_state_destroy(dcgs_state *st) { delete st; }
+
+int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n,
+                    int64_t stride, int sh_degree, const dcgs_camera *cam, const float *bg,
+                    int tile_w, int tile_h, float *rgb, float *depth, float *T, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(st && st->ctx == ctx, DCGS_E_INVALID, "render_fwd: state of another context");
+    DCGS_CHECK(n >= 0 && n < (int64_t(1) << 31) && stride >= n && (n == 0 || params),
+               DCGS_E_INVALID, "render_fwd: bad parameter block");
+    DCGS_CHECK(sh_degree >= 0 && sh_degree <= 3, DCGS_E_INVALID, "render_fwd: sh_degree 0..3");
+    DCGS_CHECK((tile_w == 16 && tile_h == 16) || (tile_w == 8 && tile_h == 8) ||
+                   (tile_w == 32 && tile_h == 16),
+               DCGS_E_INVALID, "render_fwd: tile must be 8x8, 16x16 or 32x16");
+    check_cam(cam);
+    DCGS_CHECK(bg && rgb && depth, DCGS_E_INVALID, "render_fwd: null output");
+    st->cam = *cam;
+    st->W = cam->width;
+    st->H = cam->height;
+    st->TW = tile_w;
+    st->TH = tile_h;
+    st->tiles_x = (cam->width + tile_w - 1) / tile_w;
+    st->tiles_y = (cam->height + tile_h - 1) / tile_h;
+    DCGS_CHECK((int64_t)st->tiles_x * st->tiles_y < (int64_t(1) << 24), DCGS_E_INVALID,
+               "render_fwd: too many tiles");
+    st->sh_degree = sh_degree;
+    std::memcpy(st->bg, bg, 3 * sizeof(float));
+    dcgs::render_forward(st, params, n, stride, S(stream), rgb, depth, T);
+  });
+}
+
+int dcgs_render_bwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n,
+                    int64_t stride, const float *dl_drgb, const float *dl_ddepth, float *grad,
+                    int64_t grad_stride, int accumulate, float *grad2d, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(st && st->ctx == ctx, DCGS_E_INVALID, "render_bwd: state of another context");
+    DCGS_CHECK(n == st->n && st->W > 0, DCGS_E_INVALID,
+               "render_bwd: n differs from the last forward on this state");
+    DCGS_CHECK(dl_drgb && (n == 0 || (params && grad && grad_stride >= n && stride >= n)),
+               DCGS_E_INVALID, "render_bwd: bad buffers");
+    dcgs::render_backward(st, params, n, stride, dl_drgb, dl_ddepth, grad, grad_stride,
+                          accumulate, grad2d, S(stream));
+  });
+}
+
+int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target, int64_t count,
+                 float *dl_drgb, double *stats, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(rgb && target && dl_drgb && stats && count > 0, DCGS_E_INVALID,
+               "loss_l1: bad args");
+    float *part = ctx->loss_part.need(2 * 1024);
+    dcgs::launch_loss_l1(rgb, target, count, dl_drgb, stats, part, S(stream));
+  });
+}
+
+int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad, int64_t n,
+                   int64_t grad_stride, const dcgs_adam_config *cfg, void *stream) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] {
+    DCGS_CHECK(cfg && n >= 0 && (n == 0 || (src && grad && grad_stride >= n)), DCGS_E_INVALID,
+               "adam_step: bad args");
+    DCGS_CHECK(pool->d_params, DCGS_E_INVALID, "adam_step: pool holds no scene");
+    dcgs::launch_adam(pool->d_params, pool->d_m, pool->d_v, pool->d_step, pool->R, src, grad, n,
+                      grad_stride, *cfg, S(stream));
+  });
+}
+
+int dcgs_state_info(const dcgs_state *st, int64_t *n, int64_t *n_pairs, int32_t *tiles_x,
+                    int32_t *tiles_y) {
+  if (!st) return DCGS_E_INVALID;
+  if (n) *n = st->n;
+  if (n_pairs) *n_pairs = st->n_pairs;
+  if (tiles_x) *tiles_x = st->tiles_x;
+  if (tiles_y) *tiles_y = st->tiles_y;
+  return DCGS_OK;
+}
+
+int dcgs_state_export(const dcgs_state *st, uint64_t *keys, int32_t *values, int32_t *ranges,
+                      int32_t *counts, float *records, int32_t *box, int32_t *last,
+                      void *stream) {
+  if (!st) return DCGS_E_INVALID;
+  return guarded(st->ctx, [&] {
+    dcgs::export_state(st, keys, values, ranges, counts, records, box, last, S(stream));
+  });
+}
+
+}  // extern "C"

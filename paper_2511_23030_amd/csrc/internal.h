@@ -1,0 +1,204 @@
+// Internal declarations of libdcgs: context, render state, pool, device
+// helpers and the launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dcgs.h"
+
+namespace dcgs {
+
+constexpr int kWave = 64;
+constexpr int kMaxViews = 16;
+constexpr int kRecFloats = 12;  // three float4 per projection record
+
+// Thrown inside the library only; every C entry point converts it to a status.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+#define DCGS_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::dcgs::Error{DCGS_E_HIP, std::string(#call) + ": " +             \
+                                          hipGetErrorString(e_)};             \
+  } while (0)
+
+#define DCGS_CHECK(cond, status, msg)                                         \
+  do {                                                                        \
+    if (!(cond)) throw ::dcgs::Error{(status), (msg)};                        \
+  } while (0)
+
+#define DCGS_LAUNCH_CHECK() DCGS_HIP(hipGetLastError())
+
+// Growable device buffer (never shrinks).
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  T *need(size_t n) {
+    if (n > cap) {
+      if (p) DCGS_HIP(hipFree(p));
+      p = nullptr;
+      size_t c = n + n / 8 + 64;
+      DCGS_HIP(hipMalloc(&p, c * sizeof(T)));
+      cap = c;
+    }
+    return p;
+  }
+};
+
+inline int n_rows(int deg) { return 11 + 3 * (deg + 1) * (deg + 1); }
+
+// Number of radix passes / digit width for a key of `bits` significant bits.
+inline void digit_plan(int bits, int *passes, int *width) {
+  if (bits <= 0) {
+    *passes = 0;
+    *width = 0;
+    return;
+  }
+  *passes = (bits + 7) / 8;
+  *width = (bits + *passes - 1) / *passes;
+}
+
+}  // namespace dcgs
+
+struct dcgs_ctx {
+  int device = 0;
+  std::string err;
+  dcgs::DevBuf<uint16_t> sel_mask;
+  dcgs::DevBuf<int> flag;
+  dcgs::DevBuf<float> loss_part;
+  dcgs::DevBuf<uint32_t> scan_part;
+  int n_cu = 256;
+};
+
+struct dcgs_state {
+  dcgs_ctx *ctx = nullptr;
+  // shape of the last forward
+  int64_t n = 0, n_pairs = 0;
+  int W = 0, H = 0, TW = 16, TH = 16, tiles_x = 0, tiles_y = 0, sh_degree = 0;
+  float bg[3] = {0, 0, 0};
+  dcgs_camera cam{};
+  // per Gaussian
+  dcgs::DevBuf<float4> rec;        // [3][n] float4 (A, B, C planes)
+  dcgs::DevBuf<uint32_t> zkey;     // [n]
+  dcgs::DevBuf<uint32_t> count;    // [n]
+  dcgs::DevBuf<uint32_t> order;    // [n] depth order -> Gaussian
+  dcgs::DevBuf<uint32_t> rank_of;  // [n] Gaussian -> depth rank
+  dcgs::DevBuf<uint32_t> key_tmp, val_tmp;
+  dcgs::DevBuf<uint32_t> scan;      // [n + 1] pair offsets in depth order
+  dcgs::DevBuf<uint32_t> pair_off;  // [n] pair offset by Gaussian
+  // per pair
+  dcgs::DevBuf<uint64_t> pairs, pairs_tmp;
+  dcgs::DevBuf<float4> partial;  // [3 * P] per-pair gradient partials
+  // per tile
+  dcgs::DevBuf<int2> ranges;
+  dcgs::DevBuf<int> frontier;
+  // per pixel
+  dcgs::DevBuf<float> T_final;
+  dcgs::DevBuf<int> last;
+  // radix sort histograms
+  dcgs::DevBuf<uint32_t> hist;
+  dcgs::DevBuf<float> grad2d;  // [10][n] when the caller passes none
+};
+
+struct HostChunk {
+  uint64_t id = 0;
+  int64_t n = 0;
+  int64_t pages = 0;
+  float *params = nullptr;  // [pages][R][PG] inside the pinned arena
+  float *m = nullptr;
+  float *v = nullptr;
+  int32_t *step = nullptr;  // [pages][PG]
+  // residency
+  bool resident = false;
+  int64_t last_access = -1;
+  std::vector<int32_t> dev_pages;
+};
+
+struct dcgs_pool {
+  dcgs_ctx *ctx = nullptr;
+  int deg = 0, R = 0;
+  int64_t budget = 0;        // Gaussians
+  int64_t page_cap = 0;      // device pages
+  int64_t resident_g = 0;    // Gaussians resident
+  static constexpr int PG_LOG2 = 12;
+  static constexpr int PG = 1 << PG_LOG2;
+  // device pool, page-major: [page][R][PG] floats, step [page][PG]
+  float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr;
+  int32_t *d_step = nullptr;
+  std::vector<int32_t> free_pages;  // kept sorted descending (pop_back = lowest)
+  // host store
+  char *arena = nullptr;
+  size_t arena_bytes = 0;
+  std::vector<HostChunk> chunks;               // ascending id
+  std::unordered_map<uint64_t, int> index;     // id -> position in chunks
+  dcgs::DevBuf<uint64_t> d_ids;                // ascending ids on device
+  // compaction segment upload
+  dcgs::DevBuf<int4> d_seg;
+  int4 *h_seg = nullptr;
+  size_t h_seg_cap = 0;
+  hipEvent_t seg_done = nullptr;
+};
+
+namespace dcgs {
+
+// ---- launchers (one translation unit each) ----
+void launch_chunk_ids(const float *mean, int64_t n, int64_t stride, double s,
+                      uint64_t *out, int *flag, hipStream_t st);
+void launch_select(const dcgs_camera *cams, int n_views, const uint64_t *ids,
+                   int n_chunks, double s, uint16_t *mask_tmp,
+                   uint64_t *out_ids, uint16_t *out_mask, int32_t *out_count,
+                   hipStream_t st);
+void launch_compact(const float *pool, int R, const int4 *seg, int n_seg,
+                    const uint16_t *seg_mask, float *out, int64_t out_stride,
+                    int32_t *out_src, uint16_t *out_gmask, hipStream_t st);
+void launch_adam(float *params, float *m, float *v, int32_t *step, int R,
+                 const int32_t *src, const float *grad, int64_t n,
+                 int64_t grad_stride, const dcgs_adam_config &cfg,
+                 hipStream_t st);
+void launch_loss_l1(const float *rgb, const float *target, int64_t count,
+                    float *dl, double *stats, float *part, hipStream_t st);
+
+// exclusive scan of in (or of in[gather[i]] when gather != null), n
+// elements; out has n + 1 entries (out[n] = total).
+void scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out,
+              int64_t n, uint32_t *part, hipStream_t st);
+size_t scan_part_size(int64_t n);
+
+// stable LSD radix sort of (key, value) u32 pairs over key bits [0, bits).
+// Result ends in keys/vals; tmp buffers are n entries each.
+void sort_u32_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
+                    uint32_t *vtmp, int64_t n, int bits, DevBuf<uint32_t> &hist,
+                    hipStream_t st);
+// stable LSD radix sort of u64 words by bits [lo, lo + bits).
+void sort_u64_bits(uint64_t *a, uint64_t *tmp, int64_t n, int lo, int bits,
+                   DevBuf<uint32_t> &hist, hipStream_t st);
+
+void render_forward(dcgs_state *s, const float *params, int64_t n,
+                    int64_t stride, hipStream_t st, float *rgb, float *depth,
+                    float *T);
+void render_backward(dcgs_state *s, const float *params, int64_t n,
+                     int64_t stride, const float *dl_drgb,
+                     const float *dl_ddepth, float *grad, int64_t grad_stride,
+                     int accumulate, float *grad2d, hipStream_t st);
+void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values,
+                  int32_t *ranges, int32_t *counts, float *records,
+                  int32_t *box, int32_t *last, hipStream_t st);
+
+}  // namespace dcgs

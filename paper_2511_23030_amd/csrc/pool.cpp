@@ -1,0 +1,350 @@
+// Chunk store and device residency pool (Sec. III-E "Optimization" and "LRU
+// Eviction Strategy").
+//
+// Host store: every chunk's Gaussians (parameters, Adam moments, step
+// counts) in one pinned arena, page-major [page][row][4096], so a page moves
+// between host and device with one DMA copy.  Device pool: the same page
+// layout, sized for the budget; a resident chunk owns a list of pages,
+// allocated lowest-first so a chunk's pages are usually one contiguous run
+// (one copy per run).
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+#include <thread>
+
+#include "internal.h"
+
+namespace dcgs {
+
+namespace {
+
+constexpr int PG = dcgs_pool::PG;
+
+int64_t pages_of(int64_t n) { return (n + PG - 1) / PG; }
+
+// Allocate `need` pages, preferring the lowest free page numbers.
+std::vector<int32_t> alloc_pages(dcgs_pool *p, int64_t need) {
+  DCGS_CHECK((int64_t)p->free_pages.size() >= need, DCGS_E_BUDGET,
+             "device page pool exhausted");
+  std::vector<int32_t> out(need);
+  for (int64_t k = 0; k < need; ++k) {
+    out[k] = p->free_pages.back();
+    p->free_pages.pop_back();
+  }
+  return out;
+}
+
+void release_pages(dcgs_pool *p, const std::vector<int32_t> &pages) {
+  p->free_pages.insert(p->free_pages.end(), pages.begin(), pages.end());
+  std::sort(p->free_pages.begin(), p->free_pages.end(), std::greater<int32_t>());
+}
+
+// Copy a chunk's pages host <-> device, merging runs of consecutive device
+// pages into one copy per array.
+void move_chunk(dcgs_pool *p, HostChunk &c, bool to_device, hipStream_t st) {
+  const size_t pbytes = (size_t)p->R * PG * sizeof(float);
+  const size_t sbytes = (size_t)PG * sizeof(int32_t);
+  int64_t k = 0;
+  while (k < c.pages) {
+    int64_t run = 1;
+    while (k + run < c.pages && c.dev_pages[k + run] == c.dev_pages[k] + run) ++run;
+    const int64_t dp = c.dev_pages[k];
+    float *hp[3] = {c.params + (size_t)k * p->R * PG, c.m + (size_t)k * p->R * PG,
+                    c.v + (size_t)k * p->R * PG};
+    float *dv[3] = {p->d_params + (size_t)dp * p->R * PG, p->d_m + (size_t)dp * p->R * PG,
+                    p->d_v + (size_t)dp * p->R * PG};
+    for (int a = 0; a < 3; ++a) {
+      if (to_device)
+        DCGS_HIP(hipMemcpyAsync(dv[a], hp[a], run * pbytes, hipMemcpyHostToDevice, st));
+      else
+        DCGS_HIP(hipMemcpyAsync(hp[a], dv[a], run * pbytes, hipMemcpyDeviceToHost, st));
+    }
+    int32_t *hs = c.step + (size_t)k * PG;
+    int32_t *ds = p->d_step + (size_t)dp * PG;
+    if (to_device)
+      DCGS_HIP(hipMemcpyAsync(ds, hs, run * sbytes, hipMemcpyHostToDevice, st));
+    else
+      DCGS_HIP(hipMemcpyAsync(hs, ds, run * sbytes, hipMemcpyDeviceToHost, st));
+    k += run;
+  }
+}
+
+}  // namespace
+
+void pool_create(dcgs_ctx *ctx, int deg, int64_t budget, dcgs_pool **out) {
+  DCGS_CHECK(out && deg >= 0 && deg <= 3 && budget > 0, DCGS_E_INVALID, "pool_create: bad args");
+  auto *p = new dcgs_pool();
+  p->ctx = ctx;
+  p->deg = deg;
+  p->R = n_rows(deg);
+  p->budget = budget;
+  DCGS_HIP(hipEventCreateWithFlags(&p->seg_done, hipEventDisableTiming));
+  *out = p;
+}
+
+void pool_destroy(dcgs_pool *p) {
+  if (!p) return;
+  if (p->d_params) (void)hipFree(p->d_params);
+  if (p->d_m) (void)hipFree(p->d_m);
+  if (p->d_v) (void)hipFree(p->d_v);
+  if (p->d_step) (void)hipFree(p->d_step);
+  if (p->arena) (void)hipHostFree(p->arena);
+  if (p->h_seg) (void)hipHostFree(p->h_seg);
+  if (p->seg_done) (void)hipEventDestroy(p->seg_done);
+  delete p;
+}
+
+void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStream_t st) {
+  DCGS_CHECK(params && n > 0 && s > 0, DCGS_E_INVALID, "pool_ingest: bad args");
+  DCGS_CHECK(p->chunks.empty(), DCGS_E_INVALID, "pool_ingest: pool already holds a scene");
+  const int R = p->R;
+  // 1. chunk id of every Gaussian, computed on the device in batches
+  std::vector<uint64_t> ids(n);
+  const int64_t B = std::min<int64_t>(n, int64_t(1) << 22);
+  float *dmean = nullptr;
+  uint64_t *dids = nullptr;
+  int *dflag = nullptr;
+  DCGS_HIP(hipMalloc(&dmean, 3 * B * sizeof(float)));
+  DCGS_HIP(hipMalloc(&dids, B * sizeof(uint64_t)));
+  DCGS_HIP(hipMalloc(&dflag, sizeof(int)));
+  struct Free {
+    void *a, *b, *c;
+    ~Free() {
+      (void)hipFree(a);
+      (void)hipFree(b);
+      (void)hipFree(c);
+    }
+  } fr{dmean, dids, dflag};
+  DCGS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), st));
+  for (int64_t b0 = 0; b0 < n; b0 += B) {
+    const int64_t nb = std::min(B, n - b0);
+    DCGS_HIP(hipMemcpy2DAsync(dmean, nb * sizeof(float), params + b0, n * sizeof(float),
+                              nb * sizeof(float), 3, hipMemcpyHostToDevice, st));
+    launch_chunk_ids(dmean, nb, nb, s, dids, dflag, st);
+    DCGS_HIP(hipMemcpyAsync(ids.data() + b0, dids, nb * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, st));
+  }
+  int flag = 0;
+  DCGS_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  DCGS_HIP(hipStreamSynchronize(st));
+  DCGS_CHECK(flag == 0, DCGS_E_RANGE, "pool_ingest: chunk coordinate outside Eq. (6) range");
+  // 2. group by id, keeping input order inside a chunk
+  std::vector<uint32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) { return ids[a] < ids[b]; });
+  std::vector<std::pair<int64_t, int64_t>> runs;  // [begin, end) into idx
+  for (int64_t k = 0; k < n;) {
+    int64_t e = k;
+    while (e < n && ids[idx[e]] == ids[idx[k]]) ++e;
+    runs.push_back({k, e});
+    k = e;
+  }
+  // 3. pinned arena: params, m, v pages + step pages per chunk
+  const size_t fpage = (size_t)R * PG * sizeof(float), spage = (size_t)PG * sizeof(int32_t);
+  int64_t total_pages = 0;
+  for (auto &r : runs) total_pages += pages_of(r.second - r.first);
+  p->arena_bytes = (size_t)total_pages * (3 * fpage + spage);
+  DCGS_HIP(hipHostMalloc((void **)&p->arena, p->arena_bytes, hipHostMallocDefault));
+  std::memset(p->arena, 0, p->arena_bytes);
+  char *cur = p->arena;
+  p->chunks.resize(runs.size());
+  for (size_t c = 0; c < runs.size(); ++c) {
+    HostChunk &h = p->chunks[c];
+    h.id = ids[idx[runs[c].first]];
+    h.n = runs[c].second - runs[c].first;
+    h.pages = pages_of(h.n);
+    h.params = (float *)cur;
+    cur += h.pages * fpage;
+    h.m = (float *)cur;
+    cur += h.pages * fpage;
+    h.v = (float *)cur;
+    cur += h.pages * fpage;
+    h.step = (int32_t *)cur;
+    cur += h.pages * spage;
+    p->index[h.id] = (int)c;
+  }
+  // 4. scatter the input rows into the page-major store (threads over rows)
+  auto fill_rows = [&](int r0, int r1) {
+    for (int r = r0; r < r1; ++r) {
+      const float *src = params + (size_t)r * n;
+      for (size_t c = 0; c < runs.size(); ++c) {
+        HostChunk &h = p->chunks[c];
+        for (int64_t k = 0; k < h.n; ++k) {
+          const int64_t pg = k >> dcgs_pool::PG_LOG2, off = k & (PG - 1);
+          h.params[((size_t)pg * R + r) * PG + off] = src[idx[runs[c].first + k]];
+        }
+      }
+    }
+  };
+  const int nt = std::max(1, std::min<int>(R, (int)std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (int t = 0; t < nt; ++t) th.emplace_back(fill_rows, R * t / nt, R * (t + 1) / nt);
+  for (auto &t : th) t.join();
+  // 5. device pool: the budget in pages plus one partial page per chunk
+  p->page_cap = std::min<int64_t>(total_pages, pages_of(p->budget) + (int64_t)runs.size());
+  DCGS_HIP(hipMalloc(&p->d_params, p->page_cap * fpage));
+  DCGS_HIP(hipMalloc(&p->d_m, p->page_cap * fpage));
+  DCGS_HIP(hipMalloc(&p->d_v, p->page_cap * fpage));
+  DCGS_HIP(hipMalloc(&p->d_step, p->page_cap * spage));
+  p->free_pages.resize(p->page_cap);
+  for (int64_t k = 0; k < p->page_cap; ++k) p->free_pages[k] = (int32_t)(p->page_cap - 1 - k);
+  std::vector<uint64_t> h_ids(runs.size());
+  for (size_t c = 0; c < runs.size(); ++c) h_ids[c] = p->chunks[c].id;
+  uint64_t *d = p->d_ids.need(h_ids.size());
+  DCGS_HIP(hipMemcpyAsync(d, h_ids.data(), h_ids.size() * sizeof(uint64_t),
+                          hipMemcpyHostToDevice, st));
+  DCGS_HIP(hipStreamSynchronize(st));
+}
+
+void pool_require(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *loaded,
+                  int *evicted, hipStream_t st) {
+  DCGS_CHECK(n >= 0 && (ids || n == 0), DCGS_E_INVALID, "pool_require: bad args");
+  std::vector<int> need;
+  need.reserve(n);
+  for (int k = 0; k < n; ++k) {
+    auto it = p->index.find(ids[k]);
+    DCGS_CHECK(it != p->index.end(), DCGS_E_NOT_RESIDENT, "pool_require: unknown chunk id");
+    need.push_back(it->second);
+  }
+  std::sort(need.begin(), need.end());
+  need.erase(std::unique(need.begin(), need.end()), need.end());
+  std::vector<char> is_need(p->chunks.size(), 0);
+  int64_t total = p->resident_g;
+  std::vector<int> load;
+  for (int c : need) {
+    is_need[c] = 1;
+    if (!p->chunks[c].resident) {
+      load.push_back(c);
+      total += p->chunks[c].n;
+    }
+  }
+  // evictable: resident and not needed, oldest access first, ties by id
+  std::vector<int> evictable;
+  for (size_t c = 0; c < p->chunks.size(); ++c)
+    if (p->chunks[c].resident && !is_need[c]) evictable.push_back((int)c);
+  std::sort(evictable.begin(), evictable.end(), [&](int a, int b) {
+    const HostChunk &x = p->chunks[a], &y = p->chunks[b];
+    return x.last_access != y.last_access ? x.last_access < y.last_access : x.id < y.id;
+  });
+  std::vector<int> evict;
+  for (int c : evictable) {
+    if (total <= p->budget) break;
+    evict.push_back(c);
+    total -= p->chunks[c].n;
+  }
+  DCGS_CHECK(total <= p->budget, DCGS_E_BUDGET,
+             "pool_require: visible chunks exceed the residency budget");
+  // page capacity must also hold the loaded chunks
+  int64_t free_after = (int64_t)p->free_pages.size();
+  for (int c : evict) free_after += p->chunks[c].pages;
+  int64_t need_pages = 0;
+  for (int c : load) need_pages += p->chunks[c].pages;
+  DCGS_CHECK(need_pages <= free_after, DCGS_E_BUDGET, "pool_require: device pages exhausted");
+  for (int c : evict) {
+    HostChunk &h = p->chunks[c];
+    move_chunk(p, h, false, st);
+    release_pages(p, h.dev_pages);
+    h.dev_pages.clear();
+    h.resident = false;
+    p->resident_g -= h.n;
+  }
+  for (int c : load) {
+    HostChunk &h = p->chunks[c];
+    h.dev_pages = alloc_pages(p, h.pages);
+    move_chunk(p, h, true, st);
+    h.resident = true;
+    p->resident_g += h.n;
+  }
+  for (int c : need) p->chunks[c].last_access = now;
+  DCGS_HIP(hipStreamSynchronize(st));
+  if (loaded) *loaded = (int)load.size();
+  if (evicted) *evicted = (int)evict.size();
+}
+
+void pool_read_chunk(dcgs_pool *p, uint64_t id, float *params, float *m, float *v,
+                     int32_t *step) {
+  auto it = p->index.find(id);
+  DCGS_CHECK(it != p->index.end(), DCGS_E_NOT_RESIDENT, "pool_read_chunk: unknown chunk id");
+  HostChunk &h = p->chunks[it->second];
+  const int R = p->R;
+  const size_t fpage = (size_t)R * PG, n_f = h.pages * fpage;
+  std::vector<float> tp, tm, tv;
+  std::vector<int32_t> ts;
+  const float *sp = h.params, *sm = h.m, *sv = h.v;
+  const int32_t *ss = h.step;
+  if (h.resident) {
+    tp.resize(n_f);
+    tm.resize(n_f);
+    tv.resize(n_f);
+    ts.resize(h.pages * PG);
+    for (int64_t k = 0; k < h.pages; ++k) {
+      const size_t dp = h.dev_pages[k];
+      DCGS_HIP(hipMemcpy(tp.data() + k * fpage, p->d_params + dp * fpage, fpage * 4, hipMemcpyDeviceToHost));
+      DCGS_HIP(hipMemcpy(tm.data() + k * fpage, p->d_m + dp * fpage, fpage * 4, hipMemcpyDeviceToHost));
+      DCGS_HIP(hipMemcpy(tv.data() + k * fpage, p->d_v + dp * fpage, fpage * 4, hipMemcpyDeviceToHost));
+      DCGS_HIP(hipMemcpy(ts.data() + k * PG, p->d_step + dp * PG, PG * 4, hipMemcpyDeviceToHost));
+    }
+    sp = tp.data();
+    sm = tm.data();
+    sv = tv.data();
+    ss = ts.data();
+  }
+  for (int64_t k = 0; k < h.n; ++k) {
+    const int64_t pg = k >> dcgs_pool::PG_LOG2, off = k & (PG - 1);
+    for (int r = 0; r < R; ++r) {
+      const size_t src = ((size_t)pg * R + r) * PG + off;
+      if (params) params[(size_t)r * h.n + k] = sp[src];
+      if (m) m[(size_t)r * h.n + k] = sm[src];
+      if (v) v[(size_t)r * h.n + k] = sv[src];
+    }
+    if (step) step[k] = ss[(size_t)pg * PG + off];
+  }
+}
+
+void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                  float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
+                  int64_t capacity, int64_t *n_out, hipStream_t st) {
+  DCGS_CHECK(n_ids >= 0 && (ids || n_ids == 0) && n_out, DCGS_E_INVALID, "compact: bad args");
+  std::vector<std::pair<int, uint16_t>> act;
+  for (int k = 0; k < n_ids; ++k) {
+    auto it = p->index.find(ids[k]);
+    DCGS_CHECK(it != p->index.end(), DCGS_E_NOT_RESIDENT, "compact: unknown chunk id");
+    DCGS_CHECK(p->chunks[it->second].resident, DCGS_E_NOT_RESIDENT, "compact: chunk not resident");
+    act.push_back({it->second, masks ? masks[k] : (uint16_t)0xFFFF});
+  }
+  std::sort(act.begin(), act.end());  // chunks are stored in ascending id order
+  int64_t total = 0;
+  size_t nseg = 0;
+  for (auto &a : act) {
+    total += p->chunks[a.first].n;
+    nseg += p->chunks[a.first].pages;
+  }
+  *n_out = total;
+  DCGS_CHECK(total <= capacity, DCGS_E_CAPACITY, "compact: output capacity too small");
+  DCGS_CHECK(out && out_stride >= total, DCGS_E_INVALID, "compact: bad output");
+  if (nseg == 0) return;
+  if (nseg > p->h_seg_cap) {
+    if (p->h_seg) DCGS_HIP(hipHostFree(p->h_seg));
+    p->h_seg_cap = nseg * 2;
+    DCGS_HIP(hipHostMalloc((void **)&p->h_seg, p->h_seg_cap * sizeof(int4), hipHostMallocDefault));
+  } else {
+    DCGS_HIP(hipEventSynchronize(p->seg_done));  // previous upload finished
+  }
+  int64_t dst = 0;
+  size_t s = 0;
+  for (auto &a : act) {
+    HostChunk &h = p->chunks[a.first];
+    for (int64_t k = 0; k < h.pages; ++k) {
+      const int cnt = (int)std::min<int64_t>(PG, h.n - k * PG);
+      p->h_seg[s++] = make_int4(h.dev_pages[k], cnt, (int)dst, (int)a.second);
+      dst += cnt;
+    }
+  }
+  int4 *dseg = p->d_seg.need(nseg);
+  DCGS_HIP(hipMemcpyAsync(dseg, p->h_seg, nseg * sizeof(int4), hipMemcpyHostToDevice, st));
+  DCGS_HIP(hipEventRecord(p->seg_done, st));
+  launch_compact(p->d_params, p->R, dseg, (int)nseg, nullptr, out, out_stride, out_src,
+                 out_gmask, st);
+}
+
+}  // namespace dcgs

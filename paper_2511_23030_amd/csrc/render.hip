@@ -1,0 +1,848 @@
+// Differentiable Gaussian rasterization for gfx950: projection (float64
+// geometry), depth order, (tile, Gaussian) pair emission, stable tile sort,
+// per-tile ranges, front-to-back compositing, and its adjoint.
+//
+// The paper's optimisation step renders RGB and depth of the visible
+// Gaussians for a keyframe and differentiates the losses of Eqs. (2)-(4)
+// (Sec. III-C, Sec. III-E).  The rendering model is stated in dcgs.h.
+//
+// Layout decisions (gfx950):
+//  * Parameters are SoA rows, so every per-Gaussian kernel reads coalesced.
+//  * Geometry (covariance, EWA, conic, pixel box, depth) is computed in
+//    float64: every integer decision (culling, pixel box, tile rect, the
+//    float32 depth key) then agrees with a float64 reference except within
+//    ~1e-15 of a boundary.  The cost is hidden under the 236-byte parameter
+//    read per Gaussian.
+//  * A projection record is three float4 (48 B): u and v relative to the
+//    pixel box corner (small magnitudes keep float32 offsets exact to
+//    ~1e-7 px), conic, opacity, colour, depth and the packed pixel box.
+//  * The depth digits of the (tile, depth) keys are the same for all pairs of
+//    a Gaussian, so the LSD passes over them run on the N Gaussians before
+//    pair expansion; pairs are then emitted in depth order and stably sorted
+//    on the tile digits only.  The result is the order of a full LSD radix
+//    sort of the 64-bit (tile, float32 depth bits) keys, ties by index.
+//  * Rasterization: one workgroup per tile, one pixel per lane, records
+//    staged in LDS in batches, workgroups mapped to XCDs in contiguous bands
+//    of tiles so neighbouring tiles share an L2.
+//  * Backward: each tile walks its list back to front from the deepest
+//    composited position, recovers T_k = T_{k+1}/(1-alpha_k), reduces each
+//    Gaussian's ten screen-space gradient terms across the tile (wavefront
+//    butterfly, then a fixed-order sum over waves) and writes them to a
+//    per-pair slot.  A per-Gaussian pass sums its slots in a fixed order:
+//    gradients are bit-reproducible and use no float atomics.
+#include "internal.h"
+
+namespace dcgs {
+namespace {
+
+constexpr float kAlphaMin = 1.0f / 255.0f;
+constexpr float kAlphaMax = 0.99f;
+constexpr float kTMin = 1e-4f;
+constexpr double kDilation = 0.3;
+constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
+
+struct CamD {
+  double R[9], t[3], fx, fy, cx, cy, zn, zf, C[3], limx, limy;
+  int W, H;
+};
+
+CamD make_cam(const dcgs_camera &c) {
+  CamD d{};
+  for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+  d.fx = c.fx;
+  d.fy = c.fy;
+  d.cx = c.cx;
+  d.cy = c.cy;
+  d.zn = c.z_near;
+  d.zf = c.z_far;
+  d.W = c.width;
+  d.H = c.height;
+  for (int i = 0; i < 3; ++i)  // camera centre C = -R^T t
+    d.C[i] = -(c.R[i] * c.t[0] + c.R[3 + i] * c.t[1] + c.R[6 + i] * c.t[2]);
+  d.limx = ((1.3 * 0.5) * c.width) / c.fx;
+  d.limy = ((1.3 * 0.5) * c.height) / c.fy;
+  return d;
+}
+
+// Real orthonormal SH basis (no Condon-Shortley phase), k = l*l + l + m.
+__device__ inline void sh_eval(int deg, double x, double y, double z, double *Y) {
+  constexpr double kPi = 3.14159265358979323846;
+  Y[0] = 0.5 / sqrt(kPi);
+  if (deg < 1) return;
+  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  Y[1] = c1 * y;
+  Y[2] = c1 * z;
+  Y[3] = c1 * x;
+  if (deg < 2) return;
+  const double c2a = 0.5 * sqrt(15.0 / kPi), c20 = 0.25 * sqrt(5.0 / kPi),
+               c22 = 0.25 * sqrt(15.0 / kPi);
+  Y[4] = c2a * x * y;
+  Y[5] = c2a * y * z;
+  Y[6] = c20 * (3.0 * z * z - 1.0);
+  Y[7] = c2a * x * z;
+  Y[8] = c22 * (x * x - y * y);
+  if (deg < 3) return;
+  const double c33 = 0.25 * sqrt(35.0 / (2.0 * kPi)), c32 = 0.5 * sqrt(105.0 / kPi),
+               c31 = 0.25 * sqrt(21.0 / (2.0 * kPi)), c30 = 0.25 * sqrt(7.0 / kPi),
+               c32b = 0.25 * sqrt(105.0 / kPi);
+  Y[9] = c33 * y * (3.0 * x * x - y * y);
+  Y[10] = c32 * x * y * z;
+  Y[11] = c31 * y * (5.0 * z * z - 1.0);
+  Y[12] = c30 * z * (5.0 * z * z - 3.0);
+  Y[13] = c31 * x * (5.0 * z * z - 1.0);
+  Y[14] = c32b * z * (x * x - y * y);
+  Y[15] = c33 * x * (x * x - 3.0 * y * y);
+}
+
+// Gradient of each basis function with respect to (x, y, z), treated as
+// independent; the caller projects onto the sphere's tangent plane.
+__device__ inline void sh_grad(int deg, double x, double y, double z, double (*G)[3]) {
+  constexpr double kPi = 3.14159265358979323846;
+  G[0][0] = G[0][1] = G[0][2] = 0.0;
+  if (deg < 1) return;
+  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  G[1][0] = 0; G[1][1] = c1; G[1][2] = 0;
+  G[2][0] = 0; G[2][1] = 0; G[2][2] = c1;
+  G[3][0] = c1; G[3][1] = 0; G[3][2] = 0;
+  if (deg < 2) return;
+  const double c2a = 0.5 * sqrt(15.0 / kPi), c20 = 0.25 * sqrt(5.0 / kPi),
+               c22 = 0.25 * sqrt(15.0 / kPi);
+  G[4][0] = c2a * y; G[4][1] = c2a * x; G[4][2] = 0;
+  G[5][0] = 0; G[5][1] = c2a * z; G[5][2] = c2a * y;
+  G[6][0] = 0; G[6][1] = 0; G[6][2] = 6.0 * c20 * z;
+  G[7][0] = c2a * z; G[7][1] = 0; G[7][2] = c2a * x;
+  G[8][0] = 2.0 * c22 * x; G[8][1] = -2.0 * c22 * y; G[8][2] = 0;
+  if (deg < 3) return;
+  const double c33 = 0.25 * sqrt(35.0 / (2.0 * kPi)), c32 = 0.5 * sqrt(105.0 / kPi),
+               c31 = 0.25 * sqrt(21.0 / (2.0 * kPi)), c30 = 0.25 * sqrt(7.0 / kPi),
+               c32b = 0.25 * sqrt(105.0 / kPi);
+  G[9][0] = 6.0 * c33 * x * y; G[9][1] = c33 * (3.0 * x * x - 3.0 * y * y); G[9][2] = 0;
+  G[10][0] = c32 * y * z; G[10][1] = c32 * x * z; G[10][2] = c32 * x * y;
+  G[11][0] = 0; G[11][1] = c31 * (5.0 * z * z - 1.0); G[11][2] = 10.0 * c31 * y * z;
+  G[12][0] = 0; G[12][1] = 0; G[12][2] = c30 * (15.0 * z * z - 3.0);
+  G[13][0] = c31 * (5.0 * z * z - 1.0); G[13][1] = 0; G[13][2] = 10.0 * c31 * x * z;
+  G[14][0] = 2.0 * c32b * x * z; G[14][1] = -2.0 * c32b * y * z; G[14][2] = c32b * (x * x - y * y);
+  G[15][0] = c33 * (3.0 * x * x - 3.0 * y * y); G[15][1] = -6.0 * c33 * x * y; G[15][2] = 0;
+}
+
+// Forward geometry of one Gaussian, float64.
+struct Geo {
+  double mu[3], s[3], qn[4], qnorm, o, Rg[9], M[9], Sig[6];
+  double X, Y, Z, A0[3], A1[3], a, b, c, det;
+  double u, v;
+  bool culled;
+  int i0, i1, j0, j1;
+};
+
+__device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int64_t i,
+                                const CamD &cam, Geo &g) {
+  for (int k = 0; k < 3; ++k) g.mu[k] = (double)P[k * stride + i];
+  for (int k = 0; k < 3; ++k) g.s[k] = exp((double)P[(3 + k) * stride + i]);
+  double q[4];
+  for (int k = 0; k < 4; ++k) q[k] = (double)P[(6 + k) * stride + i];
+  g.o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
+  g.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int k = 0; k < 4; ++k) g.qn[k] = q[k] / g.qnorm;
+  const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+  double *R = g.Rg;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) g.M[3 * r + c] = R[3 * r + c] * g.s[c];
+  // Sigma = M M^T: xx, xy, xz, yy, yz, zz
+  const double *M = g.M;
+  g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  g.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  g.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  const double *Rc = cam.R;
+  g.X = Rc[0] * g.mu[0] + Rc[1] * g.mu[1] + Rc[2] * g.mu[2] + cam.t[0];
+  g.Y = Rc[3] * g.mu[0] + Rc[4] * g.mu[1] + Rc[5] * g.mu[2] + cam.t[1];
+  g.Z = Rc[6] * g.mu[0] + Rc[7] * g.mu[1] + Rc[8] * g.mu[2] + cam.t[2];
+  g.culled = !(g.Z > cam.zn);
+  if (!g.culled) {
+    const double rx = fabs(g.X / g.Z), ry = fabs(g.Y / g.Z);
+    g.culled = (rx > cam.limx) || (ry > cam.limy) || (g.o < 1.0 / 255.0);
+  }
+  if (g.culled) return;
+  const double iz = 1.0 / g.Z;
+  const double j00 = cam.fx * iz, j02 = -cam.fx * g.X * iz * iz;
+  const double j11 = cam.fy * iz, j12 = -cam.fy * g.Y * iz * iz;
+  for (int c = 0; c < 3; ++c) {
+    g.A0[c] = j00 * Rc[c] + j02 * Rc[6 + c];
+    g.A1[c] = j11 * Rc[3 + c] + j12 * Rc[6 + c];
+  }
+  const double *S = g.Sig;
+  auto quad = [&](const double *p, const double *q) {
+    const double sx = S[0] * q[0] + S[1] * q[1] + S[2] * q[2];
+    const double sy = S[1] * q[0] + S[3] * q[1] + S[4] * q[2];
+    const double sz = S[2] * q[0] + S[4] * q[1] + S[5] * q[2];
+    return p[0] * sx + p[1] * sy + p[2] * sz;
+  };
+  g.a = quad(g.A0, g.A0) + kDilation;
+  g.b = quad(g.A0, g.A1);
+  g.c = quad(g.A1, g.A1) + kDilation;
+  g.det = g.a * g.c - g.b * g.b;
+  if (!(g.det > 0.0)) {
+    g.culled = true;
+    return;
+  }
+  g.u = cam.fx * g.X / g.Z + cam.cx;
+  g.v = cam.fy * g.Y / g.Z + cam.cy;
+  const double r2 = 2.0 * log(255.0 * g.o);
+  const double ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
+  const double big = 1e9;
+  const double e0 = fmin(fmax(g.u - ex - 0.5, -big), big), e1 = fmin(fmax(g.u + ex - 0.5, -big), big);
+  const double f0 = fmin(fmax(g.v - ey - 0.5, -big), big), f1 = fmin(fmax(g.v + ey - 0.5, -big), big);
+  g.i0 = (int)fmax(ceil(e0), 0.0);
+  g.i1 = (int)fmin(floor(e1), (double)(cam.W - 1));
+  g.j0 = (int)fmax(ceil(f0), 0.0);
+  g.j1 = (int)fmin(floor(f1), (double)(cam.H - 1));
+  if (g.i0 > g.i1 || g.j0 > g.j1) g.culled = true;
+}
+
+// Colour before the clamp (raw) for each channel, float64.
+__device__ inline void color_raw(const float *__restrict__ P, int64_t stride, int64_t i,
+                                 int deg, const Geo &g, const CamD &cam, double *dir,
+                                 double &dnorm, double *Y, double raw[3]) {
+  double d0 = g.mu[0] - cam.C[0], d1 = g.mu[1] - cam.C[1], d2 = g.mu[2] - cam.C[2];
+  dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+  dir[0] = d0 / dnorm;
+  dir[1] = d1 / dnorm;
+  dir[2] = d2 / dnorm;
+  sh_eval(deg, dir[0], dir[1], dir[2], Y);
+  const int K = (deg + 1) * (deg + 1);
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc += (double)P[(11 + 3 * k + ch) * stride + i] * Y[k];
+    raw[ch] = acc + 0.5;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+    k_preprocess(const float *__restrict__ P, int64_t n, int64_t stride, int deg,
+                 CamD cam, int TW, int TH, float4 *__restrict__ rec,
+                 uint32_t *__restrict__ zkey, uint32_t *__restrict__ sortkey,
+                 uint32_t *__restrict__ order, uint32_t *__restrict__ count) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Geo g;
+  load_geo(P, stride, i, cam, g);
+  order[i] = (uint32_t)i;
+  const float zf = (float)g.Z;
+  zkey[i] = __float_as_uint(zf);
+  if (g.culled) {
+    count[i] = 0;
+    sortkey[i] = kCulledKey;
+    rec[i] = make_float4(0, 0, 0, 0);
+    rec[n + i] = make_float4(0, 0, 0, 0);
+    rec[2 * n + i] = make_float4(0, 0, 0, 0);
+    return;
+  }
+  double dir[3], dn, Y[16], raw[3];
+  color_raw(P, stride, i, deg, g, cam, dir, dn, Y, raw);
+  const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
+  count[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+  sortkey[i] = __float_as_uint(zf);
+  const double id = 1.0 / g.det;
+  rec[i] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(g.c * id),
+                       (float)(-g.b * id));
+  rec[n + i] = make_float4((float)(g.a * id), (float)g.o, (float)fmax(raw[0], 0.0),
+                           (float)fmax(raw[1], 0.0));
+  rec[2 * n + i] = make_float4((float)fmax(raw[2], 0.0), zf,
+                               __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
+                               __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
+}
+
+__global__ void k_rank(const uint32_t *__restrict__ order, int64_t n,
+                       uint32_t *__restrict__ rank_of) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) rank_of[order[j]] = (uint32_t)j;
+}
+
+__global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
+                       const uint32_t *__restrict__ scan, const float4 *__restrict__ recC,
+                       int64_t n, int TW, int TH, int tiles_x,
+                       uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t g = order[j];
+  const uint32_t c = count[g];
+  const uint32_t base = scan[j];
+  pair_off[g] = base;
+  if (c == 0) return;
+  const float4 C = recC[g];
+  const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+  const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
+  const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
+  uint32_t k = base;
+  for (int ty = ty0; ty <= ty1; ++ty)
+    for (int tx = tx0; tx <= tx1; ++tx)
+      pairs[k++] = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | g;
+}
+
+__global__ void k_ranges(const uint64_t *__restrict__ pairs, int64_t P, int n_tiles,
+                         int2 *__restrict__ ranges) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  auto lower = [&](uint32_t key) {
+    int64_t lo = 0, hi = P;
+    while (lo < hi) {
+      int64_t mid = (lo + hi) >> 1;
+      if ((uint32_t)(pairs[mid] >> 32) < key) lo = mid + 1;
+      else hi = mid;
+    }
+    return lo;
+  };
+  ranges[t] = make_int2((int)lower((uint32_t)t), (int)lower((uint32_t)t + 1));
+}
+
+// XCD-aware block -> tile map: the 8 XCDs receive workgroups round-robin,
+// so workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles.
+__device__ inline int tile_of_block(int n_tiles) {
+  const int per = (n_tiles + 7) >> 3;
+  const int b = blockIdx.x;
+  return (b & 7) * per + (b >> 3);
+}
+
+struct Sample {
+  bool ok;
+  float power, G, alpha, dx, dy;
+};
+
+// The one definition of a (pixel, Gaussian) sample, shared by forward and
+// backward so that both take identical threshold decisions.
+__device__ __forceinline__ Sample sample(int px, int py, const float4 &A, const float4 &B,
+                                         const float4 &C) {
+  Sample s;
+  const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+  const int i0 = bx & 0xFFFF, i1 = bx >> 16, j0 = by & 0xFFFF, j1 = by >> 16;
+  s.ok = px >= i0 && px <= i1 && py >= j0 && py <= j1;
+  s.dx = __fsub_rn((float)(px - i0) + 0.5f, A.x);
+  s.dy = __fsub_rn((float)(py - j0) + 0.5f, A.y);
+  const float qxx = __fmul_rn(A.z, __fmul_rn(s.dx, s.dx));
+  const float qyy = __fmul_rn(B.x, __fmul_rn(s.dy, s.dy));
+  const float qxy = __fmul_rn(A.w, __fmul_rn(s.dx, s.dy));
+  s.power = __fsub_rn(__fmul_rn(-0.5f, __fadd_rn(qxx, qyy)), qxy);
+  s.G = __expf(s.power);
+  const float oG = __fmul_rn(B.y, s.G);
+  s.alpha = fminf(kAlphaMax, oG);
+  s.ok = s.ok && !(s.power > 0.0f) && !(s.alpha < kAlphaMin);
+  return s;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+    k_raster_fwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
+                 const float4 *__restrict__ rec, int64_t n, int W, int H, int tiles_x,
+                 int n_tiles, float bg0, float bg1, float bg2, float *__restrict__ rgb,
+                 float *__restrict__ depth, float *__restrict__ Tout,
+                 float *__restrict__ Tstate, int *__restrict__ last_out) {
+  constexpr int BS = TW * TH;
+  __shared__ float4 sA[BS], sB[BS], sC[BS];
+  const int tile = tile_of_block(n_tiles);
+  if (tile >= n_tiles) return;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int px = tx * TW + (threadIdx.x % TW), py = ty * TH + (threadIdx.x / TW);
+  const bool inside = px < W && py < H;
+  const int2 rg = ranges[tile];
+  float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
+  int last = -1;
+  bool done = !inside;
+  for (int base = rg.x; base < rg.y; base += BS) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int p = base + threadIdx.x;
+    if (p < rg.y) {
+      const uint32_t g = (uint32_t)pairs[p];
+      sA[threadIdx.x] = rec[g];
+      sB[threadIdx.x] = rec[n + g];
+      sC[threadIdx.x] = rec[2 * n + g];
+    }
+    __syncthreads();
+    const int nb = min(BS, rg.y - base);
+    for (int k = 0; k < nb && !done; ++k) {
+      const float4 A = sA[k], B = sB[k], C = sC[k];
+      const Sample s = sample(px, py, A, B, C);
+      if (!s.ok) continue;
+      const float Tn = T * (1.0f - s.alpha);
+      if (Tn < kTMin) {
+        done = true;
+        break;
+      }
+      const float w = s.alpha * T;
+      c0 += B.z * w;
+      c1 += B.w * w;
+      c2 += C.x * w;
+      D += C.y * w;
+      T = Tn;
+      last = base + k;
+    }
+  }
+  if (!inside) return;
+  const int64_t pix = (int64_t)py * W + px, HW = (int64_t)W * H;
+  rgb[pix] = c0 + T * bg0;
+  rgb[HW + pix] = c1 + T * bg1;
+  rgb[2 * HW + pix] = c2 + T * bg2;
+  if (depth) depth[pix] = D;
+  if (Tout) Tout[pix] = T;
+  Tstate[pix] = T;
+  last_out[pix] = last;
+}
+
+// Sum of 16 values over a wavefront: a butterfly that halves the values each
+// lane carries at every step (17 shuffles instead of 96).  Afterwards lanes
+// 4c .. 4c+3 hold the wave total of value c.
+__device__ __forceinline__ float wave_reduce16(float (&v)[16]) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int h = 8, m = 32; h >= 1; h >>= 1, m >>= 1) {
+    const bool hi = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const float send = hi ? v[i] : v[i + h];
+      const float keep = hi ? v[i + h] : v[i];
+      v[i] = keep + __shfl_xor(send, m);
+    }
+  }
+  float r = v[0];
+  r += __shfl_xor(r, 2);
+  r += __shfl_xor(r, 1);
+  return r;
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+    k_raster_bwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
+                 const float4 *__restrict__ rec, int64_t n, int W, int H, int tiles_x,
+                 int n_tiles, float bg0, float bg1, float bg2,
+                 const float *__restrict__ Tstate, const int *__restrict__ last_in,
+                 const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
+                 const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
+                 float4 *__restrict__ partial, int *__restrict__ frontier) {
+  constexpr int NT = TW * TH;
+  constexpr int NW = NT / kWave;
+  constexpr int BS = NT < 128 ? NT : 128;  // records per batch
+  constexpr int NC = 10;
+  __shared__ float4 sA[BS], sB[BS], sC[BS];
+  __shared__ uint32_t sG[BS];
+  __shared__ float red[NW][BS][NC];
+  __shared__ int max_last;
+  const int tile = tile_of_block(n_tiles);
+  if (tile >= n_tiles) return;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int px = tx * TW + (threadIdx.x % TW), py = ty * TH + (threadIdx.x / TW);
+  const bool inside = px < W && py < H;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int2 rg = ranges[tile];
+  const int64_t pix = (int64_t)py * W + px, HW = (int64_t)W * H;
+  float T = 1.0f, g0 = 0, g1 = 0, g2 = 0, gd = 0;
+  int last = -1;
+  if (inside) {
+    T = Tstate[pix];
+    last = last_in[pix];
+    g0 = dl_drgb[pix];
+    g1 = dl_drgb[HW + pix];
+    g2 = dl_drgb[2 * HW + pix];
+    if (dl_ddepth) gd = dl_ddepth[pix];
+  }
+  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2, SD = 0.0f;
+  if (threadIdx.x == 0) max_last = -1;
+  __syncthreads();
+  if (last >= 0) atomicMax(&max_last, last);
+  __syncthreads();
+  const int top = max_last;
+  if (top < rg.x) {
+    if (threadIdx.x == 0) frontier[tile] = -1;
+    return;
+  }
+  for (int end = top + 1; end > rg.x; end -= BS) {
+    const int beg = max(rg.x, end - BS);
+    const int nb = end - beg;
+    if (threadIdx.x < nb) {  // slot k holds position end - 1 - k
+      const uint32_t g = (uint32_t)pairs[end - 1 - threadIdx.x];
+      sG[threadIdx.x] = g;
+      sA[threadIdx.x] = rec[g];
+      sB[threadIdx.x] = rec[n + g];
+      sC[threadIdx.x] = rec[2 * n + g];
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+      const int pos = end - 1 - k;
+      const float4 A = sA[k], B = sB[k], C = sC[k];
+      float v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = 0.0f;
+      bool contrib = false;
+      if (inside && pos <= last) {
+        const Sample s = sample(px, py, A, B, C);
+        if (s.ok) {
+          contrib = true;
+          const float om = 1.0f - s.alpha;
+          const float Tk = T / om;  // transmittance in front of this Gaussian
+          const float w = s.alpha * Tk;
+          v[6] = g0 * w;
+          v[7] = g1 * w;
+          v[8] = g2 * w;
+          v[9] = gd * w;
+          const float da = g0 * (B.z * Tk - S0 / om) + g1 * (B.w * Tk - S1 / om) +
+                           g2 * (C.x * Tk - S2 / om) + gd * (C.y * Tk - SD / om);
+          S0 += B.z * w;
+          S1 += B.w * w;
+          S2 += C.x * w;
+          SD += C.y * w;
+          T = Tk;
+          if (B.y * s.G <= kAlphaMax) {  // alpha not clamped
+            const float dp = s.alpha * da;
+            v[5] = s.G * da;
+            v[0] = dp * (A.z * s.dx + A.w * s.dy);
+            v[1] = dp * (A.w * s.dx + B.x * s.dy);
+            v[2] = -0.5f * s.dx * s.dx * dp;
+            v[3] = -s.dx * s.dy * dp;
+            v[4] = -0.5f * s.dy * s.dy * dp;
+          }
+        }
+      }
+      if (__ballot(contrib) != 0) {
+        const float r = wave_reduce16(v);
+        if ((lane & 3) == 0 && (lane >> 2) < NC) red[wv][k][lane >> 2] = r;
+      } else if (lane < NC) {
+        red[wv][k][lane] = 0.0f;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < nb) {
+      const int k = threadIdx.x;
+      float s[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        float a = 0.0f;
+        for (int w = 0; w < NW; ++w) a += red[w][k][c];
+        s[c] = a;
+      }
+      const uint32_t g = sG[k];
+      const float4 C = sC[k];
+      const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+      const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW, ty0 = (by & 0xFFFF) / TH;
+      const uint32_t slot = pair_off[g] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+      partial[3 * (int64_t)slot] = make_float4(s[0], s[1], s[2], s[3]);
+      partial[3 * (int64_t)slot + 1] = make_float4(s[4], s[5], s[6], s[7]);
+      partial[3 * (int64_t)slot + 2] = make_float4(s[8], s[9], 0.0f, 0.0f);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) frontier[tile] = (int)rank_of[(uint32_t)pairs[top]];
+}
+
+__global__ void __launch_bounds__(256)
+    k_preprocess_bwd(const float *__restrict__ P, int64_t n, int64_t stride, int deg,
+                     CamD cam, int TW, int TH, int tiles_x,
+                     const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
+                     const uint32_t *__restrict__ rank_of, const int *__restrict__ frontier,
+                     const float4 *__restrict__ partial, float *__restrict__ grad,
+                     int64_t gstride, int accumulate, float *__restrict__ grad2d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int R = 11 + 3 * (deg + 1) * (deg + 1);
+  Geo g;
+  load_geo(P, stride, i, cam, g);
+  if (g.culled || count[i] == 0) {
+    if (grad2d)
+      for (int c = 0; c < 10; ++c) grad2d[c * n + i] = 0.0f;
+    if (!accumulate)
+      for (int r = 0; r < R; ++r) grad[r * gstride + i] = 0.0f;
+    return;
+  }
+  // Sum this Gaussian's per-tile partials in emission (row-major) order.
+  const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
+  const int wc = tx1 - tx0 + 1;
+  const uint32_t base = pair_off[i], cnt = count[i];
+  const int rank = (int)rank_of[i];
+  float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (uint32_t r = 0; r < cnt; ++r) {
+    const int t = (ty0 + (int)r / wc) * tiles_x + tx0 + (int)r % wc;
+    if (frontier[t] < rank) continue;  // the tile never reached this Gaussian
+    const float4 p0 = partial[3 * (int64_t)(base + r)];
+    const float4 p1 = partial[3 * (int64_t)(base + r) + 1];
+    const float4 p2 = partial[3 * (int64_t)(base + r) + 2];
+    s[0] += p0.x; s[1] += p0.y; s[2] += p0.z; s[3] += p0.w;
+    s[4] += p1.x; s[5] += p1.y; s[6] += p1.z; s[7] += p1.w;
+    s[8] += p2.x; s[9] += p2.y;
+  }
+  (void)ty1;
+  if (grad2d)
+    for (int c = 0; c < 10; ++c) grad2d[c * n + i] = s[c];
+
+  const double gu = s[0], gv = s[1], gQ00 = s[2], gQ01 = s[3], gQ11 = s[4];
+  const double go = s[5], gz_depth = s[9];
+  // conic Q = Sigma2^-1 -> Sigma2 entries a, b, c
+  const double det = g.det, a = g.a, b = g.b, c = g.c;
+  const double gdet = -(gQ00 * c - gQ01 * b + gQ11 * a) / (det * det);
+  const double ga = gQ11 / det + gdet * c;
+  const double gb = -gQ01 / det - 2.0 * b * gdet;
+  const double gc = gQ00 / det + gdet * a;
+  // Sigma2 = A Sigma A^T: G_Sigma = A^T G2 A, G_A = 2 G2 A Sigma
+  const double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
+  const double A[2][3] = {{g.A0[0], g.A0[1], g.A0[2]}, {g.A1[0], g.A1[1], g.A1[2]}};
+  const double *Sg = g.Sig;
+  const double Sig[3][3] = {{Sg[0], Sg[1], Sg[2]}, {Sg[1], Sg[3], Sg[4]}, {Sg[2], Sg[4], Sg[5]}};
+  double GA[2][3], GS[3][3];
+  {
+    double G2A[2][3];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k) G2A[r][k] = G2[r][0] * A[0][k] + G2[r][1] * A[1][k];
+    for (int r = 0; r < 2; ++r)
+      for (int k = 0; k < 3; ++k)
+        GA[r][k] = 2.0 * (G2A[r][0] * Sig[0][k] + G2A[r][1] * Sig[1][k] + G2A[r][2] * Sig[2][k]);
+    for (int r = 0; r < 3; ++r)
+      for (int k = 0; k < 3; ++k) GS[r][k] = A[0][r] * G2A[0][k] + A[1][r] * G2A[1][k];
+  }
+  // A = J Rc -> G_J = G_A Rc^T
+  const double *Rc = cam.R;
+  double GJ[2][3];
+  for (int r = 0; r < 2; ++r)
+    for (int k = 0; k < 3; ++k)
+      GJ[r][k] = GA[r][0] * Rc[3 * k] + GA[r][1] * Rc[3 * k + 1] + GA[r][2] * Rc[3 * k + 2];
+  const double iz = 1.0 / g.Z, iz2 = iz * iz, iz3 = iz2 * iz;
+  const double fx = cam.fx, fy = cam.fy, X = g.X, Y = g.Y;
+  double gX = GJ[0][2] * (-fx * iz2) + gu * fx * iz;
+  double gY = GJ[1][2] * (-fy * iz2) + gv * fy * iz;
+  double gZ = GJ[0][0] * (-fx * iz2) + GJ[0][2] * (2.0 * fx * X * iz3) +
+              GJ[1][1] * (-fy * iz2) + GJ[1][2] * (2.0 * fy * Y * iz3) +
+              gu * (-fx * X * iz2) + gv * (-fy * Y * iz2) + gz_depth;
+  double gmu[3];
+  for (int k = 0; k < 3; ++k) gmu[k] = Rc[k] * gX + Rc[3 + k] * gY + Rc[6 + k] * gZ;
+  // Sigma = M M^T, M = Rg diag(s)
+  double GM[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k)
+      GM[r][k] = 2.0 * (GS[r][0] * g.M[k] + GS[r][1] * g.M[3 + k] + GS[r][2] * g.M[6 + k]);
+  double GR[3][3], gls[3];
+  for (int k = 0; k < 3; ++k) {
+    double gsk = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      GR[r][k] = GM[r][k] * g.s[k];
+      gsk += GM[r][k] * g.Rg[3 * r + k];
+    }
+    gls[k] = gsk * g.s[k];
+  }
+  const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+  double gqn[4];
+  gqn[0] = 2.0 * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+  gqn[1] = 2.0 * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] +
+                  z * GR[2][0] + w * GR[2][1] - 2.0 * x * GR[2][2]);
+  gqn[2] = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] -
+                  w * GR[2][0] + z * GR[2][1] - 2.0 * y * GR[2][2]);
+  gqn[3] = 2.0 * (-2.0 * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * z * GR[1][1] +
+                  y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
+  const double dq = g.qn[0] * gqn[0] + g.qn[1] * gqn[1] + g.qn[2] * gqn[2] + g.qn[3] * gqn[3];
+  double gq[4];
+  for (int k = 0; k < 4; ++k) gq[k] = (gqn[k] - g.qn[k] * dq) / g.qnorm;
+  const double glogit = go * g.o * (1.0 - g.o);
+  // colour
+  double dir[3], dn, Yb[16], raw[3];
+  color_raw(P, stride, i, deg, g, cam, dir, dn, Yb, raw);
+  double graw[3];
+  for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > 0.0 ? (double)s[6 + ch] : 0.0;
+  const int K = (deg + 1) * (deg + 1);
+  if (deg > 0) {
+    double GY[16][3];
+    sh_grad(deg, dir[0], dir[1], dir[2], GY);
+    double gd[3] = {0, 0, 0};
+    for (int k = 1; k < K; ++k) {
+      double f = 0.0;
+      for (int ch = 0; ch < 3; ++ch) f += (double)P[(11 + 3 * k + ch) * stride + i] * graw[ch];
+      gd[0] += GY[k][0] * f;
+      gd[1] += GY[k][1] * f;
+      gd[2] += GY[k][2] * f;
+    }
+    const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+    for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) / dn;
+  }
+  double out[11];
+  out[0] = gmu[0]; out[1] = gmu[1]; out[2] = gmu[2];
+  out[3] = gls[0]; out[4] = gls[1]; out[5] = gls[2];
+  out[6] = gq[0]; out[7] = gq[1]; out[8] = gq[2]; out[9] = gq[3];
+  out[10] = glogit;
+  if (accumulate) {
+    for (int r = 0; r < 11; ++r) grad[r * gstride + i] += (float)out[r];
+    for (int k = 0; k < K; ++k)
+      for (int ch = 0; ch < 3; ++ch)
+        grad[(11 + 3 * k + ch) * gstride + i] += (float)(Yb[k] * graw[ch]);
+  } else {
+    for (int r = 0; r < 11; ++r) grad[r * gstride + i] = (float)out[r];
+    for (int k = 0; k < K; ++k)
+      for (int ch = 0; ch < 3; ++ch)
+        grad[(11 + 3 * k + ch) * gstride + i] = (float)(Yb[k] * graw[ch]);
+  }
+}
+
+// ---- export helpers (tests) ----
+__global__ void k_export_keys(const uint64_t *__restrict__ pairs, int64_t P,
+                              const uint32_t *__restrict__ zkey, uint64_t *__restrict__ keys,
+                              int32_t *__restrict__ values) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const uint64_t p = pairs[k];
+  const uint32_t g = (uint32_t)p;
+  if (keys) keys[k] = (p & 0xFFFFFFFF00000000ull) | zkey[g];
+  if (values) values[k] = (int32_t)g;
+}
+
+__global__ void k_export_rec(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
+                             int64_t n, float *__restrict__ out, int32_t *__restrict__ box) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float4 A = rec[i], B = rec[n + i], C = rec[2 * n + i];
+  const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+  const int i0 = bx & 0xFFFF, j0 = by & 0xFFFF;
+  if (out) {
+    const bool cul = count[i] == 0;
+    out[0 * n + i] = cul ? 0.0f : A.x + (float)i0;
+    out[1 * n + i] = cul ? 0.0f : A.y + (float)j0;
+    out[2 * n + i] = A.z;
+    out[3 * n + i] = A.w;
+    out[4 * n + i] = B.x;
+    out[5 * n + i] = B.y;
+    out[6 * n + i] = B.z;
+    out[7 * n + i] = B.w;
+    out[8 * n + i] = C.x;
+    out[9 * n + i] = C.y;
+  }
+  if (box) {
+    box[0 * n + i] = i0;
+    box[1 * n + i] = (int)(bx >> 16);
+    box[2 * n + i] = j0;
+    box[3 * n + i] = (int)(by >> 16);
+  }
+}
+
+__global__ void k_copy_u32_as_i32(const uint32_t *__restrict__ a, int64_t n, int32_t *__restrict__ b) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (int32_t)a[i];
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <int TW, int TH>
+void launch_fwd_t(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *T) {
+  const int nt = s->tiles_x * s->tiles_y;
+  const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, s->pairs.p,
+                     s->ranges.p, s->rec.p, s->n, s->W, s->H, s->tiles_x, nt, s->bg[0],
+                     s->bg[1], s->bg[2], rgb, depth, T, s->T_final.p, s->last.p);
+  DCGS_LAUNCH_CHECK();
+}
+
+template <int TW, int TH>
+void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const float *dl_ddepth) {
+  const int nt = s->tiles_x * s->tiles_y;
+  const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, s->pairs.p,
+                     s->ranges.p, s->rec.p, s->n, s->W, s->H, s->tiles_x, nt, s->bg[0],
+                     s->bg[1], s->bg[2], s->T_final.p, s->last.p, dl_drgb, dl_ddepth,
+                     s->pair_off.p, s->rank_of.p, s->partial.p, s->frontier.p);
+  DCGS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
+                    hipStream_t st, float *rgb, float *depth, float *T) {
+  const CamD cam = make_cam(s->cam);
+  const int nt = s->tiles_x * s->tiles_y;
+  const int64_t HW = (int64_t)s->W * s->H;
+  s->n = n;
+  float4 *rec = s->rec.need(3 * (size_t)n + 1);
+  uint32_t *zkey = s->zkey.need(n + 1), *cnt = s->count.need(n + 1);
+  uint32_t *order = s->order.need(n + 1), *sortkey = s->key_tmp.need(2 * (size_t)n + 2);
+  uint32_t *vtmp = s->val_tmp.need(n + 1);
+  s->rank_of.need(n + 1);
+  s->pair_off.need(n + 1);
+  uint32_t *scan = s->scan.need(n + 2);
+  s->ranges.need(nt + 1);
+  s->frontier.need(nt + 1);
+  s->T_final.need(HW + 1);
+  s->last.need(HW + 1);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n, 256)), dim3(256), 0, st, params, n,
+                       stride, s->sh_degree, cam, s->TW, s->TH, rec, zkey, sortkey, order, cnt);
+    DCGS_LAUNCH_CHECK();
+    // depth order of the Gaussians: stable sort of the float32 depth bits
+    sort_u32_pairs(sortkey, order, sortkey + n + 1, vtmp, n, 32, s->hist, st);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(n, 256)), dim3(256), 0, st, order, n,
+                       s->rank_of.p);
+    DCGS_LAUNCH_CHECK();
+  }
+  uint32_t *part = s->ctx->scan_part.need(scan_part_size(n) + 2);
+  scan_u32(cnt, order, scan, n, part, st);
+  uint32_t total = 0;
+  DCGS_HIP(hipMemcpyAsync(&total, scan + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  DCGS_HIP(hipStreamSynchronize(st));
+  s->n_pairs = total;
+  uint64_t *pairs = s->pairs.need((size_t)total + 1);
+  uint64_t *ptmp = s->pairs_tmp.need((size_t)total + 1);
+  s->partial.need(3 * (size_t)total + 3);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(n, 256)), dim3(256), 0, st, order, cnt, scan,
+                       rec + 2 * n, n, s->TW, s->TH, s->tiles_x, pairs, s->pair_off.p);
+    DCGS_LAUNCH_CHECK();
+  }
+  int tile_bits = 0;
+  while ((1 << tile_bits) < nt) ++tile_bits;
+  if (total > 0) sort_u64_bits(pairs, ptmp, total, 32, tile_bits, s->hist, st);
+  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(nt, 256)), dim3(256), 0, st, pairs,
+                     (int64_t)total, nt, s->ranges.p);
+  DCGS_LAUNCH_CHECK();
+  if (s->TW == 16 && s->TH == 16) launch_fwd_t<16, 16>(s, st, rgb, depth, T);
+  else if (s->TW == 8 && s->TH == 8) launch_fwd_t<8, 8>(s, st, rgb, depth, T);
+  else launch_fwd_t<32, 16>(s, st, rgb, depth, T);
+}
+
+void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
+                     const float *dl_drgb, const float *dl_ddepth, float *grad,
+                     int64_t grad_stride, int accumulate, float *grad2d, hipStream_t st) {
+  const CamD cam = make_cam(s->cam);
+  if (s->TW == 16 && s->TH == 16) launch_bwd_t<16, 16>(s, st, dl_drgb, dl_ddepth);
+  else if (s->TW == 8 && s->TH == 8) launch_bwd_t<8, 8>(s, st, dl_drgb, dl_ddepth);
+  else launch_bwd_t<32, 16>(s, st, dl_drgb, dl_ddepth);
+  if (n > 0) {
+    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, params,
+                       n, stride, s->sh_degree, cam, s->TW, s->TH, s->tiles_x, s->count.p,
+                       s->pair_off.p, s->rank_of.p, s->frontier.p, s->partial.p, grad,
+                       grad_stride, accumulate, grad2d);
+    DCGS_LAUNCH_CHECK();
+  }
+}
+
+void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values, int32_t *ranges,
+                  int32_t *counts, float *records, int32_t *box, int32_t *last,
+                  hipStream_t st) {
+  const int64_t P = s->n_pairs, n = s->n;
+  const int nt = s->tiles_x * s->tiles_y;
+  if ((keys || values) && P > 0) {
+    hipLaunchKernelGGL(k_export_keys, dim3(blocks_for(P, 256)), dim3(256), 0, st, s->pairs.p,
+                       P, s->zkey.p, keys, values);
+    DCGS_LAUNCH_CHECK();
+  }
+  if (ranges && nt > 0)
+    DCGS_HIP(hipMemcpyAsync(ranges, s->ranges.p, nt * sizeof(int2), hipMemcpyDeviceToDevice, st));
+  if (counts && n > 0) {
+    hipLaunchKernelGGL(k_copy_u32_as_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st,
+                       s->count.p, n, counts);
+    DCGS_LAUNCH_CHECK();
+  }
+  if ((records || box) && n > 0) {
+    hipLaunchKernelGGL(k_export_rec, dim3(blocks_for(n, 256)), dim3(256), 0, st, s->rec.p,
+                       s->count.p, n, records, box);
+    DCGS_LAUNCH_CHECK();
+  }
+  if (last)
+    DCGS_HIP(hipMemcpyAsync(last, s->last.p, (size_t)s->W * s->H * sizeof(int),
+                            hipMemcpyDeviceToDevice, st));
+}
+
+}  // namespace dcgs

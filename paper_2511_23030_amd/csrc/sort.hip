@@ -1,0 +1,282 @@
+// Device-wide exclusive scan and stable LSD radix sort for gfx950.
+//
+// The radix sort is the binning sort of the rasterizer: (tile, depth) keys
+// are ordered by stable passes over 8-bit (or narrower) digits, least
+// significant first.  Each pass = per-workgroup digit histograms (LDS
+// atomics), one exclusive scan of the digit-major histogram table, and a
+// scatter in which every key's rank among equal digits of its workgroup comes
+// from wavefront ballots (a match mask per digit) plus per-wave counts in LDS,
+// so equal keys keep their input order.
+#include "internal.h"
+
+namespace dcgs {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    uint32_t o = __shfl_up(v, d);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan of the block's thread values; returns the block total.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *excl) {
+  __shared__ uint32_t wsum[kScanThreads / kWave];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  uint32_t inc = wave_inclusive_scan(v);
+  if (lane == kWave - 1) wsum[w] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kScanThreads / kWave; ++k) {
+    uint32_t s = wsum[k];
+    if (k < w) off += s;
+    tot += s;
+  }
+  *excl = off + inc - v;
+  __syncthreads();
+  return tot;
+}
+
+__device__ inline uint32_t load_item(const uint32_t *in, const uint32_t *gather,
+                                     int64_t i, int64_t n) {
+  if (i >= n) return 0;
+  return gather ? in[gather[i]] : in[i];
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+    k_scan_reduce(const uint32_t *__restrict__ in,
+                  const uint32_t *__restrict__ gather, int64_t n,
+                  uint32_t *__restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    s += load_item(in, gather, base + k * kScanThreads + threadIdx.x, n);
+  uint32_t excl;
+  uint32_t tot = block_exclusive_scan(s, &excl);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the per-block totals, one workgroup.
+__global__ void __launch_bounds__(kScanThreads)
+    k_scan_top(uint32_t *__restrict__ part, int64_t nb) {
+  __shared__ uint32_t carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t r = 0; r < nb; r += kScanThreads) {
+    int64_t i = r + threadIdx.x;
+    uint32_t v = i < nb ? part[i] : 0;
+    uint32_t excl;
+    uint32_t tot = block_exclusive_scan(v, &excl);
+    uint32_t c = carry_s;
+    if (i < nb) part[i] = c + excl;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = c + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[nb] = carry_s;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+    k_scan_down(const uint32_t *__restrict__ in,
+                const uint32_t *__restrict__ gather, int64_t n,
+                const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+  __shared__ uint32_t tile[kScanTile + kScanTile / 32];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  auto pad = [](int i) { return i + (i >> 5); };
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int li = k * kScanThreads + threadIdx.x;
+    tile[pad(li)] = load_item(in, gather, base + li, n);
+  }
+  __syncthreads();
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = tile[pad(threadIdx.x * kScanItems + k)];
+    s += v[k];
+  }
+  uint32_t excl;
+  block_exclusive_scan(s, &excl);
+  uint32_t run = part[blockIdx.x] + excl;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    tile[pad(threadIdx.x * kScanItems + k)] = run;
+    run += v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    int li = k * kScanThreads + threadIdx.x;
+    if (base + li < n) out[base + li] = tile[pad(li)];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+}
+
+// ---------------------------------------------------------------- radix --
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;  // 4096 keys per block
+constexpr int kSortWaves = kSortThreads / kWave;
+
+template <typename K>
+__device__ inline uint32_t digit_of(K key, int shift, uint32_t mask) {
+  return (uint32_t)(key >> shift) & mask;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortThreads)
+    k_rs_hist(const K *__restrict__ keys, int64_t n, int shift, int width,
+              uint32_t *__restrict__ hist, int64_t nb) {
+  __shared__ uint32_t h[256];
+  const uint32_t bins = 1u << width, mask = bins - 1;
+  for (int t = threadIdx.x; t < 256; t += kSortThreads) h[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+  for (int r = 0; r < kSortRounds; ++r) {
+    int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < bins; d += kSortThreads)
+    hist[(int64_t)d * nb + blockIdx.x] = h[d];
+}
+
+template <typename K, bool kVals>
+__global__ void __launch_bounds__(kSortThreads)
+    k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+                 K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
+                 int shift, int width, const uint32_t *__restrict__ offs,
+                 int64_t nb) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[kSortWaves][256];
+  const uint32_t bins = 1u << width, mask = bins - 1;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  for (uint32_t d = threadIdx.x; d < bins; d += kSortThreads)
+    run[d] = offs[(int64_t)d * nb + blockIdx.x];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    if (base + (int64_t)r * kSortThreads >= n) break;  // uniform across block
+    for (int t = threadIdx.x; t < kSortWaves * 256; t += kSortThreads)
+      (&wcnt[0][0])[t] = 0;
+    __syncthreads();
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    const bool valid = i < n;
+    K key = valid ? kin[i] : K(0);
+    uint32_t val = (kVals && valid) ? vin[i] : 0u;
+    const uint32_t d = digit_of(key, shift, mask);
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < width; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+      kout[pos] = key;
+      if (kVals) vout[pos] = val;
+    }
+    __syncthreads();
+    for (uint32_t dd = threadIdx.x; dd < bins; dd += kSortThreads) {
+      uint32_t s = 0;
+      for (int k = 0; k < kSortWaves; ++k) s += wcnt[k][dd];
+      run[dd] += s;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename K, bool kVals>
+void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
+                int64_t n, int shift, int width, DevBuf<uint32_t> &hist,
+                hipStream_t st) {
+  const int64_t nb = (n + kSortTile - 1) / kSortTile;
+  const int64_t bins = int64_t(1) << width;
+  const int64_t tab = bins * nb;
+  // histogram table, then its scan (part area after table + 1)
+  uint32_t *h = hist.need(2 * (tab + 1) + scan_part_size(tab) + 16);
+  uint32_t *scanned = h + tab + 1;
+  uint32_t *part = scanned + tab + 1;
+  hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(kSortThreads), 0,
+                     st, kin, n, shift, width, h, nb);
+  DCGS_LAUNCH_CHECK();
+  scan_u32(h, nullptr, scanned, tab, part, st);
+  hipLaunchKernelGGL((k_rs_scatter<K, kVals>), dim3((unsigned)nb),
+                     dim3(kSortThreads), 0, st, kin, vin, kout, vout, n, shift,
+                     width, scanned, nb);
+  DCGS_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t scan_part_size(int64_t n) {
+  return (size_t)((n + kScanTile - 1) / kScanTile) + 2;
+}
+
+void scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out,
+              int64_t n, uint32_t *part, hipStream_t st) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  if (n == 0) {
+    DCGS_HIP(hipMemsetAsync(out, 0, sizeof(uint32_t), st));
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                     st, in, gather, n, part);
+  DCGS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, part, nb);
+  DCGS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0,
+                     st, in, gather, n, part, out);
+  DCGS_LAUNCH_CHECK();
+}
+
+void sort_u32_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
+                    uint32_t *vtmp, int64_t n, int bits, DevBuf<uint32_t> &hist,
+                    hipStream_t st) {
+  int passes, width;
+  digit_plan(bits, &passes, &width);
+  uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
+  for (int p = 0; p < passes; ++p) {
+    int shift = p * width;
+    int w = (shift + width > bits) ? bits - shift : width;
+    radix_pass<uint32_t, true>(ka, va, kb, vb, n, shift, w, hist, st);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (ka != keys) {
+    DCGS_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    DCGS_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  }
+}
+
+void sort_u64_bits(uint64_t *a, uint64_t *tmp, int64_t n, int lo, int bits,
+                   DevBuf<uint32_t> &hist, hipStream_t st) {
+  int passes, width;
+  digit_plan(bits, &passes, &width);
+  uint64_t *x = a, *y = tmp;
+  for (int p = 0; p < passes; ++p) {
+    int shift = p * width;
+    int w = (shift + width > bits) ? bits - shift : width;
+    radix_pass<uint64_t, false>(x, nullptr, y, nullptr, n, lo + shift, w, hist, st);
+    std::swap(x, y);
+  }
+  if (x != a)
+    DCGS_HIP(hipMemcpyAsync(a, x, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+}
+
+}  // namespace dcgs

@@ -1,0 +1,345 @@
+"""ctypes binding of libdcgs (``include/dcgs.h``): argument marshalling only.
+
+Every computation happens in the HIP library; this module converts torch
+tensors to device pointers, cameras to ``dcgs_camera`` structs, and status
+codes to exceptions.  Importing it does not load the library; the first use
+does, and raises ``LibraryMissing`` if ``libdcgs.so`` was not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdcgs.so")
+
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_CAPACITY", 3: "E_BUDGET", 4: "E_NOT_RESIDENT",
+          5: "E_HIP", 6: "E_RANGE"}
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+class DcgsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Camera(C.Structure):
+    _fields_ = [("R", C.c_double * 9), ("t", C.c_double * 3), ("fx", C.c_double),
+                ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32), ("z_near", C.c_double),
+                ("z_far", C.c_double)]
+
+    @staticmethod
+    def of(cam: dict) -> "Camera":
+        c = Camera()
+        c.R[:] = [float(x) for x in np.asarray(cam["R"], np.float64).reshape(9)]
+        c.t[:] = [float(x) for x in np.asarray(cam["t"], np.float64).reshape(3)]
+        c.fx, c.fy, c.cx, c.cy = cam["fx"], cam["fy"], cam["cx"], cam["cy"]
+        c.width, c.height = cam["width"], cam["height"]
+        c.z_near, c.z_far = cam["z_near"], cam["z_far"]
+        return c
+
+
+class AdamConfig(C.Structure):
+    _fields_ = [("lr", C.c_float * 6), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+    @staticmethod
+    def of(lr, beta1=0.9, beta2=0.999, eps=1e-15) -> "AdamConfig":
+        a = AdamConfig()
+        a.lr[:] = [float(x) for x in lr]
+        a.beta1, a.beta2, a.eps = beta1, beta2, eps
+        return a
+
+
+P = C.c_void_p
+I64 = C.c_int64
+I32 = C.c_int32
+INT = C.c_int
+DBL = C.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "dcgs_version": (C.c_char_p, []),
+    "dcgs_create": (INT, [C.POINTER(P), INT]),
+    "dcgs_destroy": (None, [P]),
+    "dcgs_last_error": (C.c_char_p, [P]),
+    "dcgs_chunk_ids": (INT, [P, P, I64, I64, DBL, P, P]),
+    "dcgs_select_chunks": (INT, [P, P, INT, P, INT, DBL, P, P, P, P]),
+    "dcgs_pool_create": (INT, [P, INT, I64, C.POINTER(P)]),
+    "dcgs_pool_destroy": (None, [P]),
+    "dcgs_pool_ingest": (INT, [P, P, I64, DBL, P]),
+    "dcgs_pool_chunks": (INT, [P, P, P, INT, C.POINTER(INT)]),
+    "dcgs_pool_device_ids": (P, [P, C.POINTER(INT)]),
+    "dcgs_pool_require": (INT, [P, P, INT, I64, C.POINTER(INT), C.POINTER(INT), P]),
+    "dcgs_pool_read_chunk": (INT, [P, C.c_uint64, P, P, P, P]),
+    "dcgs_pool_resident": (INT, [P, P, INT, C.POINTER(INT), C.POINTER(I64)]),
+    "dcgs_compact": (INT, [P, P, P, INT, P, I64, P, P, I64, C.POINTER(I64), P]),
+    "dcgs_state_create": (INT, [P, C.POINTER(P)]),
+    "dcgs_state_destroy": (None, [P]),
+    "dcgs_render_fwd": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
+    "dcgs_render_bwd": (INT, [P, P, P, I64, I64, P, P, P, I64, INT, P, P]),
+    "dcgs_loss_l1": (INT, [P, P, P, I64, P, P, P]),
+    "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
+    "dcgs_state_info": (INT, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)]),
+    "dcgs_state_export": (INT, [P, P, P, P, P, P, P, P, P]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library (raises LibraryMissing when it was never built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} not found; build it with "
+                                 "`python -m paper_2511_23030_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def ptr(t) -> int | None:
+    """Device (or host) address of a torch tensor / numpy array, None for None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return t.data_ptr()
+    return t.ctypes.data
+
+
+def stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Context:
+    """A libdcgs context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdcgs needs a HIP device; none is visible")
+        self.device = device
+        torch.cuda.set_device(device)
+        h = P()
+        self._check(lib().dcgs_create(C.byref(h), device), None)
+        self.h = h
+
+    def _check(self, st: int, handle=None):
+        if st != 0:
+            msg = lib().dcgs_last_error(handle if handle is not None else getattr(self, "h", None))
+            raise DcgsError(st, (msg or b"").decode())
+
+    def check(self, st: int):
+        self._check(st, self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dcgs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- chunks ----
+    def chunk_ids(self, mean, chunk_size: float, stream=None):
+        import torch
+        n = mean.shape[1]
+        out = torch.empty(n, dtype=torch.int64, device=mean.device)
+        self.check(lib().dcgs_chunk_ids(self.h, ptr(mean), n, mean.stride(0), chunk_size,
+                                        ptr(out), stream_handle(stream)))
+        return out
+
+    def select_chunks(self, cams: list, ids, chunk_size: float, stream=None):
+        """ids: device int64 (uint64 bit patterns), ascending.  Returns
+        (out_ids, out_mask, count) device tensors; count is a 1-element int32."""
+        import torch
+        n = ids.numel()
+        arr = (Camera * len(cams))(*[Camera.of(c) for c in cams])
+        out_ids = torch.empty(max(n, 1), dtype=torch.int64, device=ids.device)
+        out_mask = torch.empty(max(n, 1), dtype=torch.int16, device=ids.device)
+        count = torch.empty(1, dtype=torch.int32, device=ids.device)
+        self.check(lib().dcgs_select_chunks(self.h, C.cast(arr, P), len(cams), ptr(ids), n,
+                                            chunk_size, ptr(out_ids), ptr(out_mask), ptr(count),
+                                            stream_handle(stream)))
+        return out_ids, out_mask, count
+
+    def loss_l1(self, rgb, target, dl_out=None, stats=None, stream=None):
+        import torch
+        dl = torch.empty_like(rgb) if dl_out is None else dl_out
+        st = torch.empty(2, dtype=torch.float64, device=rgb.device) if stats is None else stats
+        self.check(lib().dcgs_loss_l1(self.h, ptr(rgb), ptr(target), rgb.numel(), ptr(dl),
+                                      ptr(st), stream_handle(stream)))
+        return dl, st
+
+
+class Pool:
+    """Chunk store (pinned host) plus device residency pool with an LRU budget."""
+
+    def __init__(self, ctx: Context, sh_degree: int, budget: int):
+        h = P()
+        ctx.check(lib().dcgs_pool_create(ctx.h, sh_degree, int(budget), C.byref(h)))
+        self.ctx, self.h, self.sh_degree = ctx, h, sh_degree
+        self.R = 11 + 3 * (sh_degree + 1) ** 2
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dcgs_pool_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ingest(self, params: np.ndarray, chunk_size: float, stream=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.shape[0] == self.R
+        self.ctx.check(lib().dcgs_pool_ingest(self.h, p.ctypes.data, p.shape[1], chunk_size,
+                                              stream_handle(stream)))
+
+    def chunks(self):
+        n = INT()
+        lib().dcgs_pool_chunks(self.h, None, None, 0, C.byref(n))
+        ids = np.zeros(n.value, np.uint64)
+        counts = np.zeros(n.value, np.int64)
+        self.ctx.check(lib().dcgs_pool_chunks(self.h, ids.ctypes.data, counts.ctypes.data,
+                                              n.value, C.byref(n)))
+        return ids, counts
+
+    def device_ids(self):
+        """(device address, count) of the ascending occupied chunk ids."""
+        n = INT()
+        addr = lib().dcgs_pool_device_ids(self.h, C.byref(n))
+        return addr, n.value
+
+    def require(self, ids: np.ndarray, now: int, stream=None):
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        lo, ev = INT(), INT()
+        self.ctx.check(lib().dcgs_pool_require(self.h, ids.ctypes.data, ids.size, now,
+                                               C.byref(lo), C.byref(ev), stream_handle(stream)))
+        return lo.value, ev.value
+
+    def read_chunk(self, cid: int, count: int):
+        p = np.zeros((self.R, count), np.float32)
+        m = np.zeros_like(p)
+        v = np.zeros_like(p)
+        s = np.zeros(count, np.int32)
+        self.ctx.check(lib().dcgs_pool_read_chunk(self.h, int(cid), p.ctypes.data, m.ctypes.data,
+                                                  v.ctypes.data, s.ctypes.data))
+        return p, m, v, s
+
+    def resident(self):
+        n, g = INT(), I64()
+        lib().dcgs_pool_resident(self.h, None, 0, C.byref(n), C.byref(g))
+        ids = np.zeros(max(n.value, 1), np.uint64)
+        self.ctx.check(lib().dcgs_pool_resident(self.h, ids.ctypes.data, ids.size, C.byref(n),
+                                                C.byref(g)))
+        return ids[:n.value], g.value
+
+    def compact(self, ids: np.ndarray, out, out_src, masks: np.ndarray | None = None,
+                out_gmask=None, stream=None) -> int:
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        mk = None if masks is None else np.ascontiguousarray(masks, dtype=np.uint16)
+        n = I64()
+        self.ctx.check(lib().dcgs_compact(self.h, ids.ctypes.data, None if mk is None else mk.ctypes.data,
+                                          ids.size, ptr(out), out.stride(0), ptr(out_src),
+                                          ptr(out_gmask), out.shape[1], C.byref(n),
+                                          stream_handle(stream)))
+        return n.value
+
+    def adam_step(self, src, grad, n: int, cfg: AdamConfig, stream=None):
+        self.ctx.check(lib().dcgs_adam_step(self.h, ptr(src), ptr(grad), n, grad.stride(0),
+                                            C.byref(cfg), stream_handle(stream)))
+
+
+class RenderState:
+    """Forward state of one render (records, sorted pairs, ranges, per-pixel
+    transmittance and last position) kept for its backward."""
+
+    def __init__(self, ctx: Context):
+        h = P()
+        ctx.check(lib().dcgs_state_create(ctx.h, C.byref(h)))
+        self.ctx, self.h = ctx, h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dcgs_state_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def forward(self, params, n: int, sh_degree: int, cam: dict, bg, tile=(16, 16),
+                rgb=None, depth=None, T=None, stream=None):
+        import torch
+        H, W = cam["height"], cam["width"]
+        dev = params.device
+        rgb = torch.empty(3, H, W, dtype=torch.float32, device=dev) if rgb is None else rgb
+        depth = torch.empty(H, W, dtype=torch.float32, device=dev) if depth is None else depth
+        bgv = (C.c_float * 3)(*[float(x) for x in bg])
+        camc = Camera.of(cam)
+        self.ctx.check(lib().dcgs_render_fwd(self.ctx.h, self.h, ptr(params), n, params.stride(0),
+                                             sh_degree, C.byref(camc), bgv, tile[0], tile[1],
+                                             ptr(rgb), ptr(depth), ptr(T), stream_handle(stream)))
+        return rgb, depth
+
+    def backward(self, params, n: int, dl_drgb, dl_ddepth=None, grad=None, accumulate=False,
+                 grad2d=None, stream=None):
+        import torch
+        if grad is None:
+            grad = torch.empty(params.shape[0], max(n, 1), dtype=torch.float32, device=params.device)
+        self.ctx.check(lib().dcgs_render_bwd(self.ctx.h, self.h, ptr(params), n, params.stride(0),
+                                             ptr(dl_drgb), ptr(dl_ddepth), ptr(grad),
+                                             grad.stride(0), int(accumulate), ptr(grad2d),
+                                             stream_handle(stream)))
+        return grad
+
+    def info(self):
+        n, p, tx, ty = I64(), I64(), I32(), I32()
+        lib().dcgs_state_info(self.h, C.byref(n), C.byref(p), C.byref(tx), C.byref(ty))
+        return dict(n=n.value, n_pairs=p.value, tiles_x=tx.value, tiles_y=ty.value)
+
+    def export(self, device, H: int, W: int, stream=None) -> dict:
+        """Copy the last forward's keys, values, ranges, counts, records, boxes
+        and per-pixel last positions to torch tensors."""
+        import torch
+        inf = self.info()
+        P_, n, nt = inf["n_pairs"], inf["n"], inf["tiles_x"] * inf["tiles_y"]
+        out = dict(keys=torch.empty(max(P_, 1), dtype=torch.int64, device=device),
+                   values=torch.empty(max(P_, 1), dtype=torch.int32, device=device),
+                   ranges=torch.empty(nt, 2, dtype=torch.int32, device=device),
+                   counts=torch.empty(max(n, 1), dtype=torch.int32, device=device),
+                   records=torch.empty(10, max(n, 1), dtype=torch.float32, device=device),
+                   box=torch.empty(4, max(n, 1), dtype=torch.int32, device=device),
+                   last=torch.empty(H, W, dtype=torch.int32, device=device))
+        self.ctx.check(lib().dcgs_state_export(self.h, ptr(out["keys"]), ptr(out["values"]),
+                                               ptr(out["ranges"]), ptr(out["counts"]),
+                                               ptr(out["records"]), ptr(out["box"]),
+                                               ptr(out["last"]), stream_handle(stream)))
+        out["keys"] = out["keys"][:P_]
+        out["values"] = out["values"][:P_]
+        out["counts"] = out["counts"][:n]
+        out["records"] = out["records"][:, :n]
+        out["box"] = out["box"][:, :n]
+        return out

@@ -82,18 +82,19 @@ def look_camera(position, yaw, pitch, fx, fy, width, height, z_near=0.2, z_far=1
 # Tiny scene: one view, one chunk, SH degree 0.
 # --------------------------------------------------------------------------
 def tiny_scene(n: int = 10_000, seed: int = 0, width: int = 256, height: int = 192,
-               focal: float = 200.0) -> dict:
+               focal: float = 200.0, sh_degree: int = 0, rest_sd: float = 0.05) -> dict:
     """Means uniform in [-2,2]^2 x [2,6] in front of an identity-pose camera;
     log-scales N(-3.5, 0.5); uniform unit quaternions; logits N(0,1);
-    colour U(0,1) through the degree-0 coefficient."""
+    colour U(0,1) through the degree-0 coefficient (higher SH N(0, rest_sd^2)
+    when sh_degree > 0)."""
     rng = _rng(seed)
-    params = np.zeros((n_rows(0), n), np.float64)
+    params = np.zeros((n_rows(sh_degree), n), np.float64)
     params[0] = rng.uniform(-2.0, 2.0, n)
     params[1] = rng.uniform(-2.0, 2.0, n)
     params[2] = rng.uniform(2.0, 6.0, n)
-    _fill_common(rng, params, n, -3.5, 0.5, 0, 0.0)
+    _fill_common(rng, params, n, -3.5, 0.5, sh_degree, rest_sd)
     cam = camera(np.eye(3), np.zeros(3), focal, focal, width / 2.0, height / 2.0, width, height)
-    return dict(params=params.astype(np.float32), sh_degree=0, camera=cam, chunk_size=16.0)
+    return dict(params=params.astype(np.float32), sh_degree=sh_degree, camera=cam, chunk_size=16.0)
 
 
 def target_image(width: int, height: int, seed: int = 1, channels: int = 3) -> np.ndarray:

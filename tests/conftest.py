@@ -21,3 +21,18 @@ def pytest_collection_modifyitems(config, items):
 @pytest.fixture(scope="session")
 def repo_root():
     return ROOT
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """A libdcgs context on cuda:0.  GPU tests fail (never skip) when the
+    device or the library is missing."""
+    import torch
+
+    from paper_2511_23030_amd import dcgs
+    assert torch.cuda.is_available(), "GPU test run without a visible HIP device"
+    dcgs.lib()
+    c = dcgs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()

@@ -1,0 +1,194 @@
+"""GPU parity of the render path against the FP64 oracle (tiny config and a
+ragged image): records, tile keys, per-tile ranges, images, gradients."""
+import math
+
+import numpy as np
+import pytest
+
+import scenegen
+from gpu_helpers import (IMG_TOL, assert_grad_close, flagged_pixels, gpu_render)
+from oracle import splat as osp
+
+pytestmark = pytest.mark.gpu
+
+TILES = [(16, 16), (8, 8), (32, 16)]
+SIZES = [(256, 192), (250, 190)]      # the tiny config and a ragged tail
+
+
+def _scene(size, deg=0, n=10_000, seed=0):
+    W, H = size
+    return scenegen.tiny_scene(n=n, seed=seed, width=W, height=H, sh_degree=deg)
+
+
+@pytest.mark.parametrize("size", SIZES)
+@pytest.mark.parametrize("tile", TILES)
+def test_keys_ranges_records(ctx, size, tile):
+    sc = _scene(size)
+    cam = sc["camera"]
+    print(f"case keys size={size} tile={tile}", flush=True)
+    g = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], tile)
+    rec = osp.preprocess(sc["params"], 0, cam, tile)
+    kr = osp.tile_keys(rec)
+    assert not rec.key_tie.any()
+    assert (g["counts"] == kr["counts"]).all()
+    vis = ~rec.culled
+    assert ((g["counts"] == 0) == rec.culled).all()
+    assert (g["box"].T[vis] == rec.box[vis]).all()
+    assert g["n_pairs"] == kr["keys"].size
+    assert (g["keys"].view(np.uint64) == kr["keys"]).all()
+    assert (g["values"] == kr["values"]).all()
+    assert (g["ranges"] == kr["ranges"]).all()
+    r = g["records"]
+    u = rec.u.detach().numpy()[vis]
+    v = rec.v.detach().numpy()[vis]
+    assert np.abs(r[0][vis] - u).max() < 2e-5 * max(size)
+    assert np.abs(r[1][vis] - v).max() < 2e-5 * max(size)
+    Q = rec.conic.detach().numpy()[vis]
+    for k in range(3):
+        assert np.abs(r[2 + k][vis] - Q[:, k]).max() <= 1e-6 * np.abs(Q).max() + 1e-6 * np.abs(Q[:, k]).max()
+    assert np.abs(r[5][vis] - rec.opacity.detach().numpy()[vis]).max() < 1e-6
+    assert np.abs(r[6:9][:, vis].T - rec.rgb.detach().numpy()[vis]).max() < 1e-6
+    assert (r[9][vis].astype(np.float32).view(np.int32) == rec.zbits[vis]).all()
+
+
+@pytest.mark.parametrize("size", SIZES)
+def test_image_parity_and_tile_independence(ctx, size):
+    sc = _scene(size)
+    cam = sc["camera"]
+    bg = np.array([0.1, 0.2, 0.3])
+    rec, img = osp.render(sc["params"], 0, cam, bg)
+    flag = flagged_pixels(img)
+    assert flag.sum() <= 0.001 * flag.size
+    ok = ~flag
+    ref_rgb = img.rgb.detach().numpy()
+    imgs = []
+    for tile in TILES:
+        print(f"case image size={size} tile={tile}", flush=True)
+        g = gpu_render(ctx, sc["params"], 0, cam, bg, tile)
+        assert np.abs(g["rgb"] - ref_rgb)[:, ok].max() <= IMG_TOL
+        assert np.abs(g["T"] - img.T.detach().numpy())[ok].max() <= IMG_TOL
+        D = img.depth.detach().numpy()
+        assert (np.abs(g["depth"] - D)[ok] <= IMG_TOL * np.maximum(1.0, np.abs(D[ok]))).all()
+        last = g["last"]
+        gid = np.where(last >= 0, g["values"][np.maximum(last, 0)], -1)
+        assert (gid[ok] == img.last_g[ok]).all()
+        imgs.append(g["rgb"])
+    for other in imgs[1:]:
+        assert (other == imgs[0]).all()          # bitwise: tile size never changes the image
+
+
+@pytest.mark.parametrize("deg,size,seed", [(0, (256, 192), 0), (3, (250, 190), 5)])
+def test_gradient_parity(ctx, deg, size, seed):
+    sc = _scene(size, deg=deg, seed=seed)
+    cam = sc["camera"]
+    if deg:   # a rotated, offset camera so view directions vary
+        from scipy.spatial.transform import Rotation
+        R = Rotation.from_rotvec([0.05, -0.08, 0.03]).as_matrix()
+        C = np.array([0.3, -0.2, -0.5])
+        cam = scenegen.camera(R, -R @ C, 200.0, 200.0, size[0] / 2, size[1] / 2, size[0], size[1])
+    bg = np.array([0.3, 0.1, 0.2])
+    rec = osp.preprocess(sc["params"], deg, cam, requires_grad=True)
+    img = osp.composite(rec, bg)
+    flag = flagged_pixels(img)
+    W, H = size
+    dl = scenegen.upstream_grad(W, H, seed=20 + seed, scale=1e-3)
+    dld = scenegen.upstream_grad(W, H, seed=30 + seed, channels=1, scale=1e-4)[0]
+    dl[:, flag] = 0.0
+    dld[flag] = 0.0
+    gr = osp.render_grad(rec, img, dl, dld)
+    print(f"case grad deg={deg} size={size}", flush=True)
+    g = gpu_render(ctx, sc["params"], deg, cam, bg, (16, 16), dl, dld)
+    vis = ~rec.culled
+    assert vis.sum() > 1000
+    colour_ok = vis & (rec.raw_rgb_margin > 1e-5)
+    g2 = g["grad2d"]
+    assert_grad_close(g2[0:2], gr.uv.T, "d(u,v)", vis)
+    assert_grad_close(g2[2:5], gr.conic.T, "d conic", vis)
+    assert_grad_close(g2[5:6], gr.opacity[None], "d opacity", vis)
+    assert_grad_close(g2[6:9], gr.rgb.T, "d colour", vis)
+    assert_grad_close(g2[9:10], gr.z[None], "d depth", vis)
+    G, Gr = g["grad"], gr.params
+    assert_grad_close(G[0:3], Gr[0:3], "d mean", colour_ok)
+    assert_grad_close(G[3:6], Gr[3:6], "d log-scale", vis)
+    assert_grad_close(G[6:10], Gr[6:10], "d quaternion", vis)
+    assert_grad_close(G[10:11], Gr[10:11], "d opacity logit", vis)
+    assert_grad_close(G[11:], Gr[11:], "d SH", colour_ok)
+    assert (G[:, rec.culled] == 0).all()
+
+
+def test_backward_is_deterministic(ctx):
+    sc = _scene((256, 192))
+    cam = sc["camera"]
+    dl = scenegen.upstream_grad(256, 192, seed=3, scale=1e-3)
+    a = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl)
+    b = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl)
+    assert (a["grad"] == b["grad"]).all() and (a["rgb"] == b["rgb"]).all()
+
+
+def test_empty_and_all_culled(ctx):
+    cam = scenegen.camera(np.eye(3), np.zeros(3), 50.0, 50.0, 32.0, 24.0, 64, 48)
+    bg = [0.25, 0.5, 0.75]
+    empty = np.zeros((14, 0), np.float32)
+    g = gpu_render(ctx, empty, 0, cam, bg)
+    assert (g["rgb"] == np.array(bg, np.float32)[:, None, None]).all() and (g["T"] == 1).all()
+    sc = _scene((64, 48), n=500)
+    p = sc["params"].copy()
+    p[10] = -30.0                        # opacity below 1/255: everything culled
+    dl = scenegen.upstream_grad(64, 48, seed=1)
+    g = gpu_render(ctx, p, 0, cam, bg, (16, 16), dl)
+    assert g["n_pairs"] == 0
+    assert (g["rgb"] == np.array(bg, np.float32)[:, None, None]).all()
+    assert (g["grad"] == 0).all()
+
+
+def test_single_gaussian_closed_form(ctx):
+    """Independent of the oracle: an isotropic Gaussian on the optical axis."""
+    cam = scenegen.camera(np.eye(3), np.zeros(3), 50.0, 50.0, 32.0, 24.0, 64, 48)
+    s, Z, logit = 0.05, 3.0, 0.5
+    p = np.zeros((14, 1), np.float32)
+    p[2, 0] = Z
+    p[3:6, 0] = math.log(s)
+    p[6, 0] = 1.0
+    p[10, 0] = logit
+    c = np.array([0.9, 0.3, 0.1])
+    p[11:14, 0] = (c - 0.5) * 2 * math.sqrt(math.pi)
+    bg = np.array([0.2, 0.4, 0.6])
+    g = gpu_render(ctx, p, 0, cam, bg)
+    var = (50.0 * s / Z) ** 2 + 0.3
+    j, i = np.meshgrid(np.arange(48) + 0.5, np.arange(64) + 0.5, indexing="ij")
+    a = np.minimum(0.99, np.exp(-0.5 * ((i - 32) ** 2 + (j - 24) ** 2) / var) / (1 + math.exp(-logit)))
+    a = np.where(a < 1 / 255, 0.0, a)
+    assert np.abs(g["rgb"] - (c[:, None, None] * a + (1 - a) * bg[:, None, None])).max() < IMG_TOL
+
+
+def test_keys_rotated_camera_sh3(ctx):
+    """A rotated, offset camera: keys and ranges bit-exact on every tile whose
+    list holds no Gaussian within 1e-11 of a rounding or integer decision;
+    a flagged Gaussian's depth key is one of the two nearest float32 values."""
+    from scipy.spatial.transform import Rotation
+    sc = _scene((250, 190), deg=3, seed=5)
+    R = Rotation.from_rotvec([0.05, -0.08, 0.03]).as_matrix()
+    C = np.array([0.3, -0.2, -0.5])
+    cam = scenegen.camera(R, -R @ C, 200.0, 200.0, 125.0, 95.0, 250, 190)
+    g = gpu_render(ctx, sc["params"], 3, cam, [0, 0, 0], (16, 16))
+    rec = osp.preprocess(sc["params"], 3, cam, (16, 16))
+    kr = osp.tile_keys(rec)
+    tie = rec.key_tie
+    assert tie.sum() <= 10
+    ok = ~tie & ~rec.culled
+    assert (g["counts"][ok] == kr["counts"][ok]).all()
+    zg = g["records"][9].astype(np.float32).view(np.int32).astype(np.int64)
+    assert (np.abs(zg[tie] - rec.zbits[tie]) <= 1).all()
+    bad_tiles = set()
+    for gi in np.nonzero(tie)[0]:
+        t = rec.tile_rect[gi]
+        for ty in range(t[2], t[3] + 1):
+            for tx in range(t[0], t[1] + 1):
+                bad_tiles.add(ty * kr["tiles_x"] + tx)
+    for t in range(kr["ranges"].shape[0]):
+        if t in bad_tiles:
+            continue
+        lo, hi = kr["ranges"][t]
+        glo, ghi = g["ranges"][t]
+        assert (g["keys"][glo:ghi].view(np.uint64) == kr["keys"][lo:hi]).all()
+        assert (g["values"][glo:ghi] == kr["values"][lo:hi]).all()
