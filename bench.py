@@ -1,0 +1,261 @@
+"""Mapping-iteration throughput of the DiskChunGS hot path on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload indoor-2m]
+
+One step = one full mapping iteration for one keyframe (visible-chunk
+selection, residency, compaction, projection, depth and tile sorts, raster
+forward, L1 loss, raster backward, projection backward, Adam into the pool).
+Inputs are resident in HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd splat mapping iters/s @1200x680, ~2M active Gaussians; batched vs plain"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    # The indoor room of the indoor experiments, scaled so that a keyframe
+    # sees ~2M Gaussians: 5.75M Gaussians on floor and walls of an 8x8x3 m
+    # room, SH degree 3, 2 m chunks, 1200x680 views (fx = fy = 600) along a
+    # smooth random walk, z_far = 5 m (about 19 of 57 chunks per keyframe).
+    "indoor-2m": dict(n=5_750_000, deg=3, chunk=2.0, W=1200, H=680, f=600.0, z_far=5.0,
+                      frames=400, every=8),
+    # The same room with 1.5M Gaussians (the indoor configuration as stated).
+    "indoor-1.5m": dict(n=1_500_000, deg=3, chunk=2.0, W=1200, H=680, f=600.0, z_far=5.0,
+                        frames=400, every=8),
+    # Small smoke-sized variant.
+    "indoor-small": dict(n=200_000, deg=3, chunk=2.0, W=320, H=180, f=160.0, z_far=5.0,
+                         frames=80, every=8),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str) -> dict:
+    import scenegen
+    w = dict(WORKLOADS[name])
+    sc = scenegen.room_scene(w["n"], seed=10, sh_degree=w["deg"])
+    w["true"] = sc["params"]
+    w["start"] = scenegen.perturb(sc["params"], seed=12)
+    cams = scenegen.room_trajectory(w["frames"], seed=11, width=w["W"], height=w["H"],
+                                    focal=w["f"], z_far=w["z_far"])
+    w["cams"] = cams[::w["every"]]
+    return w
+
+
+# Algorithmic HBM bytes per launch of each streaming stage (SH degree 3:
+# R = 59 float rows = 236 B per Gaussian), N active Gaussians, P pairs.
+def stage_bytes(stage: str, N: float, P: float, Npx: float, R: int) -> float:
+    g = 4.0 * R
+    return {
+        "compact": (2 * g + 4) * N,
+        "preprocess": (g + 64) * N,
+        "depth_sort": 64 * N,
+        "tile_sort": 32 * P,
+        "preprocess_bwd": (2 * g + 48 * 0) * N,
+        "adam": (g + 4 + 3 * g + 4 + 3 * g + 4) * N,
+        "loss": 36 * Npx,
+    }.get(stage, 0.0)
+
+
+# FP32 operations per (pixel, Gaussian) evaluation of the raster kernels,
+# counted from the kernels' arithmetic (an FMA counts 2, exp counts 1).
+RASTER_FLOPS = {"raster_fwd": 30.0, "raster_bwd": 80.0}
+
+
+def processed_evaluations(st_export: dict, tw: int, th: int, W: int, H: int) -> float:
+    """Sum over pixels of the list positions a pixel walks (tile start to its
+    last composited Gaussian): the evaluations both raster kernels perform."""
+    last = st_export["last"].cpu().numpy()
+    ranges = st_export["ranges"].cpu().numpy()
+    tx = -(-W // tw)
+    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    tile = (jj // th) * tx + (ii // tw)
+    start = ranges[tile, 0]
+    walk = np.where(last >= 0, last - start + 1, 0)
+    return float(walk.sum())
+
+
+def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray, budget_s: float = 20.0) -> dict:
+    """The FP64 oracle timed on the host on a bounded sample of one mapping
+    iteration: projection forward+backward of 1/16 of the active Gaussians
+    and compositing forward+backward of a 48x48 pixel crop at the image
+    centre, each scaled to the whole iteration."""
+    import torch
+
+    from oracle import chunks as oc
+    from oracle import splat as osp
+    P = w["start"]
+    cid = oc.encode_id(oc.chunk_coord(P[0:3].T, w["chunk"]))
+    act = np.isin(cid, ids_active)
+    Pa = P[:, act]
+    n_act = Pa.shape[1]
+    sub = Pa[:, ::16]
+    t0 = time.perf_counter()
+    rec = osp.preprocess(sub, w["deg"], cam, requires_grad=True)
+    (rec.u.sum() + rec.v.sum() + rec.conic.sum() + rec.rgb.sum() + rec.opacity.sum()).backward()
+    t_pre = (time.perf_counter() - t0) * (n_act / sub.shape[1])
+    W, H, c = w["W"], w["H"], 48
+    crop = (W // 2 - c // 2, W // 2 + c // 2, H // 2 - c // 2, H // 2 + c // 2)
+    t0 = time.perf_counter()
+    rec = osp.preprocess(Pa, w["deg"], cam, requires_grad=True)
+    t_full_pre = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    img = osp.composite(rec, np.zeros(3), crop)
+    dl = np.ones((3, c, c)) / (3 * W * H)
+    osp.render_grad(rec, img, dl)
+    t_crop = time.perf_counter() - t0
+    t_iter = t_pre + t_crop * (W * H) / (c * c)
+    return {"value": 1.0 / t_iter, "unit": "iters/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": (f"FP64 oracle on one keyframe of the workload ({n_act} active Gaussians): "
+                       f"projection fwd+bwd of 1/16 of them scaled x16 ({t_pre:.1f} s) plus "
+                       f"compositing fwd+bwd of a {c}x{c} crop scaled to {W}x{H} "
+                       f"({t_crop:.2f} s x {W * H / (c * c):.0f}); the crop's projection "
+                       f"({t_full_pre:.1f} s) is not counted twice")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="indoor-2m", choices=sorted(WORKLOADS))
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--profile-steps", type=int, default=6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--extra-json", default="")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of this path is described in DESIGN.md and not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2511_23030_amd import dcgs as D
+    from paper_2511_23030_amd import mapping
+    if not os.path.exists(D.LIB_PATH):
+        from paper_2511_23030_amd import build as B
+        B.build()
+    tw, th = (int(x) for x in args.tile.split("x"))
+    t_setup = time.perf_counter()
+    w = make_workload(args.workload)
+    log(f"workload {args.workload}: {w['n']} Gaussians, {len(w['cams'])} keyframes "
+        f"(generated in {time.perf_counter() - t_setup:.1f} s)")
+    ctx = D.Context(0)
+    R = 11 + 3 * (w["deg"] + 1) ** 2
+
+    # targets: renders of the true scene at every keyframe
+    gt_pool = D.Pool(ctx, w["deg"], budget=w["n"] + 1)
+    gt_pool.ingest(w["true"], w["chunk"])
+    gt_loop = mapping.MappingLoop(ctx, gt_pool, w["deg"], w["chunk"], int(w["n"] * 0.6),
+                                  w["W"], w["H"], (tw, th))
+    targets, actives = [], []
+    for cam in w["cams"]:
+        ids = gt_loop.select(cam)
+        gt_pool.require(ids, now=0)
+        n = gt_pool.compact(ids, gt_loop.params, gt_loop.src)
+        rgb, _ = gt_loop.state.forward(gt_loop.params, n, w["deg"], cam, (0, 0, 0), (tw, th))
+        targets.append(rgb.clone())
+        actives.append(n)
+    del gt_loop
+    gt_pool.close()
+    torch.cuda.synchronize()
+    log(f"targets rendered; active Gaussians per keyframe mean {np.mean(actives):.0f} "
+        f"min {min(actives)} max {max(actives)}")
+
+    pool = D.Pool(ctx, w["deg"], budget=w["n"] + 1)
+    pool.ingest(w["start"], w["chunk"])
+    loop = mapping.MappingLoop(ctx, pool, w["deg"], w["chunk"], int(max(actives) * 1.05) + 16,
+                               w["W"], w["H"], (tw, th))
+    K = len(w["cams"])
+    for s in range(args.warmup):
+        loop.step(w["cams"][s % K], targets[s % K])
+    torch.cuda.synchronize()
+    log(f"setup {time.perf_counter() - t_setup:.1f} s; timing {args.steps} steps")
+
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        k = (args.warmup + s) % K
+        loop.step(w["cams"][k], targets[k])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log(f"timed {args.steps} steps in {dt:.3f} s")
+    l1, psnr = loop.loss_psnr(3 * w["W"] * w["H"])
+
+    # stage profile (HIP events on the launch stream), outside the timed region
+    ctx.profile(True)
+    Ns, Ps, Es = [], [], []
+    for s in range(args.profile_steps):
+        k = s % K
+        loop.step(w["cams"][k], targets[k])
+        Ns.append(loop.last["n_active"])
+        Ps.append(loop.state.info()["n_pairs"])
+        ex = loop.state.export(torch.device("cuda"), w["H"], w["W"])
+        Es.append(processed_evaluations(ex, tw, th, w["W"], w["H"]))
+    torch.cuda.synchronize()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    N, Pp, E, Npx = float(np.mean(Ns)), float(np.mean(Ps)), float(np.mean(Es)), w["W"] * w["H"]
+    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    dominant = max(stages, key=stages.get)
+    avg_ms = stages[dominant]
+    if dominant in RASTER_FLOPS:
+        achieved = RASTER_FLOPS[dominant] * E / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                "kernel": dominant}
+    else:
+        achieved = stage_bytes(dominant, N, Pp, Npx, R) / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dominant}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cam = w["cams"][0]
+            ids = loop.select(cam)
+            cpu = cpu_baseline(w, cam, ids)
+        except Exception as e:  # the baseline is reported, never required
+            log(f"cpu baseline failed: {e!r}")
+
+    out = {
+        "metric": METRIC, "value": round(args.steps / dt, 3), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: plain per-view mapping iteration, indoor room "
+                               f"{w['n']} Gaussians SH{w['deg']}, {w['W']}x{w['H']}, "
+                               f"{w['chunk']:g} m chunks, tile {tw}x{th}",
+                   "active_gaussians_mean": round(N), "pairs_mean": round(Pp),
+                   "evaluations_mean": round(E), "path": "plain"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "l1": round(l1, 5), "psnr_db": round(psnr, 3),
+    }
+    print(json.dumps(out), flush=True)
+    if args.extra_json:
+        with open(args.extra_json, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -229,6 +229,33 @@ int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad,
                    int64_t n, int64_t grad_stride,
                    const dcgs_adam_config *cfg, void *stream);
 
+/* ---- stage timers -------------------------------------------------------- */
+
+/* Stages timed with HIP events recorded on the stream each kernel runs on. */
+typedef enum dcgs_stage {
+  DCGS_STAGE_SELECT = 0,       /* chunk visibility + compaction of ids      */
+  DCGS_STAGE_COMPACT = 1,      /* gather of active chunks into one buffer   */
+  DCGS_STAGE_PREPROCESS = 2,   /* projection records                        */
+  DCGS_STAGE_DEPTH_SORT = 3,   /* radix sort of Gaussians by depth key      */
+  DCGS_STAGE_SCAN_EMIT = 4,    /* pair offsets + pair emission              */
+  DCGS_STAGE_TILE_SORT = 5,    /* radix sort of pairs by tile               */
+  DCGS_STAGE_RANGES = 6,       /* per-tile [start, end)                     */
+  DCGS_STAGE_RASTER_FWD = 7,   /* front-to-back compositing                 */
+  DCGS_STAGE_LOSS = 8,         /* L1 loss and its gradient                  */
+  DCGS_STAGE_RASTER_BWD = 9,   /* back-to-front adjoint                     */
+  DCGS_STAGE_PREPROCESS_BWD = 10, /* projection backward                    */
+  DCGS_STAGE_ADAM = 11,        /* optimiser step into the pool              */
+  DCGS_STAGE_COUNT = 12
+} dcgs_stage;
+
+/* Enable (1) or disable (0) stage timing on ctx; enabling clears totals. */
+int dcgs_profile_enable(dcgs_ctx *ctx, int enable);
+
+/* SYNC.  Totals since enabling: ms[s] summed milliseconds and calls[s]
+ * launches of stage s, for s < n_stages (<= DCGS_STAGE_COUNT); either may
+ * be null.  Totals are then cleared. */
+int dcgs_profile_read(dcgs_ctx *ctx, double *ms, int64_t *calls, int n_stages);
+
 /* ---- inspection (for tests and tools) ------------------------------------ */
 
 /* Sizes of the last forward on st: Gaussians, pairs, tiles in x and y. */

@@ -17,6 +17,19 @@ void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int 
                   int64_t capacity, int64_t *n_out, hipStream_t st);
 }  // namespace dcgs
 
+namespace dcgs {
+hipEvent_t take_event(dcgs_ctx *ctx) noexcept {
+  if (!ctx->spare_events.empty()) {
+    hipEvent_t e = ctx->spare_events.back();
+    ctx->spare_events.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace dcgs
+
 namespace {
 
 template <typename F>
@@ -72,7 +85,15 @@ int dcgs_create(dcgs_ctx **out, int device) {
   return DCGS_OK;
 }
 
-void dcgs_destroy(dcgs_ctx *ctx) { delete ctx; }
+void dcgs_destroy(dcgs_ctx *ctx) {
+  if (!ctx) return;
+  for (auto &m : ctx->marks) {
+    (void)hipEventDestroy(m.a);
+    (void)hipEventDestroy(m.b);
+  }
+  for (auto e : ctx->spare_events) (void)hipEventDestroy(e);
+  delete ctx;
+}
 
 const char *dcgs_last_error(const dcgs_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -104,6 +125,7 @@ int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views, cons
                    (n_chunks == 0 || (ids && out_ids && out_mask)),
                DCGS_E_INVALID, "select_chunks: bad buffers");
     uint16_t *tmp = ctx->sel_mask.need((size_t)n_chunks + 1);
+    dcgs::StageTimer tm(ctx, DCGS_STAGE_SELECT, S(stream));
     dcgs::launch_select(cams, n_views, ids, n_chunks, chunk_size, tmp, out_ids, out_mask,
                         out_count, S(stream));
   });
@@ -241,6 +263,7 @@ int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target, int64_t c
     DCGS_CHECK(rgb && target && dl_drgb && stats && count > 0, DCGS_E_INVALID,
                "loss_l1: bad args");
     float *part = ctx->loss_part.need(2 * 1024);
+    dcgs::StageTimer tm(ctx, DCGS_STAGE_LOSS, S(stream));
     dcgs::launch_loss_l1(rgb, target, count, dl_drgb, stats, part, S(stream));
   });
 }
@@ -252,8 +275,45 @@ int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad, int64
     DCGS_CHECK(cfg && n >= 0 && (n == 0 || (src && grad && grad_stride >= n)), DCGS_E_INVALID,
                "adam_step: bad args");
     DCGS_CHECK(pool->d_params, DCGS_E_INVALID, "adam_step: pool holds no scene");
+    dcgs::StageTimer tm(pool->ctx, DCGS_STAGE_ADAM, S(stream));
     dcgs::launch_adam(pool->d_params, pool->d_m, pool->d_v, pool->d_step, pool->R, src, grad, n,
                       grad_stride, *cfg, S(stream));
+  });
+}
+
+int dcgs_profile_enable(dcgs_ctx *ctx, int enable) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    for (auto &m : ctx->marks) {
+      ctx->spare_events.push_back(m.a);
+      ctx->spare_events.push_back(m.b);
+    }
+    ctx->marks.clear();
+    ctx->prof = enable != 0;
+  });
+}
+
+int dcgs_profile_read(dcgs_ctx *ctx, double *ms, int64_t *calls, int n_stages) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(n_stages >= 0 && n_stages <= DCGS_STAGE_COUNT, DCGS_E_INVALID,
+               "profile_read: n_stages out of range");
+    for (int k = 0; k < n_stages; ++k) {
+      if (ms) ms[k] = 0.0;
+      if (calls) calls[k] = 0;
+    }
+    for (auto &m : ctx->marks) {
+      DCGS_HIP(hipEventSynchronize(m.b));
+      float t = 0.0f;
+      DCGS_HIP(hipEventElapsedTime(&t, m.a, m.b));
+      if (m.stage < n_stages) {
+        if (ms) ms[m.stage] += t;
+        if (calls) calls[m.stage] += 1;
+      }
+      ctx->spare_events.push_back(m.a);
+      ctx->spare_events.push_back(m.b);
+    }
+    ctx->marks.clear();
   });
 }
 

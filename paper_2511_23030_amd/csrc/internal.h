@@ -80,6 +80,14 @@ inline void digit_plan(int bits, int *passes, int *width) {
 struct dcgs_ctx {
   int device = 0;
   std::string err;
+  // stage timers
+  bool prof = false;
+  struct Mark {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> spare_events;
   dcgs::DevBuf<uint16_t> sel_mask;
   dcgs::DevBuf<int> flag;
   dcgs::DevBuf<float> loss_part;
@@ -157,6 +165,29 @@ struct dcgs_pool {
 };
 
 namespace dcgs {
+
+// A timing event from the context's free list (nullptr if none can be made).
+hipEvent_t take_event(dcgs_ctx *ctx) noexcept;
+
+// Records start/stop events around a stage on `st` when ctx->prof is set.
+// Never throws: a failed record only drops that sample.
+struct StageTimer {
+  dcgs_ctx *ctx;
+  hipStream_t st;
+  int stage;
+  hipEvent_t a = nullptr;
+  StageTimer(dcgs_ctx *c, int s, hipStream_t stream) noexcept : ctx(c), st(stream), stage(s) {
+    if (ctx && ctx->prof) {
+      a = take_event(ctx);
+      if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
+    }
+  }
+  ~StageTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(ctx);
+    if (b && hipEventRecord(b, st) == hipSuccess) ctx->marks.push_back({stage, a, b});
+  }
+};
 
 // ---- launchers (one translation unit each) ----
 void launch_chunk_ids(const float *mean, int64_t n, int64_t stride, double s,

@@ -343,6 +343,7 @@ void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int 
   int4 *dseg = p->d_seg.need(nseg);
   DCGS_HIP(hipMemcpyAsync(dseg, p->h_seg, nseg * sizeof(int4), hipMemcpyHostToDevice, st));
   DCGS_HIP(hipEventRecord(p->seg_done, st));
+  StageTimer tm(p->ctx, DCGS_STAGE_COMPACT, st);
   launch_compact(p->d_params, p->R, dseg, (int)nseg, nullptr, out, out_stride, out_src,
                  out_gmask, st);
 }

@@ -767,10 +767,15 @@ void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t strid
   s->frontier.need(nt + 1);
   s->T_final.need(HW + 1);
   s->last.need(HW + 1);
+  dcgs_ctx *ctx = s->ctx;
   if (n > 0) {
+    StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
     hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n, 256)), dim3(256), 0, st, params, n,
                        stride, s->sh_degree, cam, s->TW, s->TH, rec, zkey, sortkey, order, cnt);
     DCGS_LAUNCH_CHECK();
+  }
+  if (n > 0) {
+    StageTimer ts(ctx, DCGS_STAGE_DEPTH_SORT, st);
     // depth order of the Gaussians: stable sort of the float32 depth bits
     sort_u32_pairs(sortkey, order, sortkey + n + 1, vtmp, n, 32, s->hist, st);
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(n, 256)), dim3(256), 0, st, order, n,
@@ -778,7 +783,10 @@ void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t strid
     DCGS_LAUNCH_CHECK();
   }
   uint32_t *part = s->ctx->scan_part.need(scan_part_size(n) + 2);
-  scan_u32(cnt, order, scan, n, part, st);
+  {
+    StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
+    scan_u32(cnt, order, scan, n, part, st);
+  }
   uint32_t total = 0;
   DCGS_HIP(hipMemcpyAsync(&total, scan + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   DCGS_HIP(hipStreamSynchronize(st));
@@ -787,16 +795,24 @@ void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t strid
   uint64_t *ptmp = s->pairs_tmp.need((size_t)total + 1);
   s->partial.need(3 * (size_t)total + 3);
   if (n > 0) {
+    StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(n, 256)), dim3(256), 0, st, order, cnt, scan,
                        rec + 2 * n, n, s->TW, s->TH, s->tiles_x, pairs, s->pair_off.p);
     DCGS_LAUNCH_CHECK();
   }
   int tile_bits = 0;
   while ((1 << tile_bits) < nt) ++tile_bits;
-  if (total > 0) sort_u64_bits(pairs, ptmp, total, 32, tile_bits, s->hist, st);
-  hipLaunchKernelGGL(k_ranges, dim3(blocks_for(nt, 256)), dim3(256), 0, st, pairs,
-                     (int64_t)total, nt, s->ranges.p);
-  DCGS_LAUNCH_CHECK();
+  if (total > 0) {
+    StageTimer tt(ctx, DCGS_STAGE_TILE_SORT, st);
+    sort_u64_bits(pairs, ptmp, total, 32, tile_bits, s->hist, st);
+  }
+  {
+    StageTimer tr(ctx, DCGS_STAGE_RANGES, st);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(nt, 256)), dim3(256), 0, st, pairs,
+                       (int64_t)total, nt, s->ranges.p);
+    DCGS_LAUNCH_CHECK();
+  }
+  StageTimer tf(ctx, DCGS_STAGE_RASTER_FWD, st);
   if (s->TW == 16 && s->TH == 16) launch_fwd_t<16, 16>(s, st, rgb, depth, T);
   else if (s->TW == 8 && s->TH == 8) launch_fwd_t<8, 8>(s, st, rgb, depth, T);
   else launch_fwd_t<32, 16>(s, st, rgb, depth, T);
@@ -806,10 +822,14 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
                      const float *dl_drgb, const float *dl_ddepth, float *grad,
                      int64_t grad_stride, int accumulate, float *grad2d, hipStream_t st) {
   const CamD cam = make_cam(s->cam);
-  if (s->TW == 16 && s->TH == 16) launch_bwd_t<16, 16>(s, st, dl_drgb, dl_ddepth);
-  else if (s->TW == 8 && s->TH == 8) launch_bwd_t<8, 8>(s, st, dl_drgb, dl_ddepth);
-  else launch_bwd_t<32, 16>(s, st, dl_drgb, dl_ddepth);
+  {
+    StageTimer tb(s->ctx, DCGS_STAGE_RASTER_BWD, st);
+    if (s->TW == 16 && s->TH == 16) launch_bwd_t<16, 16>(s, st, dl_drgb, dl_ddepth);
+    else if (s->TW == 8 && s->TH == 8) launch_bwd_t<8, 8>(s, st, dl_drgb, dl_ddepth);
+    else launch_bwd_t<32, 16>(s, st, dl_drgb, dl_ddepth);
+  }
   if (n > 0) {
+    StageTimer tp(s->ctx, DCGS_STAGE_PREPROCESS_BWD, st);
     hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, params,
                        n, stride, s->sh_degree, cam, s->TW, s->TH, s->tiles_x, s->count.p,
                        s->pair_off.p, s->rank_of.p, s->frontier.p, s->partial.p, grad,

@@ -87,6 +87,8 @@ SIGNATURES = {
     "dcgs_render_bwd": (INT, [P, P, P, I64, I64, P, P, P, I64, INT, P, P]),
     "dcgs_loss_l1": (INT, [P, P, P, I64, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
+    "dcgs_profile_enable": (INT, [P, INT]),
+    "dcgs_profile_read": (INT, [P, P, P, INT]),
     "dcgs_state_info": (INT, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)]),
     "dcgs_state_export": (INT, [P, P, P, P, P, P, P, P, P]),
 }
@@ -179,6 +181,19 @@ class Context:
                                             chunk_size, ptr(out_ids), ptr(out_mask), ptr(count),
                                             stream_handle(stream)))
         return out_ids, out_mask, count
+
+    STAGES = ("select", "compact", "preprocess", "depth_sort", "scan_emit", "tile_sort",
+              "ranges", "raster_fwd", "loss", "raster_bwd", "preprocess_bwd", "adam")
+
+    def profile(self, enable: bool):
+        self.check(lib().dcgs_profile_enable(self.h, int(enable)))
+
+    def profile_read(self) -> dict:
+        n = len(self.STAGES)
+        ms = np.zeros(n, np.float64)
+        calls = np.zeros(n, np.int64)
+        self.check(lib().dcgs_profile_read(self.h, ms.ctypes.data, calls.ctypes.data, n))
+        return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(self.STAGES)}
 
     def loss_l1(self, rgb, target, dl_out=None, stats=None, stream=None):
         import torch

@@ -1,0 +1,95 @@
+"""Parity at the headline workload's real size, in the launch configuration
+bench.py times (indoor room, 5.75M Gaussians, ~2M active, 1200x680, 16x16
+tiles): every tile key and range bit-exact; colour, depth and transmittance
+on three sampled 64x64 crops; gradients of every Gaussian whose pixel box
+lies inside the central crop (its whole gradient comes from that crop)."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import IMG_TOL, assert_grad_close, flagged_pixels
+from oracle import chunks as oc
+from oracle import splat as osp
+from paper_2511_23030_amd import dcgs as D
+from paper_2511_23030_amd import mapping
+
+pytestmark = pytest.mark.gpu
+
+
+def test_headline_keyframe(ctx):
+    import bench
+    w = bench.make_workload("indoor-2m")
+    cam = w["cams"][3]
+    W, H, deg, s = w["W"], w["H"], w["deg"], w["chunk"]
+    print("case fullsize: workload generated", flush=True)
+    pool = D.Pool(ctx, deg, budget=w["n"] + 1)
+    pool.ingest(w["start"], s)
+    loop = mapping.MappingLoop(ctx, pool, deg, s, 3_000_000, W, H, (16, 16))
+    ids = loop.select(cam)
+    # the oracle's own selection and compaction
+    cid = oc.encode_id(oc.chunk_coord(w["start"][0:3].T, s))
+    all_ids = np.unique(cid)
+    ref_sel = oc.select_chunks([cam], all_ids, s)
+    assert not ref_sel["tie"].any()
+    assert (ids == ref_sel["union_ids"]).all()
+    pool.require(ids, now=0)
+    n = pool.compact(ids, loop.params, loop.src)
+    order = np.argsort(cid, kind="stable")
+    act = order[np.isin(cid[order], ids)]
+    Pa = w["start"][:, act]
+    assert n == Pa.shape[1] and 1.5e6 < n < 2.6e6
+    assert (loop.params[:, :n].cpu().numpy() == Pa).all()
+    print(f"case fullsize: {n} active", flush=True)
+
+    bg = (0.0, 0.0, 0.0)
+    T = torch.empty(H, W, device="cuda")
+    loop.state.forward(loop.params, n, deg, cam, bg, (16, 16), loop.rgb, loop.depth, T)
+    ex = loop.state.export(loop.params.device, H, W)
+    rec = osp.preprocess(Pa, deg, cam, (16, 16), requires_grad=True)
+    kr = osp.tile_keys(rec)
+    tie = rec.key_tie
+    assert tie.sum() < 1e-4 * n
+    bad_tiles = np.zeros(kr["ranges"].shape[0], bool)
+    for gi in np.nonzero(tie)[0]:
+        t = rec.tile_rect[gi]
+        for ty in range(t[2], t[3] + 1):
+            bad_tiles[ty * kr["tiles_x"] + t[0]: ty * kr["tiles_x"] + t[1] + 1] = True
+    gk = ex["keys"].cpu().numpy().view(np.uint64)
+    gv = ex["values"].cpu().numpy()
+    gr = ex["ranges"].cpu().numpy()
+    assert gk.size == kr["keys"].size
+    for t in np.nonzero(~bad_tiles)[0]:
+        lo, hi = kr["ranges"][t]
+        glo, ghi = gr[t]
+        assert (glo, ghi) == (lo, hi) or bad_tiles[:t].any()
+        assert (gk[glo:ghi] == kr["keys"][lo:hi]).all() and (gv[glo:ghi] == kr["values"][lo:hi]).all()
+    print("case fullsize: keys and ranges", flush=True)
+
+    rgb, depth, Tg = loop.rgb.cpu().numpy(), loop.depth.cpu().numpy(), T.cpu().numpy()
+    crops = [(568, 632, 308, 372), (0, 64, 0, 64), (1136, 1200, 616, 680)]
+    rng = np.random.default_rng(9)
+    dl = (rng.normal(size=(3, H, W)) * 1e-6).astype(np.float32)
+    for k, (x0, x1, y0, y1) in enumerate(crops):
+        img = osp.composite(rec, np.zeros(3), (x0, x1, y0, y1))
+        flag = flagged_pixels(img)
+        assert flag.sum() <= 0.01 * flag.size
+        ok = ~flag
+        assert np.abs(rgb[:, y0:y1, x0:x1] - img.rgb.detach().numpy())[:, ok].max() <= IMG_TOL
+        assert np.abs(Tg[y0:y1, x0:x1] - img.T.detach().numpy())[ok].max() <= IMG_TOL
+        Dr = img.depth.detach().numpy()
+        assert (np.abs(depth[y0:y1, x0:x1] - Dr)[ok] <= IMG_TOL * np.maximum(1, np.abs(Dr[ok]))).all()
+        if k == 0:
+            dl[:, y0:y1, x0:x1][:, flag] = 0.0
+            central = (img, (x0, x1, y0, y1))
+    print("case fullsize: images", flush=True)
+
+    img, (x0, x1, y0, y1) = central
+    box = rec.box
+    inside = (~rec.culled & (box[:, 0] >= x0) & (box[:, 1] < x1) & (box[:, 2] >= y0)
+              & (box[:, 3] < y1) & (rec.raw_rgb_margin > 1e-5))
+    assert inside.sum() >= 50
+    g_ref = osp.render_grad(rec, img, dl[:, y0:y1, x0:x1])
+    grad = loop.state.backward(loop.params, n, torch.from_numpy(dl).cuda(), None, loop.grad)
+    G = grad[:, :n].cpu().numpy()
+    assert_grad_close(G[:, inside], g_ref.params[:, inside], "full-size gradients")
+    pool.close()
