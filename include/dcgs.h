@@ -188,36 +188,58 @@ int dcgs_compact(dcgs_pool *pool, const uint64_t *ids, const uint16_t *masks,
 int dcgs_state_create(dcgs_ctx *ctx, dcgs_state **out);
 void dcgs_state_destroy(dcgs_state *st);
 
-/* SYNC (reads the pair count back once).  Render one view.
+/* SYNC (reads the pair count back once).  Render n_views views of one
+ * parameter block in single launches (the batched window of a mapping
+ * step; n_views = 1 is the plain per-view render).
  *   params: device [R][stride], n Gaussians, SH degree sh_degree
- *   cam: host; bg: host float[3]; tile_w x tile_h in {8x8, 16x16, 32x16}
- *   rgb: device [3][H][W]; depth: device [H][W]; T: device [H][W] or null.
+ *   gmask: device uint16 [n] or null: Gaussian i is drawn in view v only when
+ *          bit v + mask_shift is set (the view mask of its chunk); null draws
+ *          all Gaussians in all views.  mask_shift lets view k of a window be
+ *          rendered alone from the window's compacted buffer.
+ *   cams: host [n_views], 1 <= n_views <= 16, all of one width and height
+ *   bg: host float[3]
+ *   raster shape: tile_w x tile_h pixels per workgroup, pixels_per_lane
+ *   vertically adjacent pixels per lane; supported (16,16,{1,2,4}),
+ *   (8,8,1), (32,16,{2,4,8}); pixels_per_lane 0 picks 2, 1 and 4.  The
+ *   image does not depend on the shape (each pixel composites only the
+ *   Gaussians whose pixel box holds it), nor on the other views.
+ *   rgb: device [n_views][3][H][W]; depth: device [n_views][H][W];
+ *   T: device [n_views][H][W] or null.
  * Outputs are overwritten.  The state keeps what render_bwd needs. */
 int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params,
                     int64_t n, int64_t stride, int sh_degree,
-                    const dcgs_camera *cam, const float *bg, int tile_w,
-                    int tile_h, float *rgb, float *depth, float *T,
+                    const uint16_t *gmask, int mask_shift,
+                    const dcgs_camera *cams, int n_views, const float *bg,
+                    int tile_w, int tile_h,
+                    int pixels_per_lane, float *rgb, float *depth, float *T,
                     void *stream);
 
 /* Backward of the last render_fwd on `st` (same params): the adjoint of the
  * compositing runs back to front from each pixel's last composited Gaussian,
  * recovering each earlier transmittance by division, then chains through
- * the projection to the raw parameters.
- *   dl_drgb: device [3][H][W]; dl_ddepth: device [H][W] or null
+ * the projection to the raw parameters, summing the views in view order
+ * (float32 additions in the same order as one single-view backward per
+ * view accumulating into grad).  Deterministic: no float atomics.
+ *   dl_drgb: device [n_views][3][H][W]; dl_ddepth: device [n_views][H][W]
+ *   or null
  *   grad: device [R][grad_stride]; accumulate != 0 adds into it, 0
  *   overwrites rows for all n Gaussians (culled ones get 0).
- *   grad2d: device [10][n] or null: per-Gaussian dL/d(u, v, Q00, Q01, Q11,
- *   o, r, g, b, Z) of the screen-space record (Q01 counted once). */
+ *   grad2d: device [10][n_views * n] or null: per record (view v, Gaussian
+ *   i at v * n + i) dL/d(u, v, Q00, Q01, Q11, o, r, g, b, Z) of the
+ *   screen-space record (Q01 counted once). */
 int dcgs_render_bwd(dcgs_ctx *ctx, dcgs_state *st, const float *params,
                     int64_t n, int64_t stride, const float *dl_drgb,
                     const float *dl_ddepth, float *grad, int64_t grad_stride,
                     int accumulate, float *grad2d, void *stream);
 
-/* Eqs. (2)-(4) without SSIM: dl_drgb = sign(rgb - target) / count (0 at
- * equality); stats (device double[2]) gets sum |rgb - target| and the sum of
- * squared error with rgb clipped to [0, 1] (for PSNR). */
+/* Eqs. (2)-(4) without SSIM over `count` values: dl_drgb = sign(rgb -
+ * target) / norm (0 at equality), so norm = 3HW gives the mean over one
+ * image and, for n_views images in one buffer, the sum over views of each
+ * view's mean; stats (device double[2]) gets sum |rgb - target| and the sum
+ * of squared error with rgb clipped to [0, 1] (for PSNR). */
 int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target,
-                 int64_t count, float *dl_drgb, double *stats, void *stream);
+                 int64_t count, double norm, float *dl_drgb, double *stats,
+                 void *stream);
 
 /* ---- optimiser: per-Gaussian Adam state (Sec. III-G resets it) ----------- */
 

@@ -86,7 +86,7 @@ class Records:
     box: np.ndarray               # int64 [n, 4]: i0, i1, j0, j1 (inclusive)
     tile_rect: np.ndarray         # int64 [n, 4]: tx0, tx1, ty0, ty1
     raw_rgb_margin: np.ndarray    # |colour before clamp| (gradient switch)
-    key_tie: np.ndarray           # bool: some integer decision within 1e-9 of a flip
+    key_tie: np.ndarray           # bool: some integer decision within 1e-13 of a flip
     width: int
     height: int
     tile: tuple
@@ -163,7 +163,7 @@ def preprocess(params: np.ndarray, sh_degree: int, cam: dict, tile=(16, 16),
         zbits = zf.view(np.int32).astype(np.int64)
 
         # Margins of every integer decision that is actually reached
-        # (relative); 1e-11 is far above the float64 disagreement of two
+        # (relative); 1e-13 is far above the float64 disagreement of two
         # correct implementations (~1e-15).
         def frac_margin(x):
             return np.abs(x - np.round(x)) / np.maximum(1.0, np.abs(x))
@@ -179,7 +179,7 @@ def preprocess(params: np.ndarray, sh_degree: int, cam: dict, tile=(16, 16),
             m = np.minimum.reduce([m_near, m_guard, m_opac, m_box])
             ulp = np.abs(np.nextafter(zf, np.float32(np.inf)).astype(np.float64) - zf.astype(np.float64))
             mz = np.where(culled, inf, np.abs(np.abs(Zd - zf.astype(np.float64)) - 0.5 * ulp) / np.abs(Zd))
-        key_tie = (m < 1e-11) | (mz < 1e-11)
+        key_tie = (m < 1e-13) | (mz < 1e-13)
         rgb_margin = np.abs(raw.numpy()).min(axis=1)
 
     # The composited depth is its own graph node, so its gradient is the

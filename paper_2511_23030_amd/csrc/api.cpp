@@ -210,34 +210,54 @@ int dcgs_state_create(dcgs_ctx *ctx, dcgs_state **out) {
   return DCGS_OK;
 }
 
-void dcgs_state_destroy(dcgs_state *st) { delete st; }
+void dcgs_state_destroy(dcgs_state *st) {
+  if (!st) return;
+  if (st->cam_pinned) (void)hipHostFree(st->cam_pinned);
+  delete st;
+}
 
 int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n,
-                    int64_t stride, int sh_degree, const dcgs_camera *cam, const float *bg,
-                    int tile_w, int tile_h, float *rgb, float *depth, float *T, void *stream) {
+                    int64_t stride, int sh_degree, const uint16_t *gmask, int mask_shift,
+                    const dcgs_camera *cams, int n_views, const float *bg, int tile_w,
+                    int tile_h, int pixels_per_lane, float *rgb, float *depth, float *T,
+                    void *stream) {
   if (!ctx) return DCGS_E_INVALID;
   return guarded(ctx, [&] {
     DCGS_CHECK(st && st->ctx == ctx, DCGS_E_INVALID, "render_fwd: state of another context");
-    DCGS_CHECK(n >= 0 && n < (int64_t(1) << 31) && stride >= n && (n == 0 || params),
-               DCGS_E_INVALID, "render_fwd: bad parameter block");
+    DCGS_CHECK(n_views >= 1 && n_views <= dcgs::kMaxViews && cams, DCGS_E_INVALID,
+               "render_fwd: 1..16 views required");
+    DCGS_CHECK(n >= 0 && n * n_views < (int64_t(1) << 31) && stride >= n && (n == 0 || params),
+               DCGS_E_INVALID, "render_fwd: bad parameter block (n * n_views must be < 2^31)");
     DCGS_CHECK(sh_degree >= 0 && sh_degree <= 3, DCGS_E_INVALID, "render_fwd: sh_degree 0..3");
-    DCGS_CHECK((tile_w == 16 && tile_h == 16) || (tile_w == 8 && tile_h == 8) ||
-                   (tile_w == 32 && tile_h == 16),
-               DCGS_E_INVALID, "render_fwd: tile must be 8x8, 16x16 or 32x16");
-    check_cam(cam);
+    DCGS_CHECK(mask_shift >= 0 && mask_shift + n_views <= 16, DCGS_E_INVALID,
+               "render_fwd: mask_shift + n_views must be <= 16");
+    int ppt = pixels_per_lane;
+    if (ppt == 0) ppt = tile_w == 8 ? 1 : tile_w == 16 ? 2 : 4;
+    const bool shape_ok = (tile_w == 16 && tile_h == 16 && (ppt == 1 || ppt == 2 || ppt == 4)) ||
+                          (tile_w == 8 && tile_h == 8 && ppt == 1) ||
+                          (tile_w == 32 && tile_h == 16 && (ppt == 2 || ppt == 4 || ppt == 8));
+    DCGS_CHECK(shape_ok, DCGS_E_INVALID,
+               "render_fwd: raster shape must be 16x16x{1,2,4}, 8x8x1 or 32x16x{2,4,8}");
+    for (int v = 0; v < n_views; ++v) {
+      check_cam(&cams[v]);
+      DCGS_CHECK(cams[v].width == cams[0].width && cams[v].height == cams[0].height,
+                 DCGS_E_INVALID, "render_fwd: all views must share width and height");
+      st->cams[v] = cams[v];
+    }
     DCGS_CHECK(bg && rgb && depth, DCGS_E_INVALID, "render_fwd: null output");
-    st->cam = *cam;
-    st->W = cam->width;
-    st->H = cam->height;
+    st->V = n_views;
+    st->ppt = ppt;
+    st->W = cams[0].width;
+    st->H = cams[0].height;
     st->TW = tile_w;
     st->TH = tile_h;
-    st->tiles_x = (cam->width + tile_w - 1) / tile_w;
-    st->tiles_y = (cam->height + tile_h - 1) / tile_h;
-    DCGS_CHECK((int64_t)st->tiles_x * st->tiles_y < (int64_t(1) << 24), DCGS_E_INVALID,
+    st->tiles_x = (st->W + tile_w - 1) / tile_w;
+    st->tiles_y = (st->H + tile_h - 1) / tile_h;
+    DCGS_CHECK((int64_t)st->tiles_x * st->tiles_y * n_views < (int64_t(1) << 24), DCGS_E_INVALID,
                "render_fwd: too many tiles");
     st->sh_degree = sh_degree;
     std::memcpy(st->bg, bg, 3 * sizeof(float));
-    dcgs::render_forward(st, params, n, stride, S(stream), rgb, depth, T);
+    dcgs::render_forward(st, params, n, stride, gmask, mask_shift, S(stream), rgb, depth, T);
   });
 }
 
@@ -247,7 +267,7 @@ int dcgs_render_bwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t 
   if (!ctx) return DCGS_E_INVALID;
   return guarded(ctx, [&] {
     DCGS_CHECK(st && st->ctx == ctx, DCGS_E_INVALID, "render_bwd: state of another context");
-    DCGS_CHECK(n == st->n && st->W > 0, DCGS_E_INVALID,
+    DCGS_CHECK(n == st->n && st->W > 0 && st->cam_dev.p, DCGS_E_INVALID,
                "render_bwd: n differs from the last forward on this state");
     DCGS_CHECK(dl_drgb && (n == 0 || (params && grad && grad_stride >= n && stride >= n)),
                DCGS_E_INVALID, "render_bwd: bad buffers");
@@ -257,14 +277,14 @@ int dcgs_render_bwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t 
 }
 
 int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target, int64_t count,
-                 float *dl_drgb, double *stats, void *stream) {
+                 double norm, float *dl_drgb, double *stats, void *stream) {
   if (!ctx) return DCGS_E_INVALID;
   return guarded(ctx, [&] {
-    DCGS_CHECK(rgb && target && dl_drgb && stats && count > 0, DCGS_E_INVALID,
+    DCGS_CHECK(rgb && target && dl_drgb && stats && count > 0 && norm > 0, DCGS_E_INVALID,
                "loss_l1: bad args");
     float *part = ctx->loss_part.need(2 * 1024);
     dcgs::StageTimer tm(ctx, DCGS_STAGE_LOSS, S(stream));
-    dcgs::launch_loss_l1(rgb, target, count, dl_drgb, stats, part, S(stream));
+    dcgs::launch_loss_l1(rgb, target, count, norm, dl_drgb, stats, part, S(stream));
   });
 }
 

@@ -99,9 +99,12 @@ struct dcgs_state {
   dcgs_ctx *ctx = nullptr;
   // shape of the last forward
   int64_t n = 0, n_pairs = 0;
-  int W = 0, H = 0, TW = 16, TH = 16, tiles_x = 0, tiles_y = 0, sh_degree = 0;
+  int W = 0, H = 0, TW = 16, TH = 16, ppt = 2, tiles_x = 0, tiles_y = 0, sh_degree = 0;
   float bg[3] = {0, 0, 0};
-  dcgs_camera cam{};
+  int V = 1;                              // views rendered together
+  dcgs_camera cams[dcgs::kMaxViews]{};
+  dcgs::DevBuf<uint8_t> cam_dev;          // projection constants per view
+  void *cam_pinned = nullptr;             // host staging for cam_dev
   // per Gaussian
   dcgs::DevBuf<float4> rec;        // [3][n] float4 (A, B, C planes)
   dcgs::DevBuf<uint32_t> zkey;     // [n]
@@ -204,7 +207,8 @@ void launch_adam(float *params, float *m, float *v, int32_t *step, int R,
                  int64_t grad_stride, const dcgs_adam_config &cfg,
                  hipStream_t st);
 void launch_loss_l1(const float *rgb, const float *target, int64_t count,
-                    float *dl, double *stats, float *part, hipStream_t st);
+                    double norm, float *dl, double *stats, float *part,
+                    hipStream_t st);
 
 // exclusive scan of in (or of in[gather[i]] when gather != null), n
 // elements; out has n + 1 entries (out[n] = total).
@@ -222,8 +226,8 @@ void sort_u64_bits(uint64_t *a, uint64_t *tmp, int64_t n, int lo, int bits,
                    DevBuf<uint32_t> &hist, hipStream_t st);
 
 void render_forward(dcgs_state *s, const float *params, int64_t n,
-                    int64_t stride, hipStream_t st, float *rgb, float *depth,
-                    float *T);
+                    int64_t stride, const uint16_t *gmask, int mask_shift, hipStream_t st,
+                    float *rgb, float *depth, float *T);
 void render_backward(dcgs_state *s, const float *params, int64_t n,
                      int64_t stride, const float *dl_drgb,
                      const float *dl_ddepth, float *grad, int64_t grad_stride,

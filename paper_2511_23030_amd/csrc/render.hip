@@ -95,35 +95,33 @@ __device__ inline void sh_eval(int deg, double x, double y, double z, double *Y)
   Y[15] = c33 * x * (x * x - 3.0 * y * y);
 }
 
-// Gradient of each basis function with respect to (x, y, z), treated as
-// independent; the caller projects onto the sphere's tangent plane.
-__device__ inline void sh_grad(int deg, double x, double y, double z, double (*G)[3]) {
+// gd = sum_k f[k] grad Y_k(x, y, z), with (x, y, z) treated as independent
+// (the caller projects onto the sphere's tangent plane); k >= 1.
+__device__ inline void sh_grad_dot(int deg, double x, double y, double z, const double *f,
+                                   double gd[3]) {
   constexpr double kPi = 3.14159265358979323846;
-  G[0][0] = G[0][1] = G[0][2] = 0.0;
+  gd[0] = gd[1] = gd[2] = 0.0;
   if (deg < 1) return;
   const double c1 = sqrt(3.0 / (4.0 * kPi));
-  G[1][0] = 0; G[1][1] = c1; G[1][2] = 0;
-  G[2][0] = 0; G[2][1] = 0; G[2][2] = c1;
-  G[3][0] = c1; G[3][1] = 0; G[3][2] = 0;
+  gd[0] += c1 * f[3];
+  gd[1] += c1 * f[1];
+  gd[2] += c1 * f[2];
   if (deg < 2) return;
   const double c2a = 0.5 * sqrt(15.0 / kPi), c20 = 0.25 * sqrt(5.0 / kPi),
                c22 = 0.25 * sqrt(15.0 / kPi);
-  G[4][0] = c2a * y; G[4][1] = c2a * x; G[4][2] = 0;
-  G[5][0] = 0; G[5][1] = c2a * z; G[5][2] = c2a * y;
-  G[6][0] = 0; G[6][1] = 0; G[6][2] = 6.0 * c20 * z;
-  G[7][0] = c2a * z; G[7][1] = 0; G[7][2] = c2a * x;
-  G[8][0] = 2.0 * c22 * x; G[8][1] = -2.0 * c22 * y; G[8][2] = 0;
+  gd[0] += c2a * y * f[4] + c2a * z * f[7] + 2.0 * c22 * x * f[8];
+  gd[1] += c2a * x * f[4] + c2a * z * f[5] - 2.0 * c22 * y * f[8];
+  gd[2] += c2a * y * f[5] + 6.0 * c20 * z * f[6] + c2a * x * f[7];
   if (deg < 3) return;
   const double c33 = 0.25 * sqrt(35.0 / (2.0 * kPi)), c32 = 0.5 * sqrt(105.0 / kPi),
                c31 = 0.25 * sqrt(21.0 / (2.0 * kPi)), c30 = 0.25 * sqrt(7.0 / kPi),
                c32b = 0.25 * sqrt(105.0 / kPi);
-  G[9][0] = 6.0 * c33 * x * y; G[9][1] = c33 * (3.0 * x * x - 3.0 * y * y); G[9][2] = 0;
-  G[10][0] = c32 * y * z; G[10][1] = c32 * x * z; G[10][2] = c32 * x * y;
-  G[11][0] = 0; G[11][1] = c31 * (5.0 * z * z - 1.0); G[11][2] = 10.0 * c31 * y * z;
-  G[12][0] = 0; G[12][1] = 0; G[12][2] = c30 * (15.0 * z * z - 3.0);
-  G[13][0] = c31 * (5.0 * z * z - 1.0); G[13][1] = 0; G[13][2] = 10.0 * c31 * x * z;
-  G[14][0] = 2.0 * c32b * x * z; G[14][1] = -2.0 * c32b * y * z; G[14][2] = c32b * (x * x - y * y);
-  G[15][0] = c33 * (3.0 * x * x - 3.0 * y * y); G[15][1] = -6.0 * c33 * x * y; G[15][2] = 0;
+  gd[0] += 6.0 * c33 * x * y * f[9] + c32 * y * z * f[10] + c31 * (5.0 * z * z - 1.0) * f[13] +
+           2.0 * c32b * x * z * f[14] + c33 * (3.0 * x * x - 3.0 * y * y) * f[15];
+  gd[1] += c33 * (3.0 * x * x - 3.0 * y * y) * f[9] + c32 * x * z * f[10] +
+           c31 * (5.0 * z * z - 1.0) * f[11] - 2.0 * c32b * y * z * f[14] - 6.0 * c33 * x * y * f[15];
+  gd[2] += c32 * x * y * f[10] + 10.0 * c31 * y * z * f[11] + c30 * (15.0 * z * z - 3.0) * f[12] +
+           10.0 * c31 * x * z * f[13] + c32b * (x * x - y * y) * f[14];
 }
 
 // Forward geometry of one Gaussian, float64.
@@ -135,8 +133,9 @@ struct Geo {
   int i0, i1, j0, j1;
 };
 
-__device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int64_t i,
-                                const CamD &cam, Geo &g) {
+// Camera-independent part: activations, rotation, covariance.
+__device__ inline void load_gauss(const float *__restrict__ P, int64_t stride, int64_t i,
+                                  Geo &g) {
   for (int k = 0; k < 3; ++k) g.mu[k] = (double)P[k * stride + i];
   for (int k = 0; k < 3; ++k) g.s[k] = exp((double)P[(3 + k) * stride + i]);
   double q[4];
@@ -159,6 +158,10 @@ __device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int
   g.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
   g.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
   g.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+}
+
+// Camera-dependent part: camera coordinates, culling, EWA, conic, pixel box.
+__device__ inline void project(const CamD &cam, Geo &g) {
   const double *Rc = cam.R;
   g.X = Rc[0] * g.mu[0] + Rc[1] * g.mu[1] + Rc[2] * g.mu[2] + cam.t[0];
   g.Y = Rc[3] * g.mu[0] + Rc[4] * g.mu[1] + Rc[5] * g.mu[2] + cam.t[1];
@@ -205,6 +208,12 @@ __device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int
   if (g.i0 > g.i1 || g.j0 > g.j1) g.culled = true;
 }
 
+__device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int64_t i,
+                                const CamD &cam, Geo &g) {
+  load_gauss(P, stride, i, g);
+  project(cam, g);
+}
+
 // Colour before the clamp (raw) for each channel, float64.
 __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, int64_t i,
                                  int deg, const Geo &g, const CamD &cam, double *dir,
@@ -223,39 +232,55 @@ __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, in
   }
 }
 
+// One thread per Gaussian; it projects the Gaussian into every view whose
+// bit is set in its chunk's view mask.  Record r = v * n + g.
 __global__ void __launch_bounds__(256)
     k_preprocess(const float *__restrict__ P, int64_t n, int64_t stride, int deg,
-                 CamD cam, int TW, int TH, float4 *__restrict__ rec,
-                 uint32_t *__restrict__ zkey, uint32_t *__restrict__ sortkey,
-                 uint32_t *__restrict__ order, uint32_t *__restrict__ count) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                 const CamD *__restrict__ cams, int V, const uint16_t *__restrict__ gmask,
+                 int mask_shift, int TW, int TH, float4 *__restrict__ rec,
+                 uint32_t *__restrict__ zkey,
+                 uint32_t *__restrict__ sortkey, uint32_t *__restrict__ order,
+                 uint32_t *__restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int64_t nr = n * V;
   Geo g;
-  load_geo(P, stride, i, cam, g);
-  order[i] = (uint32_t)i;
-  const float zf = (float)g.Z;
-  zkey[i] = __float_as_uint(zf);
-  if (g.culled) {
-    count[i] = 0;
-    sortkey[i] = kCulledKey;
-    rec[i] = make_float4(0, 0, 0, 0);
-    rec[n + i] = make_float4(0, 0, 0, 0);
-    rec[2 * n + i] = make_float4(0, 0, 0, 0);
-    return;
+  load_gauss(P, stride, i, g);
+  const unsigned m = gmask ? ((unsigned)gmask[i] >> mask_shift) : 0xFFFFu;
+  for (int v = 0; v < V; ++v) {
+    const int64_t r = v * n + i;
+    order[r] = (uint32_t)r;
+    const CamD &cam = cams[v];
+    bool culled = !((m >> v) & 1u);
+    float zf = 0.0f;
+    if (!culled) {
+      project(cam, g);
+      culled = g.culled;
+      zf = (float)g.Z;
+    }
+    zkey[r] = __float_as_uint(zf);
+    if (culled) {
+      count[r] = 0;
+      sortkey[r] = kCulledKey;
+      rec[r] = make_float4(0, 0, 0, 0);
+      rec[nr + r] = make_float4(0, 0, 0, 0);
+      rec[2 * nr + r] = make_float4(0, 0, 0, 0);
+      continue;
+    }
+    double dir[3], dn, Y[16], raw[3];
+    color_raw(P, stride, i, deg, g, cam, dir, dn, Y, raw);
+    const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
+    count[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    sortkey[r] = __float_as_uint(zf);
+    const double id = 1.0 / g.det;
+    rec[r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(g.c * id),
+                         (float)(-g.b * id));
+    rec[nr + r] = make_float4((float)(g.a * id), (float)g.o, (float)fmax(raw[0], 0.0),
+                              (float)fmax(raw[1], 0.0));
+    rec[2 * nr + r] = make_float4((float)fmax(raw[2], 0.0), zf,
+                                  __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
+                                  __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
   }
-  double dir[3], dn, Y[16], raw[3];
-  color_raw(P, stride, i, deg, g, cam, dir, dn, Y, raw);
-  const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
-  count[i] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-  sortkey[i] = __float_as_uint(zf);
-  const double id = 1.0 / g.det;
-  rec[i] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(g.c * id),
-                       (float)(-g.b * id));
-  rec[n + i] = make_float4((float)(g.a * id), (float)g.o, (float)fmax(raw[0], 0.0),
-                           (float)fmax(raw[1], 0.0));
-  rec[2 * n + i] = make_float4((float)fmax(raw[2], 0.0), zf,
-                               __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
-                               __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
 }
 
 __global__ void k_rank(const uint32_t *__restrict__ order, int64_t n,
@@ -264,13 +289,16 @@ __global__ void k_rank(const uint32_t *__restrict__ order, int64_t n,
   if (j < n) rank_of[order[j]] = (uint32_t)j;
 }
 
+// Pairs of record r = v n + g: (global tile v T + t) << 32 | r, emitted in
+// depth order, tiles of a record row-major.
 __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
                        const uint32_t *__restrict__ scan, const float4 *__restrict__ recC,
-                       int64_t n, int TW, int TH, int tiles_x,
+                       int64_t nr, int64_t n, int TW, int TH, int tiles_x, int tiles_per_view,
                        uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+  if (j >= nr) return;
   const uint32_t g = order[j];
+  const uint32_t view_base = (uint32_t)(g / (uint64_t)n) * (uint32_t)tiles_per_view;
   const uint32_t c = count[g];
   const uint32_t base = scan[j];
   pair_off[g] = base;
@@ -282,7 +310,7 @@ __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__res
   uint32_t k = base;
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx)
-      pairs[k++] = ((uint64_t)(uint32_t)(ty * tiles_x + tx) << 32) | g;
+      pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | g;
 }
 
 __global__ void k_ranges(const uint64_t *__restrict__ pairs, int64_t P, int n_tiles,
@@ -318,43 +346,67 @@ struct Sample {
 // backward so that both take identical threshold decisions.
 __device__ __forceinline__ Sample sample(int px, int py, const float4 &A, const float4 &B,
                                          const float4 &C) {
+  // No implicit FMA contraction here: every kernel that inlines this takes
+  // the same roundings (HIP's __f*_rn helpers are plain operators).
+#pragma clang fp contract(off)
   Sample s;
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int i0 = bx & 0xFFFF, i1 = bx >> 16, j0 = by & 0xFFFF, j1 = by >> 16;
   s.ok = px >= i0 && px <= i1 && py >= j0 && py <= j1;
-  s.dx = __fsub_rn((float)(px - i0) + 0.5f, A.x);
-  s.dy = __fsub_rn((float)(py - j0) + 0.5f, A.y);
-  const float qxx = __fmul_rn(A.z, __fmul_rn(s.dx, s.dx));
-  const float qyy = __fmul_rn(B.x, __fmul_rn(s.dy, s.dy));
-  const float qxy = __fmul_rn(A.w, __fmul_rn(s.dx, s.dy));
-  s.power = __fsub_rn(__fmul_rn(-0.5f, __fadd_rn(qxx, qyy)), qxy);
-  s.G = __expf(s.power);
-  const float oG = __fmul_rn(B.y, s.G);
+  s.dx = ((float)(px - i0) + 0.5f) - A.x;
+  s.dy = ((float)(py - j0) + 0.5f) - A.y;
+  const float qxx = A.z * (s.dx * s.dx);
+  const float qyy = B.x * (s.dy * s.dy);
+  const float qxy = A.w * (s.dx * s.dy);
+  s.power = -0.5f * (qxx + qyy) - qxy;
+  s.G = __builtin_amdgcn_exp2f(1.44269502f * s.power);  // e^power
+  const float oG = B.y * s.G;
   s.alpha = fminf(kAlphaMax, oG);
   s.ok = s.ok && !(s.power > 0.0f) && !(s.alpha < kAlphaMin);
   return s;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_fwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
                  const float4 *__restrict__ rec, int64_t n, int W, int H, int tiles_x,
-                 int n_tiles, float bg0, float bg1, float bg2, float *__restrict__ rgb,
-                 float *__restrict__ depth, float *__restrict__ Tout,
+                 int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
+                 float *__restrict__ rgb, float *__restrict__ depth, float *__restrict__ Tout,
                  float *__restrict__ Tstate, int *__restrict__ last_out) {
-  constexpr int BS = TW * TH;
+#pragma clang fp contract(off)
+  constexpr int NT = TW * TH / PPT;
+  constexpr int BS = NT;
   __shared__ float4 sA[BS], sB[BS], sC[BS];
-  const int tile = tile_of_block(n_tiles);
-  if (tile >= n_tiles) return;
+  const int gt = tile_of_block(n_tiles);
+  if (gt >= n_tiles) return;
+  const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * TW + (threadIdx.x % TW), py = ty * TH + (threadIdx.x / TW);
-  const bool inside = px < W && py < H;
-  const int2 rg = ranges[tile];
-  float T = 1.0f, c0 = 0.0f, c1 = 0.0f, c2 = 0.0f, D = 0.0f;
-  int last = -1;
-  bool done = !inside;
+  {  // this view's images
+    const int64_t HWv = (int64_t)W * H;
+    rgb += view * 3 * HWv;
+    if (depth) depth += view * HWv;
+    if (Tout) Tout += view * HWv;
+    Tstate += view * HWv;
+    last_out += view * HWv;
+  }
+  // lane t owns PPT vertically adjacent pixels of the tile
+  const int px = tx * TW + (threadIdx.x % TW);
+  const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
+  const int2 rg = ranges[gt];
+  float T[PPT], c0[PPT], c1[PPT], c2[PPT], D[PPT];
+  int last[PPT];
+  bool done[PPT];
+  int n_live = 0;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    T[j] = 1.0f;
+    c0[j] = c1[j] = c2[j] = D[j] = 0.0f;
+    last[j] = -1;
+    done[j] = !(px < W && py0 + j < H);
+    n_live += !done[j];
+  }
   for (int base = rg.x; base < rg.y; base += BS) {
-    if (__syncthreads_count(!done) == 0) break;
+    if (__syncthreads_count(n_live) == 0) break;
     const int p = base + threadIdx.x;
     if (p < rg.y) {
       const uint32_t g = (uint32_t)pairs[p];
@@ -364,66 +416,119 @@ __global__ void __launch_bounds__(TW * TH)
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
-    for (int k = 0; k < nb && !done; ++k) {
+    for (int k = 0; k < nb && n_live > 0; ++k) {
       const float4 A = sA[k], B = sB[k], C = sC[k];
-      const Sample s = sample(px, py, A, B, C);
-      if (!s.ok) continue;
-      const float Tn = T * (1.0f - s.alpha);
-      if (Tn < kTMin) {
-        done = true;
-        break;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (done[j]) continue;
+        const Sample s = sample(px, py0 + j, A, B, C);
+        if (!s.ok) continue;
+        // contraction is off in this kernel: every raster shape composites
+        // with the same roundings
+        const float Tn = T[j] * (1.0f - s.alpha);
+        if (Tn < kTMin) {
+          done[j] = true;
+          --n_live;
+          continue;
+        }
+        const float w = s.alpha * T[j];
+        c0[j] = __builtin_fmaf(B.z, w, c0[j]);
+        c1[j] = __builtin_fmaf(B.w, w, c1[j]);
+        c2[j] = __builtin_fmaf(C.x, w, c2[j]);
+        D[j] = __builtin_fmaf(C.y, w, D[j]);
+        T[j] = Tn;
+        last[j] = base + k;
       }
-      const float w = s.alpha * T;
-      c0 += B.z * w;
-      c1 += B.w * w;
-      c2 += C.x * w;
-      D += C.y * w;
-      T = Tn;
-      last = base + k;
     }
   }
-  if (!inside) return;
-  const int64_t pix = (int64_t)py * W + px, HW = (int64_t)W * H;
-  rgb[pix] = c0 + T * bg0;
-  rgb[HW + pix] = c1 + T * bg1;
-  rgb[2 * HW + pix] = c2 + T * bg2;
-  if (depth) depth[pix] = D;
-  if (Tout) Tout[pix] = T;
-  Tstate[pix] = T;
-  last_out[pix] = last;
+  const int64_t HW = (int64_t)W * H;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int py = py0 + j;
+    if (!(px < W && py < H)) continue;
+    const int64_t pix = (int64_t)py * W + px;
+    rgb[pix] = __builtin_fmaf(T[j], bg0, c0[j]);
+    rgb[HW + pix] = __builtin_fmaf(T[j], bg1, c1[j]);
+    rgb[2 * HW + pix] = __builtin_fmaf(T[j], bg2, c2[j]);
+    if (depth) depth[pix] = D[j];
+    if (Tout) Tout[pix] = T[j];
+    Tstate[pix] = T[j];
+    last_out[pix] = last[j];
+  }
 }
 
-// Sum of 16 values over a wavefront: a butterfly that halves the values each
-// lane carries at every step (17 shuffles instead of 96).  Afterwards lanes
-// 4c .. 4c+3 hold the wave total of value c.
+// Cross-lane moves inside 16-lane rows through DPP (VALU, no LDS path).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppShl4 = 0x104;   // row_shl:4 (lane i reads lane i + 4)
+constexpr int kDppShr4 = 0x114;   // row_shr:4 (lane i reads lane i - 4)
+constexpr int kDppRor8 = 0x128;   // row_ror:8 (lane i reads lane i ^ 8 in a row)
+
+// Sum of 16 values over a wavefront by a halving butterfly: at each level a
+// lane keeps half of its values and adds its partner's copy of that half.
+// Levels 1, 2, 4, 8 stay inside 16-lane rows (DPP); the two cross-row
+// levels move one value each (LDS-crossbar shuffles).  Afterwards the lane
+// whose low 4 bits are l holds the wave total of value bitrev4(l).
 __device__ __forceinline__ float wave_reduce16(float (&v)[16]) {
   const int lane = threadIdx.x & (kWave - 1);
+  {
+    const bool hi = lane & 1;
 #pragma unroll
-  for (int h = 8, m = 32; h >= 1; h >>= 1, m >>= 1) {
-    const bool hi = (lane & m) != 0;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const float send = hi ? v[i] : v[i + h];
-      const float keep = hi ? v[i + h] : v[i];
-      v[i] = keep + __shfl_xor(send, m);
+    for (int i = 0; i < 8; ++i) {
+      const float send = hi ? v[i] : v[i + 8];
+      const float keep = hi ? v[i + 8] : v[i];
+      v[i] = keep + dpp<kDppXor1>(send);
     }
   }
+  {
+    const bool hi = lane & 2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = hi ? v[i] : v[i + 4];
+      const float keep = hi ? v[i + 4] : v[i];
+      v[i] = keep + dpp<kDppXor2>(send);
+    }
+  }
+  {
+    const bool hi = lane & 4;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = hi ? v[i] : v[i + 2];
+      const float keep = hi ? v[i + 2] : v[i];
+      const float up = dpp<kDppShl4>(send), down = dpp<kDppShr4>(send);
+      v[i] = keep + (hi ? down : up);
+    }
+  }
+  {
+    const bool hi = lane & 8;
+    const float send = hi ? v[0] : v[1];
+    const float keep = hi ? v[1] : v[0];
+    v[0] = keep + dpp<kDppRor8>(send);
+  }
   float r = v[0];
-  r += __shfl_xor(r, 2);
-  r += __shfl_xor(r, 1);
+  r += __shfl_xor(r, 16);
+  r += __shfl_xor(r, 32);
   return r;
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH)
+__device__ __forceinline__ int bitrev4(int l) {
+  return ((l & 1) << 3) | ((l & 2) << 1) | ((l & 4) >> 1) | ((l & 8) >> 3);
+}
+
+template <int TW, int TH, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_bwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
                  const float4 *__restrict__ rec, int64_t n, int W, int H, int tiles_x,
-                 int n_tiles, float bg0, float bg1, float bg2,
+                 int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  const float *__restrict__ Tstate, const int *__restrict__ last_in,
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
                  const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
                  float4 *__restrict__ partial, int *__restrict__ frontier) {
-  constexpr int NT = TW * TH;
+  constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
   constexpr int BS = NT < 128 ? NT : 128;  // records per batch
   constexpr int NC = 10;
@@ -431,32 +536,53 @@ __global__ void __launch_bounds__(TW * TH)
   __shared__ uint32_t sG[BS];
   __shared__ float red[NW][BS][NC];
   __shared__ int max_last;
-  const int tile = tile_of_block(n_tiles);
-  if (tile >= n_tiles) return;
+  const int gt = tile_of_block(n_tiles);
+  if (gt >= n_tiles) return;
+  const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int px = tx * TW + (threadIdx.x % TW), py = ty * TH + (threadIdx.x / TW);
-  const bool inside = px < W && py < H;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int2 rg = ranges[tile];
-  const int64_t pix = (int64_t)py * W + px, HW = (int64_t)W * H;
-  float T = 1.0f, g0 = 0, g1 = 0, g2 = 0, gd = 0;
-  int last = -1;
-  if (inside) {
-    T = Tstate[pix];
-    last = last_in[pix];
-    g0 = dl_drgb[pix];
-    g1 = dl_drgb[HW + pix];
-    g2 = dl_drgb[2 * HW + pix];
-    if (dl_ddepth) gd = dl_ddepth[pix];
+  {  // this view's images and upstream gradients
+    const int64_t HWv = (int64_t)W * H;
+    Tstate += view * HWv;
+    last_in += view * HWv;
+    dl_drgb += view * 3 * HWv;
+    if (dl_ddepth) dl_ddepth += view * HWv;
   }
-  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2, SD = 0.0f;
+  const int px = tx * TW + (threadIdx.x % TW);
+  const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int2 rg = ranges[gt];
+  const int64_t HW = (int64_t)W * H;
+  float T[PPT], g0[PPT], g1[PPT], g2[PPT], gd[PPT], S0[PPT], S1[PPT], S2[PPT], SD[PPT];
+  int last[PPT];
+  int my_last = -1;
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    T[j] = 1.0f;
+    g0[j] = g1[j] = g2[j] = gd[j] = 0.0f;
+    last[j] = -1;
+    const int py = py0 + j;
+    if (px < W && py < H) {
+      const int64_t pix = (int64_t)py * W + px;
+      T[j] = Tstate[pix];
+      last[j] = last_in[pix];
+      g0[j] = dl_drgb[pix];
+      g1[j] = dl_drgb[HW + pix];
+      g2[j] = dl_drgb[2 * HW + pix];
+      if (dl_ddepth) gd[j] = dl_ddepth[pix];
+    }
+    S0[j] = T[j] * bg0;
+    S1[j] = T[j] * bg1;
+    S2[j] = T[j] * bg2;
+    SD[j] = 0.0f;
+    my_last = max(my_last, last[j]);
+  }
   if (threadIdx.x == 0) max_last = -1;
   __syncthreads();
-  if (last >= 0) atomicMax(&max_last, last);
+  if (my_last >= 0) atomicMax(&max_last, my_last);
   __syncthreads();
   const int top = max_last;
   if (top < rg.x) {
-    if (threadIdx.x == 0) frontier[tile] = -1;
+    if (threadIdx.x == 0) frontier[gt] = -1;
     return;
   }
   for (int end = top + 1; end > rg.x; end -= BS) {
@@ -472,43 +598,50 @@ __global__ void __launch_bounds__(TW * TH)
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
       const int pos = end - 1 - k;
+      if (__ballot(pos <= my_last) == 0) {  // no pixel of this wave reaches pos
+        if (lane < NC) red[wv][k][lane] = 0.0f;
+        continue;
+      }
       const float4 A = sA[k], B = sB[k], C = sC[k];
       float v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = 0.0f;
       bool contrib = false;
-      if (inside && pos <= last) {
-        const Sample s = sample(px, py, A, B, C);
-        if (s.ok) {
-          contrib = true;
-          const float om = 1.0f - s.alpha;
-          const float Tk = T / om;  // transmittance in front of this Gaussian
-          const float w = s.alpha * Tk;
-          v[6] = g0 * w;
-          v[7] = g1 * w;
-          v[8] = g2 * w;
-          v[9] = gd * w;
-          const float da = g0 * (B.z * Tk - S0 / om) + g1 * (B.w * Tk - S1 / om) +
-                           g2 * (C.x * Tk - S2 / om) + gd * (C.y * Tk - SD / om);
-          S0 += B.z * w;
-          S1 += B.w * w;
-          S2 += C.x * w;
-          SD += C.y * w;
-          T = Tk;
-          if (B.y * s.G <= kAlphaMax) {  // alpha not clamped
-            const float dp = s.alpha * da;
-            v[5] = s.G * da;
-            v[0] = dp * (A.z * s.dx + A.w * s.dy);
-            v[1] = dp * (A.w * s.dx + B.x * s.dy);
-            v[2] = -0.5f * s.dx * s.dx * dp;
-            v[3] = -s.dx * s.dy * dp;
-            v[4] = -0.5f * s.dy * s.dy * dp;
-          }
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        if (pos > last[j]) continue;
+        const Sample s = sample(px, py0 + j, A, B, C);
+        if (!s.ok) continue;
+        contrib = true;
+        const float om = 1.0f - s.alpha;
+        const float iom = __builtin_amdgcn_rcpf(om);
+        const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
+        const float w = s.alpha * Tk;
+        v[6] += g0[j] * w;
+        v[7] += g1[j] * w;
+        v[8] += g2[j] * w;
+        v[9] += gd[j] * w;
+        const float da = g0[j] * (B.z * Tk - S0[j] * iom) + g1[j] * (B.w * Tk - S1[j] * iom) +
+                         g2[j] * (C.x * Tk - S2[j] * iom) + gd[j] * (C.y * Tk - SD[j] * iom);
+        S0[j] += B.z * w;
+        S1[j] += B.w * w;
+        S2[j] += C.x * w;
+        SD[j] += C.y * w;
+        T[j] = Tk;
+        if (B.y * s.G <= kAlphaMax) {  // alpha not clamped
+          const float dp = s.alpha * da;
+          v[5] += s.G * da;
+          v[0] += dp * (A.z * s.dx + A.w * s.dy);
+          v[1] += dp * (A.w * s.dx + B.x * s.dy);
+          v[2] += -0.5f * s.dx * s.dx * dp;
+          v[3] += -s.dx * s.dy * dp;
+          v[4] += -0.5f * s.dy * s.dy * dp;
         }
       }
       if (__ballot(contrib) != 0) {
         const float r = wave_reduce16(v);
-        if ((lane & 3) == 0 && (lane >> 2) < NC) red[wv][k][lane >> 2] = r;
+        const int c = bitrev4(lane & 15);
+        if (lane < 16 && c < NC) red[wv][k][c] = r;
       } else if (lane < NC) {
         red[wv][k][lane] = 0.0f;
       }
@@ -520,6 +653,7 @@ __global__ void __launch_bounds__(TW * TH)
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         float a = 0.0f;
+#pragma unroll
         for (int w = 0; w < NW; ++w) a += red[w][k][c];
         s[c] = a;
       }
@@ -534,48 +668,15 @@ __global__ void __launch_bounds__(TW * TH)
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) frontier[tile] = (int)rank_of[(uint32_t)pairs[top]];
+  if (threadIdx.x == 0) frontier[gt] = (int)rank_of[(uint32_t)pairs[top]];
 }
 
-__global__ void __launch_bounds__(256)
-    k_preprocess_bwd(const float *__restrict__ P, int64_t n, int64_t stride, int deg,
-                     CamD cam, int TW, int TH, int tiles_x,
-                     const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
-                     const uint32_t *__restrict__ rank_of, const int *__restrict__ frontier,
-                     const float4 *__restrict__ partial, float *__restrict__ grad,
-                     int64_t gstride, int accumulate, float *__restrict__ grad2d) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int R = 11 + 3 * (deg + 1) * (deg + 1);
-  Geo g;
-  load_geo(P, stride, i, cam, g);
-  if (g.culled || count[i] == 0) {
-    if (grad2d)
-      for (int c = 0; c < 10; ++c) grad2d[c * n + i] = 0.0f;
-    if (!accumulate)
-      for (int r = 0; r < R; ++r) grad[r * gstride + i] = 0.0f;
-    return;
-  }
-  // Sum this Gaussian's per-tile partials in emission (row-major) order.
-  const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
-  const int wc = tx1 - tx0 + 1;
-  const uint32_t base = pair_off[i], cnt = count[i];
-  const int rank = (int)rank_of[i];
-  float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (uint32_t r = 0; r < cnt; ++r) {
-    const int t = (ty0 + (int)r / wc) * tiles_x + tx0 + (int)r % wc;
-    if (frontier[t] < rank) continue;  // the tile never reached this Gaussian
-    const float4 p0 = partial[3 * (int64_t)(base + r)];
-    const float4 p1 = partial[3 * (int64_t)(base + r) + 1];
-    const float4 p2 = partial[3 * (int64_t)(base + r) + 2];
-    s[0] += p0.x; s[1] += p0.y; s[2] += p0.z; s[3] += p0.w;
-    s[4] += p1.x; s[5] += p1.y; s[6] += p1.z; s[7] += p1.w;
-    s[8] += p2.x; s[9] += p2.y;
-  }
-  (void)ty1;
-  if (grad2d)
-    for (int c = 0; c < 10; ++c) grad2d[c * n + i] = s[c];
-
+// Chain the ten screen-space gradient terms s[] of one (view, Gaussian)
+// record to the raw parameters: out[0..10] for mean, log-scale, quaternion
+// and opacity logit; Yb[k] * graw[c] for SH coefficient k of channel c.
+__device__ inline void param_grads(const float *__restrict__ P, int64_t stride, int64_t i,
+                                   int deg, const Geo &g, const CamD &cam, const float s[10],
+                                   double out[11], double Yb[16], double graw[3]) {
   const double gu = s[0], gv = s[1], gQ00 = s[2], gQ01 = s[3], gQ11 = s[4];
   const double go = s[5], gz_depth = s[9];
   // conic Q = Sigma2^-1 -> Sigma2 entries a, b, c
@@ -643,41 +744,110 @@ __global__ void __launch_bounds__(256)
   for (int k = 0; k < 4; ++k) gq[k] = (gqn[k] - g.qn[k] * dq) / g.qnorm;
   const double glogit = go * g.o * (1.0 - g.o);
   // colour
-  double dir[3], dn, Yb[16], raw[3];
+  double dir[3], dn, raw[3];
   color_raw(P, stride, i, deg, g, cam, dir, dn, Yb, raw);
-  double graw[3];
   for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > 0.0 ? (double)s[6 + ch] : 0.0;
   const int K = (deg + 1) * (deg + 1);
   if (deg > 0) {
-    double GY[16][3];
-    sh_grad(deg, dir[0], dir[1], dir[2], GY);
-    double gd[3] = {0, 0, 0};
+    double f[16];
+    f[0] = 0.0;
     for (int k = 1; k < K; ++k) {
-      double f = 0.0;
-      for (int ch = 0; ch < 3; ++ch) f += (double)P[(11 + 3 * k + ch) * stride + i] * graw[ch];
-      gd[0] += GY[k][0] * f;
-      gd[1] += GY[k][1] * f;
-      gd[2] += GY[k][2] * f;
+      double a = 0.0;
+      for (int ch = 0; ch < 3; ++ch) a += (double)P[(11 + 3 * k + ch) * stride + i] * graw[ch];
+      f[k] = a;
     }
+    double gd[3];
+    sh_grad_dot(deg, dir[0], dir[1], dir[2], f, gd);
     const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
     for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) / dn;
   }
-  double out[11];
   out[0] = gmu[0]; out[1] = gmu[1]; out[2] = gmu[2];
   out[3] = gls[0]; out[4] = gls[1]; out[5] = gls[2];
   out[6] = gq[0]; out[7] = gq[1]; out[8] = gq[2]; out[9] = gq[3];
   out[10] = glogit;
-  if (accumulate) {
-    for (int r = 0; r < 11; ++r) grad[r * gstride + i] += (float)out[r];
-    for (int k = 0; k < K; ++k)
-      for (int ch = 0; ch < 3; ++ch)
-        grad[(11 + 3 * k + ch) * gstride + i] += (float)(Yb[k] * graw[ch]);
-  } else {
-    for (int r = 0; r < 11; ++r) grad[r * gstride + i] = (float)out[r];
-    for (int k = 0; k < K; ++k)
-      for (int ch = 0; ch < 3; ++ch)
-        grad[(11 + 3 * k + ch) * gstride + i] = (float)(Yb[k] * graw[ch]);
+}
+
+// Per record (view v, Gaussian g) with a non-empty tile rect: the sum of its
+// per-tile partials in emission order (only tiles whose backward reached it),
+// written as ten planes s2d[c][r].  Integer box from the packed record.
+__global__ void __launch_bounds__(256)
+    k_sum_partials(int64_t nr, int TW, int TH, int tiles_x, int tiles_per_view, int64_t n,
+                   const float4 *__restrict__ recC, const uint32_t *__restrict__ count,
+                   const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
+                   const int *__restrict__ frontier, const float4 *__restrict__ partial,
+                   float *__restrict__ s2d) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nr) return;
+  const uint32_t cnt = count[r];
+  float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (cnt > 0) {
+    const float4 C = recC[r];
+    const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+    const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
+    const int ty0 = (int)(by & 0xFFFF) / TH;
+    const int wc = tx1 - tx0 + 1;
+    const int tile_base = (int)(r / n) * tiles_per_view;
+    const uint32_t base = pair_off[r];
+    const int rank = (int)rank_of[r];
+    for (uint32_t k = 0; k < cnt; ++k) {
+      const int t = tile_base + (ty0 + (int)k / wc) * tiles_x + tx0 + (int)k % wc;
+      if (frontier[t] < rank) continue;
+      const float4 p0 = partial[3 * (int64_t)(base + k)];
+      const float4 p1 = partial[3 * (int64_t)(base + k) + 1];
+      const float4 p2 = partial[3 * (int64_t)(base + k) + 2];
+      s[0] += p0.x; s[1] += p0.y; s[2] += p0.z; s[3] += p0.w;
+      s[4] += p1.x; s[5] += p1.y; s[6] += p1.z; s[7] += p1.w;
+      s[8] += p2.x; s[9] += p2.y;
+    }
   }
+#pragma unroll
+  for (int c = 0; c < 10; ++c) s2d[c * nr + r] = s[c];
+}
+
+// Projection backward over all views: one thread per Gaussian; record
+// r = v n + g of every view that drew it contributes, in view order, with
+// float32 accumulation (the same additions as one single-view backward per
+// view accumulating into the gradient buffer).  The eleven geometry rows
+// accumulate in registers; the SH rows are added in place view by view.
+template <int DEG>
+__global__ void __launch_bounds__(256)
+    k_preprocess_bwd(const float *__restrict__ P, int64_t n, int64_t stride,
+                     const CamD *__restrict__ cams, int V, const uint32_t *__restrict__ count,
+                     const float *__restrict__ s2d, float *__restrict__ grad, int64_t gstride,
+                     int accumulate) {
+  constexpr int K = (DEG + 1) * (DEG + 1), R = 11 + 3 * K;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t nr = n * V;
+  float acc[11];
+#pragma unroll
+  for (int r = 0; r < 11; ++r) acc[r] = accumulate ? grad[r * gstride + i] : 0.0f;
+  bool sh_written = accumulate != 0;
+  for (int v = 0; v < V; ++v) {
+    const int64_t rr = v * n + i;
+    if (count[rr] == 0) continue;
+    const CamD &cam = cams[v];
+    Geo g;
+    load_geo(P, stride, i, cam, g);
+    float s[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) s[c] = s2d[c * nr + rr];
+    double out[11], Yb[16], graw[3];
+    param_grads(P, stride, i, DEG, g, cam, s, out, Yb, graw);
+#pragma unroll
+    for (int r = 0; r < 11; ++r) acc[r] += (float)out[r];
+    for (int k = 0; k < K; ++k)
+      for (int ch = 0; ch < 3; ++ch) {
+        const int64_t idx = (int64_t)(11 + 3 * k + ch) * gstride + i;
+        const float val = (float)(Yb[k] * graw[ch]);
+        grad[idx] = sh_written ? grad[idx] + val : 0.0f + val;
+      }
+    sh_written = true;
+  }
+#pragma unroll
+  for (int r = 0; r < 11; ++r) grad[r * gstride + i] = acc[r];
+  if (!sh_written)
+    for (int r = 11; r < R; ++r) grad[r * gstride + i] = 0.0f;
 }
 
 // ---- export helpers (tests) ----
@@ -727,77 +897,116 @@ __global__ void k_copy_u32_as_i32(const uint32_t *__restrict__ a, int64_t n, int
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 void launch_fwd_t(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *T) {
-  const int nt = s->tiles_x * s->tiles_y;
+  const int nt = s->tiles_x * s->tiles_y * s->V;
   const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, s->pairs.p,
-                     s->ranges.p, s->rec.p, s->n, s->W, s->H, s->tiles_x, nt, s->bg[0],
-                     s->bg[1], s->bg[2], rgb, depth, T, s->T_final.p, s->last.p);
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
+                     s->pairs.p, s->ranges.p, s->rec.p, s->n * s->V, s->W, s->H, s->tiles_x, nt,
+                     s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], rgb, depth, T,
+                     s->T_final.p, s->last.p);
   DCGS_LAUNCH_CHECK();
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const float *dl_ddepth) {
-  const int nt = s->tiles_x * s->tiles_y;
+  const int nt = s->tiles_x * s->tiles_y * s->V;
   const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
-  hipLaunchKernelGGL((k_raster_bwd<TW, TH>), dim3(grid), dim3(TW * TH), 0, st, s->pairs.p,
-                     s->ranges.p, s->rec.p, s->n, s->W, s->H, s->tiles_x, nt, s->bg[0],
-                     s->bg[1], s->bg[2], s->T_final.p, s->last.p, dl_drgb, dl_ddepth,
-                     s->pair_off.p, s->rank_of.p, s->partial.p, s->frontier.p);
+  hipLaunchKernelGGL((k_raster_bwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
+                     s->pairs.p, s->ranges.p, s->rec.p, s->n * s->V, s->W, s->H, s->tiles_x, nt,
+                     s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], s->T_final.p,
+                     s->last.p, dl_drgb, dl_ddepth, s->pair_off.p, s->rank_of.p, s->partial.p,
+                     s->frontier.p);
   DCGS_LAUNCH_CHECK();
+}
+
+// Raster shapes: tile width x height and pixels per lane.
+#define DCGS_RASTER_SHAPES(X) \
+  X(16, 16, 1) X(16, 16, 2) X(16, 16, 4) X(8, 8, 1) X(32, 16, 2) X(32, 16, 4) X(32, 16, 8)
+
+void launch_fwd(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *T) {
+#define X(a, b, c)                                                   \
+  if (s->TW == a && s->TH == b && s->ppt == c) {                     \
+    launch_fwd_t<a, b, c>(s, st, rgb, depth, T);                     \
+    return;                                                          \
+  }
+  DCGS_RASTER_SHAPES(X)
+#undef X
+  throw Error{DCGS_E_INVALID, "unsupported raster shape"};
+}
+
+void launch_bwd(dcgs_state *s, hipStream_t st, const float *dl_drgb, const float *dl_ddepth) {
+#define X(a, b, c)                                                   \
+  if (s->TW == a && s->TH == b && s->ppt == c) {                     \
+    launch_bwd_t<a, b, c>(s, st, dl_drgb, dl_ddepth);                \
+    return;                                                          \
+  }
+  DCGS_RASTER_SHAPES(X)
+#undef X
+  throw Error{DCGS_E_INVALID, "unsupported raster shape"};
 }
 
 }  // namespace
 
 void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
-                    hipStream_t st, float *rgb, float *depth, float *T) {
-  const CamD cam = make_cam(s->cam);
-  const int nt = s->tiles_x * s->tiles_y;
+                    const uint16_t *gmask, int mask_shift, hipStream_t st, float *rgb,
+                    float *depth, float *T) {
+  dcgs_ctx *ctx = s->ctx;
+  const int V = s->V;
+  const int tpv = s->tiles_x * s->tiles_y;
+  const int nt = tpv * V;
+  const int64_t nr = n * V;
   const int64_t HW = (int64_t)s->W * s->H;
   s->n = n;
-  float4 *rec = s->rec.need(3 * (size_t)n + 1);
-  uint32_t *zkey = s->zkey.need(n + 1), *cnt = s->count.need(n + 1);
-  uint32_t *order = s->order.need(n + 1), *sortkey = s->key_tmp.need(2 * (size_t)n + 2);
-  uint32_t *vtmp = s->val_tmp.need(n + 1);
-  s->rank_of.need(n + 1);
-  s->pair_off.need(n + 1);
-  uint32_t *scan = s->scan.need(n + 2);
+  // cameras -> device (the pinned staging copy is complete: every forward
+  // synchronises its stream before returning)
+  if (!s->cam_pinned) DCGS_HIP(hipHostMalloc(&s->cam_pinned, kMaxViews * sizeof(CamD), hipHostMallocDefault));
+  CamD *hc = (CamD *)s->cam_pinned;
+  for (int v = 0; v < V; ++v) hc[v] = make_cam(s->cams[v]);
+  CamD *dc = (CamD *)s->cam_dev.need(kMaxViews * sizeof(CamD));
+  DCGS_HIP(hipMemcpyAsync(dc, hc, V * sizeof(CamD), hipMemcpyHostToDevice, st));
+  float4 *rec = s->rec.need(3 * (size_t)nr + 1);
+  uint32_t *zkey = s->zkey.need(nr + 1), *cnt = s->count.need(nr + 1);
+  uint32_t *order = s->order.need(nr + 1), *sortkey = s->key_tmp.need(2 * (size_t)nr + 2);
+  uint32_t *vtmp = s->val_tmp.need(nr + 1);
+  s->rank_of.need(nr + 1);
+  s->pair_off.need(nr + 1);
+  uint32_t *scan = s->scan.need(nr + 2);
   s->ranges.need(nt + 1);
   s->frontier.need(nt + 1);
-  s->T_final.need(HW + 1);
-  s->last.need(HW + 1);
-  dcgs_ctx *ctx = s->ctx;
+  s->T_final.need(V * HW + 1);
+  s->last.need(V * HW + 1);
   if (n > 0) {
     StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
     hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n, 256)), dim3(256), 0, st, params, n,
-                       stride, s->sh_degree, cam, s->TW, s->TH, rec, zkey, sortkey, order, cnt);
+                       stride, s->sh_degree, dc, V, gmask, mask_shift, s->TW, s->TH, rec, zkey,
+                       sortkey, order, cnt);
     DCGS_LAUNCH_CHECK();
   }
-  if (n > 0) {
+  if (nr > 0) {
     StageTimer ts(ctx, DCGS_STAGE_DEPTH_SORT, st);
-    // depth order of the Gaussians: stable sort of the float32 depth bits
-    sort_u32_pairs(sortkey, order, sortkey + n + 1, vtmp, n, 32, s->hist, st);
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(n, 256)), dim3(256), 0, st, order, n,
+    // depth order of all records: stable sort of the float32 depth bits
+    sort_u32_pairs(sortkey, order, sortkey + nr + 1, vtmp, nr, 32, s->hist, st);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, nr,
                        s->rank_of.p);
     DCGS_LAUNCH_CHECK();
   }
-  uint32_t *part = s->ctx->scan_part.need(scan_part_size(n) + 2);
+  uint32_t *part = s->ctx->scan_part.need(scan_part_size(nr) + 2);
   {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-    scan_u32(cnt, order, scan, n, part, st);
+    scan_u32(cnt, order, scan, nr, part, st);
   }
   uint32_t total = 0;
-  DCGS_HIP(hipMemcpyAsync(&total, scan + n, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  DCGS_HIP(hipMemcpyAsync(&total, scan + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   DCGS_HIP(hipStreamSynchronize(st));
   s->n_pairs = total;
   uint64_t *pairs = s->pairs.need((size_t)total + 1);
   uint64_t *ptmp = s->pairs_tmp.need((size_t)total + 1);
   s->partial.need(3 * (size_t)total + 3);
-  if (n > 0) {
+  if (nr > 0) {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(n, 256)), dim3(256), 0, st, order, cnt, scan,
-                       rec + 2 * n, n, s->TW, s->TH, s->tiles_x, pairs, s->pair_off.p);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, cnt, scan,
+                       rec + 2 * nr, nr, n, s->TW, s->TH, s->tiles_x, tpv, pairs, s->pair_off.p);
     DCGS_LAUNCH_CHECK();
   }
   int tile_bits = 0;
@@ -813,27 +1022,36 @@ void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t strid
     DCGS_LAUNCH_CHECK();
   }
   StageTimer tf(ctx, DCGS_STAGE_RASTER_FWD, st);
-  if (s->TW == 16 && s->TH == 16) launch_fwd_t<16, 16>(s, st, rgb, depth, T);
-  else if (s->TW == 8 && s->TH == 8) launch_fwd_t<8, 8>(s, st, rgb, depth, T);
-  else launch_fwd_t<32, 16>(s, st, rgb, depth, T);
+  launch_fwd(s, st, rgb, depth, T);
 }
 
 void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
                      const float *dl_drgb, const float *dl_ddepth, float *grad,
                      int64_t grad_stride, int accumulate, float *grad2d, hipStream_t st) {
-  const CamD cam = make_cam(s->cam);
   {
     StageTimer tb(s->ctx, DCGS_STAGE_RASTER_BWD, st);
-    if (s->TW == 16 && s->TH == 16) launch_bwd_t<16, 16>(s, st, dl_drgb, dl_ddepth);
-    else if (s->TW == 8 && s->TH == 8) launch_bwd_t<8, 8>(s, st, dl_drgb, dl_ddepth);
-    else launch_bwd_t<32, 16>(s, st, dl_drgb, dl_ddepth);
+    launch_bwd(s, st, dl_drgb, dl_ddepth);
   }
   if (n > 0) {
     StageTimer tp(s->ctx, DCGS_STAGE_PREPROCESS_BWD, st);
-    hipLaunchKernelGGL(k_preprocess_bwd, dim3(blocks_for(n, 256)), dim3(256), 0, st, params,
-                       n, stride, s->sh_degree, cam, s->TW, s->TH, s->tiles_x, s->count.p,
-                       s->pair_off.p, s->rank_of.p, s->frontier.p, s->partial.p, grad,
-                       grad_stride, accumulate, grad2d);
+    const CamD *dc = (const CamD *)s->cam_dev.p;
+    const int tpv = s->tiles_x * s->tiles_y;
+    const int64_t nr = n * s->V;
+    float *s2d = grad2d ? grad2d : s->grad2d.need(10 * (size_t)nr + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, s->TW,
+                       s->TH, s->tiles_x, tpv, n, s->rec.p + 2 * nr, s->count.p, s->pair_off.p,
+                       s->rank_of.p, s->frontier.p, s->partial.p, s2d);
+    DCGS_LAUNCH_CHECK();
+#define DCGS_PBWD(D)                                                                         \
+  hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks_for(n, 256)), dim3(256), 0, st, params, \
+                     n, stride, dc, s->V, s->count.p, s2d, grad, grad_stride, accumulate)
+    switch (s->sh_degree) {
+      case 0: DCGS_PBWD(0); break;
+      case 1: DCGS_PBWD(1); break;
+      case 2: DCGS_PBWD(2); break;
+      default: DCGS_PBWD(3); break;
+    }
+#undef DCGS_PBWD
     DCGS_LAUNCH_CHECK();
   }
 }
@@ -841,8 +1059,8 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
 void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values, int32_t *ranges,
                   int32_t *counts, float *records, int32_t *box, int32_t *last,
                   hipStream_t st) {
-  const int64_t P = s->n_pairs, n = s->n;
-  const int nt = s->tiles_x * s->tiles_y;
+  const int64_t P = s->n_pairs, nr = s->n * s->V;
+  const int nt = s->tiles_x * s->tiles_y * s->V;
   if ((keys || values) && P > 0) {
     hipLaunchKernelGGL(k_export_keys, dim3(blocks_for(P, 256)), dim3(256), 0, st, s->pairs.p,
                        P, s->zkey.p, keys, values);
@@ -850,18 +1068,18 @@ void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values, int32_t 
   }
   if (ranges && nt > 0)
     DCGS_HIP(hipMemcpyAsync(ranges, s->ranges.p, nt * sizeof(int2), hipMemcpyDeviceToDevice, st));
-  if (counts && n > 0) {
-    hipLaunchKernelGGL(k_copy_u32_as_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                       s->count.p, n, counts);
+  if (counts && nr > 0) {
+    hipLaunchKernelGGL(k_copy_u32_as_i32, dim3(blocks_for(nr, 256)), dim3(256), 0, st,
+                       s->count.p, nr, counts);
     DCGS_LAUNCH_CHECK();
   }
-  if ((records || box) && n > 0) {
-    hipLaunchKernelGGL(k_export_rec, dim3(blocks_for(n, 256)), dim3(256), 0, st, s->rec.p,
-                       s->count.p, n, records, box);
+  if ((records || box) && nr > 0) {
+    hipLaunchKernelGGL(k_export_rec, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->rec.p,
+                       s->count.p, nr, records, box);
     DCGS_LAUNCH_CHECK();
   }
   if (last)
-    DCGS_HIP(hipMemcpyAsync(last, s->last.p, (size_t)s->W * s->H * sizeof(int),
+    DCGS_HIP(hipMemcpyAsync(last, s->last.p, (size_t)s->V * s->W * s->H * sizeof(int),
                             hipMemcpyDeviceToDevice, st));
 }
 

@@ -70,9 +70,8 @@ constexpr int kLossBlocks = 1024;
 
 __global__ void __launch_bounds__(256)
     k_loss(const float *__restrict__ x, const float *__restrict__ y, int64_t count,
-           float *__restrict__ dl, float *__restrict__ part) {
+           float inv, float *__restrict__ dl, float *__restrict__ part) {
   __shared__ float s1[256], s2[256];
-  const float inv = (float)(1.0 / (double)count);
   float a1 = 0.0f, a2 = 0.0f;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -98,15 +97,28 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void k_loss_final(const float *__restrict__ part, int nb, double *__restrict__ stats) {
-  if (threadIdx.x != 0) return;
+__global__ void __launch_bounds__(256)
+    k_loss_final(const float *__restrict__ part, int nb, double *__restrict__ stats) {
+  __shared__ double s1[256], s2[256];
   double a = 0.0, b = 0.0;
-  for (int k = 0; k < nb; ++k) {
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) {
     a += part[2 * k];
     b += part[2 * k + 1];
   }
-  stats[0] = a;
-  stats[1] = b;
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) {
+      s1[threadIdx.x] += s1[threadIdx.x + h];
+      s2[threadIdx.x] += s2[threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    stats[0] = s1[0];
+    stats[1] = s2[0];
+  }
 }
 
 }  // namespace
@@ -135,11 +147,12 @@ void launch_adam(float *params, float *m, float *v, int32_t *step, int R, const 
   DCGS_LAUNCH_CHECK();
 }
 
-void launch_loss_l1(const float *rgb, const float *target, int64_t count, float *dl,
-                    double *stats, float *part, hipStream_t st) {
-  hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, rgb, target, count, dl, part);
+void launch_loss_l1(const float *rgb, const float *target, int64_t count, double norm,
+                    float *dl, double *stats, float *part, hipStream_t st) {
+  hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, st, rgb, target, count,
+                     (float)(1.0 / norm), dl, part);
   DCGS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, part, kLossBlocks, stats);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, kLossBlocks, stats);
   DCGS_LAUNCH_CHECK();
 }
 

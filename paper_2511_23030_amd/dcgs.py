@@ -83,9 +83,10 @@ SIGNATURES = {
     "dcgs_compact": (INT, [P, P, P, INT, P, I64, P, P, I64, C.POINTER(I64), P]),
     "dcgs_state_create": (INT, [P, C.POINTER(P)]),
     "dcgs_state_destroy": (None, [P]),
-    "dcgs_render_fwd": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
+    "dcgs_render_fwd": (INT, [P, P, P, I64, I64, INT, P, INT, P, INT, P, INT, INT, INT, P, P, P,
+                              P]),
     "dcgs_render_bwd": (INT, [P, P, P, I64, I64, P, P, P, I64, INT, P, P]),
-    "dcgs_loss_l1": (INT, [P, P, P, I64, P, P, P]),
+    "dcgs_loss_l1": (INT, [P, P, P, I64, DBL, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
     "dcgs_profile_enable": (INT, [P, INT]),
     "dcgs_profile_read": (INT, [P, P, P, INT]),
@@ -195,12 +196,17 @@ class Context:
         self.check(lib().dcgs_profile_read(self.h, ms.ctypes.data, calls.ctypes.data, n))
         return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(self.STAGES)}
 
-    def loss_l1(self, rgb, target, dl_out=None, stats=None, stream=None):
+    def loss_l1(self, rgb, target, dl_out=None, stats=None, stream=None, norm=None):
+        """L1 loss gradient sign(rgb - target) / norm (norm defaults to the
+        element count of one image: 3HW for rgb [.., 3, H, W])."""
         import torch
         dl = torch.empty_like(rgb) if dl_out is None else dl_out
         st = torch.empty(2, dtype=torch.float64, device=rgb.device) if stats is None else stats
-        self.check(lib().dcgs_loss_l1(self.h, ptr(rgb), ptr(target), rgb.numel(), ptr(dl),
-                                      ptr(st), stream_handle(stream)))
+        if norm is None:
+            norm = float(rgb.shape[-1] * rgb.shape[-2] * rgb.shape[-3]) if rgb.dim() >= 3 \
+                else float(rgb.numel())
+        self.check(lib().dcgs_loss_l1(self.h, ptr(rgb), ptr(target), rgb.numel(), float(norm),
+                                      ptr(dl), ptr(st), stream_handle(stream)))
         return dl, st
 
 
@@ -305,18 +311,28 @@ class RenderState:
         except Exception:
             pass
 
-    def forward(self, params, n: int, sh_degree: int, cam: dict, bg, tile=(16, 16),
-                rgb=None, depth=None, T=None, stream=None):
+    def forward(self, params, n: int, sh_degree: int, cam, bg, tile=(16, 16),
+                rgb=None, depth=None, T=None, stream=None, ppt: int = 0, gmask=None,
+                mask_shift: int = 0):
+        """Render one camera (dict) or a window of cameras (list of dicts).
+        Outputs are [3, H, W] / [H, W] for one camera and [V, 3, H, W] /
+        [V, H, W] for a list.  gmask: device int16 [n] view bits or None."""
         import torch
-        H, W = cam["height"], cam["width"]
+        cams = cam if isinstance(cam, (list, tuple)) else [cam]
+        V = len(cams)
+        H, W = cams[0]["height"], cams[0]["width"]
         dev = params.device
-        rgb = torch.empty(3, H, W, dtype=torch.float32, device=dev) if rgb is None else rgb
-        depth = torch.empty(H, W, dtype=torch.float32, device=dev) if depth is None else depth
+        lead = (V,) if isinstance(cam, (list, tuple)) else ()
+        rgb = torch.empty(*lead, 3, H, W, dtype=torch.float32, device=dev) if rgb is None else rgb
+        depth = torch.empty(*lead, H, W, dtype=torch.float32, device=dev) if depth is None else depth
         bgv = (C.c_float * 3)(*[float(x) for x in bg])
-        camc = Camera.of(cam)
+        arr = (Camera * V)(*[Camera.of(c) for c in cams])
         self.ctx.check(lib().dcgs_render_fwd(self.ctx.h, self.h, ptr(params), n, params.stride(0),
-                                             sh_degree, C.byref(camc), bgv, tile[0], tile[1],
-                                             ptr(rgb), ptr(depth), ptr(T), stream_handle(stream)))
+                                             sh_degree, ptr(gmask), mask_shift, C.cast(arr, P),
+                                             V, bgv,
+                                             tile[0], tile[1], ppt, ptr(rgb), ptr(depth), ptr(T),
+                                             stream_handle(stream)))
+        self.n_views = V
         return rgb, depth
 
     def backward(self, params, n: int, dl_drgb, dl_ddepth=None, grad=None, accumulate=False,
@@ -337,17 +353,19 @@ class RenderState:
 
     def export(self, device, H: int, W: int, stream=None) -> dict:
         """Copy the last forward's keys, values, ranges, counts, records, boxes
-        and per-pixel last positions to torch tensors."""
+        and per-pixel last positions to torch tensors (records indexed
+        v * n + i over the views of the last forward)."""
         import torch
         inf = self.info()
-        P_, n, nt = inf["n_pairs"], inf["n"], inf["tiles_x"] * inf["tiles_y"]
+        V = getattr(self, "n_views", 1)
+        P_, n, nt = inf["n_pairs"], inf["n"] * V, inf["tiles_x"] * inf["tiles_y"] * V
         out = dict(keys=torch.empty(max(P_, 1), dtype=torch.int64, device=device),
                    values=torch.empty(max(P_, 1), dtype=torch.int32, device=device),
                    ranges=torch.empty(nt, 2, dtype=torch.int32, device=device),
                    counts=torch.empty(max(n, 1), dtype=torch.int32, device=device),
                    records=torch.empty(10, max(n, 1), dtype=torch.float32, device=device),
                    box=torch.empty(4, max(n, 1), dtype=torch.int32, device=device),
-                   last=torch.empty(H, W, dtype=torch.int32, device=device))
+                   last=torch.empty(V, H, W, dtype=torch.int32, device=device))
         self.ctx.check(lib().dcgs_state_export(self.h, ptr(out["keys"]), ptr(out["values"]),
                                                ptr(out["ranges"]), ptr(out["counts"]),
                                                ptr(out["records"]), ptr(out["box"]),
@@ -357,4 +375,6 @@ class RenderState:
         out["counts"] = out["counts"][:n]
         out["records"] = out["records"][:, :n]
         out["box"] = out["box"][:, :n]
+        if V == 1:
+            out["last"] = out["last"][0]
         return out

@@ -19,9 +19,10 @@ DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4)
 class MappingLoop:
     def __init__(self, ctx: D.Context, pool: D.Pool, sh_degree: int, chunk_size: float,
                  capacity: int, width: int, height: int, tile=(16, 16), bg=(0.0, 0.0, 0.0),
-                 lr=DEFAULT_LR):
+                 lr=DEFAULT_LR, ppt: int = 0):
         self.ctx, self.pool = ctx, pool
         self.deg, self.s, self.tile, self.bg = sh_degree, float(chunk_size), tuple(tile), bg
+        self.ppt = ppt
         self.R = 11 + 3 * (sh_degree + 1) ** 2
         dev = torch.device("cuda", ctx.device)
         self.cap = int(capacity)
@@ -54,13 +55,86 @@ class MappingLoop:
         k = int(self.sel_count.item())
         return self.sel_ids[:k].cpu().numpy().view(np.uint64)
 
+    def select_window(self, cams: list) -> tuple[np.ndarray, np.ndarray]:
+        """Union of the chunks the views see (ascending ids) and each chunk's
+        view mask (host copies; one sync)."""
+        addr, n = self.pool.device_ids()
+        if n > self.sel_ids.numel():
+            dev = self.sel_ids.device
+            self.sel_ids = torch.empty(n, dtype=torch.int64, device=dev)
+            self.sel_mask = torch.empty(n, dtype=torch.int16, device=dev)
+        arr = (D.Camera * len(cams))(*[D.Camera.of(c) for c in cams])
+        self.ctx.check(D.lib().dcgs_select_chunks(
+            self.ctx.h, C.cast(arr, C.c_void_p), len(cams), addr, n, self.s, D.ptr(self.sel_ids),
+            D.ptr(self.sel_mask), D.ptr(self.sel_count), D.stream_handle()))
+        k = int(self.sel_count.item())
+        return (self.sel_ids[:k].cpu().numpy().view(np.uint64),
+                self.sel_mask[:k].cpu().numpy().view(np.uint16))
+
+    def _window_buffers(self, V: int):
+        if getattr(self, "_wv", 0) != V:
+            H, W = self.rgb.shape[1], self.rgb.shape[2]
+            dev = self.rgb.device
+            self.rgb_v = torch.empty(V, 3, H, W, dtype=torch.float32, device=dev)
+            self.depth_v = torch.empty(V, H, W, dtype=torch.float32, device=dev)
+            self.dl_v = torch.empty(V, 3, H, W, dtype=torch.float32, device=dev)
+            self.gmask = torch.empty(self.cap, dtype=torch.int16, device=dev)
+            self._wv = V
+
+    def window_step(self, cams: list, targets: torch.Tensor) -> dict:
+        """One batched mapping iteration over a window of keyframes: one
+        selection, one compaction of the union with per-Gaussian view masks,
+        one forward and one backward launch sequence for all views, the loss
+        summed over views, one Adam step."""
+        V = len(cams)
+        self._window_buffers(V)
+        ids, masks = self.select_window(cams)
+        loaded, evicted = self.pool.require(ids, now=self.iter)
+        n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
+        self.state.forward(self.params, n, self.deg, list(cams), self.bg, self.tile, self.rgb_v,
+                           self.depth_v, ppt=self.ppt, gmask=self.gmask)
+        H, W = self.rgb.shape[1], self.rgb.shape[2]
+        self.ctx.loss_l1(self.rgb_v, targets, self.dl_v, self.stats, norm=3.0 * H * W)
+        self.state.backward(self.params, n, self.dl_v, None, self.grad, accumulate=False)
+        self.pool.adam_step(self.src, self.grad, n, self.adam)
+        self.iter += 1
+        self.last = dict(n_active=n, n_chunks=int(ids.size), loaded=loaded, evicted=evicted,
+                         views=V)
+        return self.last
+
+    def window_step_sequential(self, cams: list, targets: torch.Tensor) -> dict:
+        """The same update as window_step computed as one single-view forward
+        and backward per view, accumulating gradients, then one Adam step
+        (the per-view comparator of the batched path)."""
+        V = len(cams)
+        self._window_buffers(V)
+        ids, masks = self.select_window(cams)
+        loaded, evicted = self.pool.require(ids, now=self.iter)
+        n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
+        H, W = self.rgb.shape[1], self.rgb.shape[2]
+        stats = torch.zeros(2, dtype=torch.float64, device=self.rgb.device)
+        for v in range(V):
+            self.state.forward(self.params, n, self.deg, cams[v], self.bg, self.tile,
+                               self.rgb_v[v], self.depth_v[v], ppt=self.ppt, gmask=self.gmask,
+                               mask_shift=v)
+            self.ctx.loss_l1(self.rgb_v[v], targets[v], self.dl_v[v], self.stats)
+            stats += self.stats
+            self.state.backward(self.params, n, self.dl_v[v], None, self.grad, accumulate=v > 0)
+        self.stats.copy_(stats)
+        self.pool.adam_step(self.src, self.grad, n, self.adam)
+        self.iter += 1
+        self.last = dict(n_active=n, n_chunks=int(ids.size), loaded=loaded, evicted=evicted,
+                         views=V)
+        return self.last
+
     def step(self, cam: dict, target: torch.Tensor, ids: np.ndarray | None = None) -> dict:
         """One plain mapping iteration for one keyframe; returns host stats."""
         if ids is None:
             ids = self.select(cam)
         loaded, evicted = self.pool.require(ids, now=self.iter)
         n = self.pool.compact(ids, self.params, self.src)
-        self.state.forward(self.params, n, self.deg, cam, self.bg, self.tile, self.rgb, self.depth)
+        self.state.forward(self.params, n, self.deg, cam, self.bg, self.tile, self.rgb, self.depth,
+                           ppt=self.ppt)
         self.ctx.loss_l1(self.rgb, target, self.dl, self.stats)
         self.state.backward(self.params, n, self.dl, None, self.grad, accumulate=False)
         self.pool.adam_step(self.src, self.grad, n, self.adam)

@@ -12,13 +12,16 @@ MARGIN_T = 1e-4         # decision may differ between FP32 and FP64
 MARGIN_CLAMP = 1e-5
 
 
-def gpu_render(ctx, params, deg, cam, bg, tile=(16, 16), dl=None, dld=None):
+SHAPES = [(16, 16, 1), (16, 16, 2), (16, 16, 4), (8, 8, 1), (32, 16, 2), (32, 16, 4), (32, 16, 8)]
+
+
+def gpu_render(ctx, params, deg, cam, bg, tile=(16, 16), dl=None, dld=None, ppt=0):
     H, W = cam["height"], cam["width"]
     Pt = torch.from_numpy(np.ascontiguousarray(params, np.float32)).cuda()
     n = Pt.shape[1]
     st = D.RenderState(ctx)
     T = torch.empty(H, W, dtype=torch.float32, device="cuda")
-    rgb, depth = st.forward(Pt, n, deg, cam, bg, tile, T=T)
+    rgb, depth = st.forward(Pt, n, deg, cam, bg, tile, T=T, ppt=ppt)
     ex = st.export(Pt.device, H, W)
     out = dict(rgb=rgb.cpu().numpy(), depth=depth.cpu().numpy(), T=T.cpu().numpy(),
                **{k: v.cpu().numpy() for k, v in ex.items()}, n_pairs=st.info()["n_pairs"])

@@ -48,7 +48,7 @@ def test_null_arguments_are_rejected_without_touching_the_device(libpath):
     from paper_2511_23030_amd import dcgs
     L = dcgs.lib()
     assert L.dcgs_create(None, 0) == 1              # DCGS_E_INVALID
-    assert L.dcgs_render_fwd(None, None, None, 0, 0, 0, None, None, 16, 16,
+    assert L.dcgs_render_fwd(None, None, None, 0, 0, 0, None, 0, None, 1, None, 16, 16, 0,
                              None, None, None, None) == 1
     assert L.dcgs_adam_step(None, None, None, 0, 0, None, None) == 1
     assert L.dcgs_state_info(None, None, None, None, None) == 1

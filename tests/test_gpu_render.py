@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenegen
-from gpu_helpers import (IMG_TOL, assert_grad_close, flagged_pixels, gpu_render)
+from gpu_helpers import (IMG_TOL, SHAPES, assert_grad_close, flagged_pixels, gpu_render)
 from oracle import splat as osp
 
 pytestmark = pytest.mark.gpu
@@ -62,9 +62,9 @@ def test_image_parity_and_tile_independence(ctx, size):
     ok = ~flag
     ref_rgb = img.rgb.detach().numpy()
     imgs = []
-    for tile in TILES:
-        print(f"case image size={size} tile={tile}", flush=True)
-        g = gpu_render(ctx, sc["params"], 0, cam, bg, tile)
+    for shape in SHAPES:
+        print(f"case image size={size} shape={shape}", flush=True)
+        g = gpu_render(ctx, sc["params"], 0, cam, bg, shape[:2], ppt=shape[2])
         assert np.abs(g["rgb"] - ref_rgb)[:, ok].max() <= IMG_TOL
         assert np.abs(g["T"] - img.T.detach().numpy())[ok].max() <= IMG_TOL
         D = img.depth.detach().numpy()
@@ -77,8 +77,15 @@ def test_image_parity_and_tile_independence(ctx, size):
         assert (other == imgs[0]).all()          # bitwise: tile size never changes the image
 
 
-@pytest.mark.parametrize("deg,size,seed", [(0, (256, 192), 0), (3, (250, 190), 5)])
-def test_gradient_parity(ctx, deg, size, seed):
+@pytest.mark.parametrize("deg,size,seed,shape", [(0, (256, 192), 0, (16, 16, 2)),
+                                                 (3, (250, 190), 5, (16, 16, 2)),
+                                                 (0, (250, 190), 6, (16, 16, 1)),
+                                                 (0, (250, 190), 7, (16, 16, 4)),
+                                                 (0, (250, 190), 8, (8, 8, 1)),
+                                                 (3, (250, 190), 9, (32, 16, 4)),
+                                                 (0, (250, 190), 10, (32, 16, 8)),
+                                                 (0, (256, 192), 11, (32, 16, 2))])
+def test_gradient_parity(ctx, deg, size, seed, shape):
     sc = _scene(size, deg=deg, seed=seed)
     cam = sc["camera"]
     if deg:   # a rotated, offset camera so view directions vary
@@ -96,8 +103,8 @@ def test_gradient_parity(ctx, deg, size, seed):
     dl[:, flag] = 0.0
     dld[flag] = 0.0
     gr = osp.render_grad(rec, img, dl, dld)
-    print(f"case grad deg={deg} size={size}", flush=True)
-    g = gpu_render(ctx, sc["params"], deg, cam, bg, (16, 16), dl, dld)
+    print(f"case grad deg={deg} size={size} shape={shape}", flush=True)
+    g = gpu_render(ctx, sc["params"], deg, cam, bg, shape[:2], dl, dld, ppt=shape[2])
     vis = ~rec.culled
     assert vis.sum() > 1000
     colour_ok = vis & (rec.raw_rgb_margin > 1e-5)
