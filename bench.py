@@ -39,6 +39,15 @@ WORKLOADS = {
     # Small smoke-sized variant.
     "indoor-small": dict(n=200_000, deg=3, chunk=2.0, W=320, H=180, f=160.0, z_far=5.0,
                          frames=80, every=8),
+    # The driving corridor: 25M Gaussians held in the host store, a 4 km
+    # road with 90 degree turns, 30 m wide, 10 m facades, 50 m chunks,
+    # 1241x376 views (fx = fy = 718) from a forward camera moving 1 m per
+    # frame, keyframes every 2 frames, z_far = 350 m (2-3M active per view);
+    # the device holds at most 6M Gaussians, the rest is staged on demand.
+    "driving-25m": dict(n=25_000_000, deg=3, chunk=50.0, W=1241, H=376, f=718.0, z_far=350.0,
+                        frames=4000, every=2, budget=6_000_000, walk=True),
+    "driving-small": dict(n=1_000_000, deg=3, chunk=50.0, W=620, H=188, f=359.0, z_far=350.0,
+                          frames=4000, every=2, budget=300_000, walk=True),
 }
 
 
@@ -49,11 +58,19 @@ def log(msg):
 def make_workload(name: str) -> dict:
     import scenegen
     w = dict(WORKLOADS[name])
-    sc = scenegen.room_scene(w["n"], seed=10, sh_degree=w["deg"])
+    w.setdefault("budget", w["n"] + 1)
+    w.setdefault("walk", False)
+    if name.startswith("driving"):
+        path = scenegen.driving_path(20)
+        sc = scenegen.driving_scene(w["n"], seed=20, sh_degree=w["deg"], path=path)
+        cams = scenegen.driving_trajectory(path, w["frames"], width=w["W"], height=w["H"],
+                                           focal=w["f"], z_far=w["z_far"])
+    else:
+        sc = scenegen.room_scene(w["n"], seed=10, sh_degree=w["deg"])
+        cams = scenegen.room_trajectory(w["frames"], seed=11, width=w["W"], height=w["H"],
+                                        focal=w["f"], z_far=w["z_far"])
     w["true"] = sc["params"]
     w["start"] = scenegen.perturb(sc["params"], seed=12)
-    cams = scenegen.room_trajectory(w["frames"], seed=11, width=w["W"], height=w["H"],
-                                    focal=w["f"], z_far=w["z_far"])
     w["cams"] = cams[::w["every"]]
     return w
 
@@ -137,7 +154,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1, help="untimed windows per path")
     ap.add_argument("--window", type=int, default=16, help="keyframes per batched window")
     ap.add_argument("--workload", default="indoor-2m", choices=sorted(WORKLOADS))
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto", help="WxH, or auto (autotuner)")
     ap.add_argument("--ppt", type=int, default=0, help="pixels per lane (0: library default)")
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -155,7 +172,7 @@ def main():
     if not os.path.exists(D.LIB_PATH):
         from paper_2511_23030_amd import build as B
         B.build()
-    tw, th = (int(x) for x in args.tile.split("x"))
+    tw, th = (16, 16) if args.tile == "auto" else (int(x) for x in args.tile.split("x"))
     t_setup = time.perf_counter()
     w = make_workload(args.workload)
     log(f"workload {args.workload}: {w['n']} Gaussians, {len(w['cams'])} keyframes "
@@ -163,67 +180,96 @@ def main():
     ctx = D.Context(0)
     R = 11 + 3 * (w["deg"] + 1) ** 2
 
+    V = args.window
+    walk = w["walk"]
+    if walk:
+        # the camera only moves forward: warmup windows, then the timed ones
+        n_win = args.warmup + -(-max(args.steps, V) // V)
+        w["cams"] = w["cams"][:n_win * V]
+    K = len(w["cams"])
+
     # targets: renders of the true scene at every keyframe
-    gt_pool = D.Pool(ctx, w["deg"], budget=w["n"] + 1)
+    gt_pool = D.Pool(ctx, w["deg"], budget=w["budget"])
     gt_pool.ingest(w["true"], w["chunk"])
-    gt_loop = mapping.MappingLoop(ctx, gt_pool, w["deg"], w["chunk"], int(w["n"] * 0.6),
-                                  w["W"], w["H"], (tw, th))
+    cap = int(min(w["n"], w["budget"]) * 1.1) + 16
+    gt_loop = mapping.MappingLoop(ctx, gt_pool, w["deg"], w["chunk"], cap, w["W"], w["H"],
+                                  (tw, th))
     targets, actives = [], []
-    for cam in w["cams"]:
+    for k, cam in enumerate(w["cams"]):
         ids = gt_loop.select(cam)
-        gt_pool.require(ids, now=0)
+        gt_pool.require(ids, now=k)
         n = gt_pool.compact(ids, gt_loop.params, gt_loop.src)
         rgb, _ = gt_loop.state.forward(gt_loop.params, n, w["deg"], cam, (0, 0, 0), (tw, th))
         targets.append(rgb.clone())
         actives.append(n)
     del gt_loop
     gt_pool.close()
+    del w["true"]
     torch.cuda.synchronize()
     log(f"targets rendered; active Gaussians per keyframe mean {np.mean(actives):.0f} "
         f"min {min(actives)} max {max(actives)}")
 
-    V = args.window
-    K = len(w["cams"])
     windows = [list(range(k, k + V)) for k in range(0, K - V + 1, V)]
     tstack = [torch.stack([targets[i] for i in win]) for win in windows]
 
     def make_loop():
-        pool = D.Pool(ctx, w["deg"], budget=w["n"] + 1)
+        pool = D.Pool(ctx, w["deg"], budget=w["budget"])
         pool.ingest(w["start"], w["chunk"])
-        return pool, mapping.MappingLoop(ctx, pool, w["deg"], w["chunk"],
-                                         int(max(actives) * 2.2) + 16, w["W"], w["H"], (tw, th),
-                                         ppt=args.ppt)
+        cap_w = int(min(w["n"], w["budget"]) * 1.1) + 16
+        return pool, mapping.MappingLoop(ctx, pool, w["deg"], w["chunk"], cap_w, w["W"], w["H"],
+                                         (tw, th), ppt=args.ppt)
+
+    cursor = {}
 
     def run(loop, kind: str, n_views: int) -> float:
-        """Time `n_views` keyframe views of one path; returns seconds."""
+        """Time `n_views` keyframe views of one path; returns seconds.  Each
+        step selects (on a side stream) and stages the next step's chunks
+        while the current one runs."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        done, k = 0, 0
+        done = 0
+        k, sel = cursor.get(kind, (0, None))
         while done < n_views:
             if kind == "plain":
-                c = (k * 3) % K
-                loop.step(w["cams"][c], targets[c])
+                c = k % K if walk else (k * 3) % K
+                loop.step(w["cams"][c], targets[c], None if sel is None else sel[0])
+                nxt = (k + 1) % K if walk else ((k + 1) * 3) % K
+                sel = loop.prefetch_window([w["cams"][nxt]])
                 done += 1
             else:
                 wi = k % len(windows)
                 cams = [w["cams"][i] for i in windows[wi]]
                 if kind == "batched":
-                    loop.window_step(cams, tstack[wi])
+                    loop.window_step(cams, tstack[wi], sel=sel)
                 else:
-                    loop.window_step_sequential(cams, tstack[wi])
+                    loop.window_step_sequential(cams, tstack[wi], sel=sel)
+                nw = (k + 1) % len(windows)
+                sel = loop.prefetch_window([w["cams"][i] for i in windows[nw]])
                 done += V
             k += 1
+        cursor[kind] = (k, sel)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
     pool_b, loop_b = make_loop()
     pool_s, loop_s = make_loop()
+    log(f"pools ingested ({time.perf_counter() - t_setup:.1f} s since start)")
+    tuned, tune_ms = None, []
+    if args.tile == "auto":
+        tuned, tune_ms = loop_b.autotune([w["cams"][i] for i in windows[0]])
+        for lp in (loop_s,):
+            lp.tile, lp.ppt = tuned[:2], tuned[2]
+        tw, th = tuned[0], tuned[1]
+        args.ppt = tuned[2]
+        log(f"autotuned raster shape {tuned}; fwd+bwd ms per shape {[round(t, 2) for t in tune_ms]}")
     n_views = max(args.steps, V)
     run(loop_b, "batched", args.warmup * V)
+    cursor["sequential"] = (0, None)
     run(loop_s, "sequential", args.warmup * V)
     log(f"setup {time.perf_counter() - t_setup:.1f} s; timing {n_views} views per path")
     t_b = run(loop_b, "batched", n_views)
     t_s = run(loop_s, "sequential", n_views)
+    pool_stats = pool_b.stats()
     n_timed = ((n_views + V - 1) // V) * V
     dt = t_b
     # equal-PSNR check: both pools received the same windows, so the same update
@@ -232,6 +278,7 @@ def main():
         for wi in range(len(windows)):
             cams = [w["cams"][i] for i in windows[wi]]
             ids, masks = loop_.select_window(cams)
+            loop_.pool.require(ids, now=loop_.iter)
             n = loop_.pool.compact(ids, loop_.params, loop_.src, masks=masks, out_gmask=loop_.gmask)
             loop_.state.forward(loop_.params, n, w["deg"], cams, (0, 0, 0), (tw, th), loop_.rgb_v,
                                 loop_.depth_v, ppt=args.ppt, gmask=loop_.gmask)
@@ -290,22 +337,28 @@ def main():
         except Exception as e:  # the baseline is reported, never required
             log(f"cpu baseline failed: {e!r}")
 
+    scene = "driving corridor" if walk else "indoor room"
+    metric = METRIC if args.workload == "indoor-2m" else (
+        f"fwd+bwd splat mapping iters/s @{w['W']}x{w['H']}, {args.workload}; batched vs plain")
     out = {
-        "metric": METRIC, "value": round(n_timed / dt, 3), "unit": "iters/s", "n_gpus": 1,
+        "metric": metric, "value": round(n_timed / dt, 3), "unit": "iters/s", "n_gpus": 1,
         "steps": n_timed, "warmup": args.warmup * V, "ms_per_step": round(1e3 * dt / n_timed, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: indoor room {w['n']} Gaussians SH{w['deg']}, "
-                               f"{w['W']}x{w['H']}, {w['chunk']:g} m chunks, tile {tw}x{th}, "
+        "config": {"workload": f"{args.workload}: {scene} {w['n']} Gaussians SH{w['deg']}, "
+                               f"{w['W']}x{w['H']}, {w['chunk']:g} m chunks, device budget "
+                               f"{min(w['budget'], w['n'])} Gaussians, tile {tw}x{th}, "
                                f"{args.ppt or 'default'} px/lane; value = batched windows of "
                                f"{V} keyframes (one iteration = one keyframe view)",
+                   "pool_batched": pool_stats,
                    "active_gaussians_per_window_mean": round(N), "pairs_per_window_mean": round(Pp),
                    "evaluations_per_window_mean": round(E),
                    "batched_views_per_s": round(n_timed / t_b, 3),
                    "sequential_views_per_s": round(n_timed / t_s, 3),
                    "plain_iters_per_s": round(plain_rate, 3),
                    "psnr_batched_db": round(psnr_b, 4), "psnr_sequential_db": round(psnr_s, 4),
-                   "psnr_delta_db": round(abs(psnr_b - psnr_s), 6)},
+                   "psnr_delta_db": round(abs(psnr_b - psnr_s), 6),
+                   "raster_shape": [tw, th, args.ppt], "autotune_ms": [round(t, 3) for t in tune_ms]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},

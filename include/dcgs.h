@@ -145,18 +145,36 @@ int dcgs_pool_chunks(dcgs_pool *pool, uint64_t *ids, int64_t *counts,
 /* Device array of the occupied chunk ids (ascending), for select_chunks. */
 const uint64_t *dcgs_pool_device_ids(dcgs_pool *pool, int *n_out);
 
-/* SYNC.  Make the chunks `ids` (host, n) resident: load = ids \ resident;
- * if the budget would be exceeded, evict the evictable (resident, not in
- * ids) chunks oldest access first (ties: lower id), the shortest such prefix
- * that fits, writing their state back to the host store.  The chunks in ids
- * get access time `now`.  DCGS_E_BUDGET if ids alone do not fit (nothing is
- * changed then).  *loaded / *evicted (nullable) get the chunk counts. */
+/* Make the chunks `ids` (host, n) resident for frame `now`: load = ids \
+ * resident; if the budget would be exceeded, evict the evictable (resident,
+ * not in ids) chunks oldest access first (ties: lower id), the shortest
+ * such prefix that fits, writing their state back to the host store.  The
+ * chunks in ids get access time `now`.  DCGS_E_BUDGET if ids alone do not
+ * fit (nothing is changed then).  *loaded / *evicted (nullable) get the
+ * chunk counts; loads here count as misses (not staged ahead of time).
+ * Host-asynchronous: copies run on the pool's own copy stream, and
+ * `stream` (the compute stream) waits, device-side, for every chunk in ids;
+ * an eviction's copy waits for the compute work of the chunk's last frame.
+ * `now` must not decrease from call to call. */
 int dcgs_pool_require(dcgs_pool *pool, const uint64_t *ids, int n,
                       int64_t now, int *loaded, int *evicted, void *stream);
 
-/* SYNC.  Current state of one chunk (from the device if resident, else the
- * host store), into host arrays params/m/v [R][count] and step [count];
- * any of them may be null. */
+/* Stage chunks ahead of need (host-asynchronous, copy stream): each id not
+ * resident is loaded, in the given order, after evicting chunks that were
+ * not used in frame `now` and are not in ids (oldest first) to make room;
+ * staging stops at the first chunk that does not fit.  Staged chunks get access time `now`.  *staged
+ * (nullable) gets the number staged.  A later require() of a staged chunk
+ * counts as a hit and only waits for its copy event. */
+int dcgs_pool_prefetch(dcgs_pool *pool, const uint64_t *ids, int n,
+                       int64_t now, int *staged, void *stream);
+
+/* Counters: out[0..7] = loads, evictions, prefetched, misses, hits, bytes
+ * host->device, bytes device->host, Gaussians resident (first n_out). */
+int dcgs_pool_stats(dcgs_pool *pool, int64_t *out, int n_out);
+
+/* SYNC (waits for the device).  Current state of one chunk (from the
+ * device if resident, else the host store), into host arrays params/m/v
+ * [R][count] and step [count]; any of them may be null. */
 int dcgs_pool_read_chunk(dcgs_pool *pool, uint64_t id, float *params,
                          float *m, float *v, int32_t *step);
 
@@ -250,6 +268,23 @@ int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target,
 int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad,
                    int64_t n, int64_t grad_stride,
                    const dcgs_adam_config *cfg, void *stream);
+
+/* ---- autotuner ----------------------------------------------------------- */
+
+/* SYNC.  Time one forward and one backward pass of every supported raster
+ * shape (tile_w, tile_h, pixels_per_lane) on the given window (same
+ * arguments as dcgs_render_fwd), keep the fastest, and remember it in ctx
+ * for windows of the same width, height, view count and size class
+ * (ceil(log2(n))).  A cached answer returns at once unless force != 0.
+ * Images do not depend on the shape.  Scratch images and gradients are
+ * owned by ctx.  out_shape: host int[3]; times_ms: host double[n_shapes]
+ * or null (filled only when shapes are timed); *n_shapes (host, nullable)
+ * gets the number of shapes. */
+int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params,
+                  int64_t n, int64_t stride, int sh_degree,
+                  const uint16_t *gmask, const dcgs_camera *cams, int n_views,
+                  int force, int *out_shape, double *times_ms, int *n_shapes,
+                  void *stream);
 
 /* ---- stage timers -------------------------------------------------------- */
 

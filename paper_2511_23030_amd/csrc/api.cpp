@@ -10,6 +10,8 @@ void pool_destroy(dcgs_pool *p);
 void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStream_t st);
 void pool_require(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *loaded,
                   int *evicted, hipStream_t st);
+void pool_prefetch(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *staged,
+                   hipStream_t st);
 void pool_read_chunk(dcgs_pool *p, uint64_t id, float *params, float *m, float *v,
                      int32_t *step);
 void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int n_ids,
@@ -170,6 +172,21 @@ int dcgs_pool_require(dcgs_pool *pool, const uint64_t *ids, int n, int64_t now, 
                  [&] { dcgs::pool_require(pool, ids, n, now, loaded, evicted, S(stream)); });
 }
 
+int dcgs_pool_prefetch(dcgs_pool *pool, const uint64_t *ids, int n, int64_t now, int *staged,
+                       void *stream) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx,
+                 [&] { dcgs::pool_prefetch(pool, ids, n, now, staged, S(stream)); });
+}
+
+int dcgs_pool_stats(dcgs_pool *pool, int64_t *out, int n_out) {
+  if (!pool || !out) return DCGS_E_INVALID;
+  const int64_t v[8] = {pool->n_loads,  pool->n_evictions, pool->n_prefetched, pool->n_misses,
+                        pool->n_hits,   pool->bytes_h2d,   pool->bytes_d2h,    pool->resident_g};
+  for (int k = 0; k < n_out && k < 8; ++k) out[k] = v[k];
+  return DCGS_OK;
+}
+
 int dcgs_pool_read_chunk(dcgs_pool *pool, uint64_t id, float *params, float *m, float *v,
                          int32_t *step) {
   if (!pool) return DCGS_E_INVALID;
@@ -298,6 +315,70 @@ int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad, int64
     dcgs::StageTimer tm(pool->ctx, DCGS_STAGE_ADAM, S(stream));
     dcgs::launch_adam(pool->d_params, pool->d_m, pool->d_v, pool->d_step, pool->R, src, grad, n,
                       grad_stride, *cfg, S(stream));
+  });
+}
+
+int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n, int64_t stride,
+                  int sh_degree, const uint16_t *gmask, const dcgs_camera *cams, int n_views,
+                  int force, int *out_shape, double *times_ms, int *n_shapes, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  static const int kShapes[][3] = {{16, 16, 1}, {16, 16, 2}, {16, 16, 4}, {8, 8, 1},
+                                   {32, 16, 2}, {32, 16, 4}, {32, 16, 8}};
+  constexpr int kN = sizeof(kShapes) / sizeof(kShapes[0]);
+  if (n_shapes) *n_shapes = kN;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(st && st->ctx == ctx && out_shape && cams && n_views >= 1 &&
+                   n_views <= dcgs::kMaxViews && n >= 0,
+               DCGS_E_INVALID, "autotune: bad args");
+    int lg = 0;
+    while ((int64_t(1) << lg) < n) ++lg;
+    const uint64_t key = (uint64_t)cams[0].width << 40 | (uint64_t)cams[0].height << 24 |
+                         (uint64_t)n_views << 8 | (uint64_t)lg;
+    auto it = ctx->tune_cache.find(key);
+    if (it != ctx->tune_cache.end() && !force) {
+      for (int k = 0; k < 3; ++k) out_shape[k] = it->second[k];
+      return;
+    }
+    const int W = cams[0].width, H = cams[0].height;
+    const int64_t HW = (int64_t)W * H;
+    const int R = dcgs::n_rows(sh_degree);
+    float *img = ctx->tune_img.need(n_views * HW * 8 + 1);
+    float *rgb = img, *depth = img + 3 * n_views * HW, *dl = img + 4 * n_views * HW;
+    float *grad = ctx->tune_grad.need((size_t)R * (n > 0 ? n : 1));
+    DCGS_HIP(hipMemsetAsync(dl, 0, 3 * n_views * HW * sizeof(float), S(stream)));
+    const float bg[3] = {0, 0, 0};
+    hipEvent_t e0, e1;
+    DCGS_HIP(hipEventCreate(&e0));
+    DCGS_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int bi = 1;
+    for (int k = 0; k < kN; ++k) {
+      const int *sh = kShapes[k];
+      auto pass = [&] {
+        int rc = dcgs_render_fwd(ctx, st, params, n, stride, sh_degree, gmask, 0, cams, n_views,
+                                 bg, sh[0], sh[1], sh[2], rgb, depth, nullptr, stream);
+        DCGS_CHECK(rc == DCGS_OK, rc, "autotune: forward failed: " + ctx->err);
+        rc = dcgs_render_bwd(ctx, st, params, n, stride, dl, nullptr, grad, n, 0, nullptr, stream);
+        DCGS_CHECK(rc == DCGS_OK, rc, "autotune: backward failed: " + ctx->err);
+      };
+      pass();  // warm: buffers sized, code loaded
+      DCGS_HIP(hipEventRecord(e0, S(stream)));
+      pass();
+      DCGS_HIP(hipEventRecord(e1, S(stream)));
+      DCGS_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      DCGS_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (times_ms) times_ms[k] = ms;
+      if (ms < best) {
+        best = ms;
+        bi = k;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::array<int, 3> a{kShapes[bi][0], kShapes[bi][1], kShapes[bi][2]};
+    ctx->tune_cache[key] = a;
+    for (int k = 0; k < 3; ++k) out_shape[k] = a[k];
   });
 }
 

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -93,6 +94,9 @@ struct dcgs_ctx {
   dcgs::DevBuf<float> loss_part;
   dcgs::DevBuf<uint32_t> scan_part;
   int n_cu = 256;
+  // autotuner: scratch outputs and the cache (key -> tile_w, tile_h, ppt)
+  dcgs::DevBuf<float> tune_img, tune_grad;
+  std::unordered_map<uint64_t, std::array<int, 3>> tune_cache;
 };
 
 struct dcgs_state {
@@ -140,6 +144,8 @@ struct HostChunk {
   bool resident = false;
   int64_t last_access = -1;
   std::vector<int32_t> dev_pages;
+  hipEvent_t ready = nullptr;  // recorded on the copy stream after the last load
+  bool staged = false;         // loaded by a prefetch, not yet required
 };
 
 struct dcgs_pool {
@@ -165,6 +171,15 @@ struct dcgs_pool {
   int4 *h_seg = nullptr;
   size_t h_seg_cap = 0;
   hipEvent_t seg_done = nullptr;
+  hipEvent_t cut = nullptr;  // compute-stream point an eviction's copy waits for
+  // staging: every host<->device chunk copy runs on this stream
+  hipStream_t copy = nullptr;
+  // frame_event[f]: recorded on the compute stream at the first require of
+  // frame f, i.e. after all work of frames < f was enqueued there
+  std::unordered_map<int64_t, hipEvent_t> frame_event;
+  // counters
+  int64_t n_loads = 0, n_evictions = 0, n_prefetched = 0, n_misses = 0, n_hits = 0;
+  int64_t bytes_h2d = 0, bytes_d2h = 0;
 };
 
 namespace dcgs {

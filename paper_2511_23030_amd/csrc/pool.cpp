@@ -39,11 +39,12 @@ void release_pages(dcgs_pool *p, const std::vector<int32_t> &pages) {
   std::sort(p->free_pages.begin(), p->free_pages.end(), std::greater<int32_t>());
 }
 
-// Copy a chunk's pages host <-> device, merging runs of consecutive device
-// pages into one copy per array.
-void move_chunk(dcgs_pool *p, HostChunk &c, bool to_device, hipStream_t st) {
+// Copy a chunk's pages host <-> device on the copy stream, merging runs of
+// consecutive device pages into one copy per array.
+void move_chunk(dcgs_pool *p, HostChunk &c, bool to_device) {
   const size_t pbytes = (size_t)p->R * PG * sizeof(float);
   const size_t sbytes = (size_t)PG * sizeof(int32_t);
+  hipStream_t st = p->copy;
   int64_t k = 0;
   while (k < c.pages) {
     int64_t run = 1;
@@ -67,6 +68,67 @@ void move_chunk(dcgs_pool *p, HostChunk &c, bool to_device, hipStream_t st) {
       DCGS_HIP(hipMemcpyAsync(hs, ds, run * sbytes, hipMemcpyDeviceToHost, st));
     k += run;
   }
+  const int64_t bytes = c.pages * (int64_t)(3 * pbytes + sbytes);
+  if (to_device) {
+    p->bytes_h2d += bytes;
+    ++p->n_loads;
+  } else {
+    p->bytes_d2h += bytes;
+    ++p->n_evictions;
+  }
+  DCGS_HIP(hipEventRecord(c.ready, st));
+}
+
+// The event that follows every compute-stream use of a chunk last used in
+// frame u < now: the first frame event recorded after u.
+hipEvent_t after_frame(dcgs_pool *p, int64_t u) {
+  hipEvent_t best = nullptr;
+  int64_t bf = INT64_MAX;
+  for (auto &kv : p->frame_event)
+    if (kv.first > u && kv.first < bf) {
+      bf = kv.first;
+      best = kv.second;
+    }
+  return best;
+}
+
+void mark_frame(dcgs_pool *p, int64_t now, hipStream_t st) {
+  if (p->frame_event.count(now)) return;
+  hipEvent_t e;
+  DCGS_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  DCGS_HIP(hipEventRecord(e, st));
+  p->frame_event[now] = e;
+  // forget frames older than every resident chunk's last use
+  int64_t oldest = now;
+  for (auto &c : p->chunks)
+    if (c.resident && c.last_access >= 0) oldest = std::min(oldest, c.last_access);
+  for (auto it = p->frame_event.begin(); it != p->frame_event.end();) {
+    if (it->first <= oldest && it->first != now && it->first + 1 <= oldest) {
+      (void)hipEventDestroy(it->second);
+      it = p->frame_event.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// Write an evictable chunk back to the host store and free its pages.  The
+// copy waits for the compute-stream work of the chunk's last frame (for a
+// chunk already used in frame `now`, for everything enqueued on `st` so far).
+void evict_chunk(dcgs_pool *p, HostChunk &h, int64_t now, hipStream_t st) {
+  if (h.last_access >= 0 && h.last_access < now) {
+    hipEvent_t e = after_frame(p, h.last_access);
+    if (e) DCGS_HIP(hipStreamWaitEvent(p->copy, e, 0));
+  } else if (h.last_access >= now) {
+    DCGS_HIP(hipEventRecord(p->cut, st));
+    DCGS_HIP(hipStreamWaitEvent(p->copy, p->cut, 0));
+  }
+  move_chunk(p, h, false);
+  release_pages(p, h.dev_pages);
+  h.dev_pages.clear();
+  h.resident = false;
+  h.staged = false;
+  p->resident_g -= h.n;
 }
 
 }  // namespace
@@ -79,11 +141,14 @@ void pool_create(dcgs_ctx *ctx, int deg, int64_t budget, dcgs_pool **out) {
   p->R = n_rows(deg);
   p->budget = budget;
   DCGS_HIP(hipEventCreateWithFlags(&p->seg_done, hipEventDisableTiming));
+  DCGS_HIP(hipEventCreateWithFlags(&p->cut, hipEventDisableTiming));
+  DCGS_HIP(hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking));
   *out = p;
 }
 
 void pool_destroy(dcgs_pool *p) {
   if (!p) return;
+  if (p->copy) (void)hipStreamSynchronize(p->copy);
   if (p->d_params) (void)hipFree(p->d_params);
   if (p->d_m) (void)hipFree(p->d_m);
   if (p->d_v) (void)hipFree(p->d_v);
@@ -91,6 +156,11 @@ void pool_destroy(dcgs_pool *p) {
   if (p->arena) (void)hipHostFree(p->arena);
   if (p->h_seg) (void)hipHostFree(p->h_seg);
   if (p->seg_done) (void)hipEventDestroy(p->seg_done);
+  if (p->cut) (void)hipEventDestroy(p->cut);
+  for (auto &c : p->chunks)
+    if (c.ready) (void)hipEventDestroy(c.ready);
+  for (auto &kv : p->frame_event) (void)hipEventDestroy(kv.second);
+  if (p->copy) (void)hipStreamDestroy(p->copy);
   delete p;
 }
 
@@ -161,6 +231,7 @@ void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStre
     cur += h.pages * fpage;
     h.step = (int32_t *)cur;
     cur += h.pages * spage;
+    DCGS_HIP(hipEventCreateWithFlags(&h.ready, hipEventDisableTiming));
     p->index[h.id] = (int)c;
   }
   // 4. scatter the input rows into the page-major store (threads over rows)
@@ -234,31 +305,83 @@ void pool_require(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *lo
   }
   DCGS_CHECK(total <= p->budget, DCGS_E_BUDGET,
              "pool_require: visible chunks exceed the residency budget");
-  // page capacity must also hold the loaded chunks
   int64_t free_after = (int64_t)p->free_pages.size();
   for (int c : evict) free_after += p->chunks[c].pages;
   int64_t need_pages = 0;
   for (int c : load) need_pages += p->chunks[c].pages;
   DCGS_CHECK(need_pages <= free_after, DCGS_E_BUDGET, "pool_require: device pages exhausted");
-  for (int c : evict) {
-    HostChunk &h = p->chunks[c];
-    move_chunk(p, h, false, st);
-    release_pages(p, h.dev_pages);
-    h.dev_pages.clear();
-    h.resident = false;
-    p->resident_g -= h.n;
-  }
+  mark_frame(p, now, st);
+  for (int c : evict) evict_chunk(p, p->chunks[c], now, st);
   for (int c : load) {
     HostChunk &h = p->chunks[c];
     h.dev_pages = alloc_pages(p, h.pages);
-    move_chunk(p, h, true, st);
+    move_chunk(p, h, true);
     h.resident = true;
+    h.staged = false;
     p->resident_g += h.n;
+    ++p->n_misses;
   }
-  for (int c : need) p->chunks[c].last_access = now;
-  DCGS_HIP(hipStreamSynchronize(st));
+  for (int c : need) {
+    HostChunk &h = p->chunks[c];
+    if (h.staged) {
+      ++p->n_hits;
+      h.staged = false;
+    }
+    // the compute stream waits for the chunk's last copy (no host wait)
+    DCGS_HIP(hipStreamWaitEvent(st, h.ready, 0));
+    h.last_access = now;
+  }
   if (loaded) *loaded = (int)load.size();
   if (evicted) *evicted = (int)evict.size();
+}
+
+void pool_prefetch(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *staged,
+                   hipStream_t st) {
+  DCGS_CHECK(n >= 0 && (ids || n == 0), DCGS_E_INVALID, "pool_prefetch: bad args");
+  std::vector<int> want;
+  want.reserve(n);
+  std::vector<char> wanted(p->chunks.size(), 0);
+  for (int k = 0; k < n; ++k) {
+    auto it = p->index.find(ids[k]);
+    DCGS_CHECK(it != p->index.end(), DCGS_E_NOT_RESIDENT, "pool_prefetch: unknown chunk id");
+    want.push_back(it->second);
+    wanted[it->second] = 1;
+  }
+  mark_frame(p, now, st);
+  int done = 0;
+  for (int c : want) {
+    HostChunk &h = p->chunks[c];
+    if (h.resident) continue;
+    // room: evict chunks neither used in this frame nor asked for, oldest
+    // first (best effort)
+    std::vector<int> evictable;
+    for (size_t e = 0; e < p->chunks.size(); ++e) {
+      const HostChunk &x = p->chunks[e];
+      if (x.resident && x.last_access < now && !wanted[e]) evictable.push_back((int)e);
+    }
+    std::sort(evictable.begin(), evictable.end(), [&](int a, int b) {
+      const HostChunk &x = p->chunks[a], &y = p->chunks[b];
+      return x.last_access != y.last_access ? x.last_access < y.last_access : x.id < y.id;
+    });
+    int64_t total = p->resident_g + h.n, pages_free = (int64_t)p->free_pages.size();
+    size_t m = 0;
+    while (m < evictable.size() && (total > p->budget || pages_free < h.pages)) {
+      total -= p->chunks[evictable[m]].n;
+      pages_free += p->chunks[evictable[m]].pages;
+      ++m;
+    }
+    if (total > p->budget || pages_free < h.pages) break;  // budget full: stop staging
+    for (size_t q = 0; q < m; ++q) evict_chunk(p, p->chunks[evictable[q]], now, st);
+    h.dev_pages = alloc_pages(p, h.pages);
+    move_chunk(p, h, true);
+    h.resident = true;
+    h.staged = true;
+    h.last_access = now;
+    p->resident_g += h.n;
+    ++p->n_prefetched;
+    ++done;
+  }
+  if (staged) *staged = done;
 }
 
 void pool_read_chunk(dcgs_pool *p, uint64_t id, float *params, float *m, float *v,
@@ -266,6 +389,7 @@ void pool_read_chunk(dcgs_pool *p, uint64_t id, float *params, float *m, float *
   auto it = p->index.find(id);
   DCGS_CHECK(it != p->index.end(), DCGS_E_NOT_RESIDENT, "pool_read_chunk: unknown chunk id");
   HostChunk &h = p->chunks[it->second];
+  DCGS_HIP(hipDeviceSynchronize());  // pending copies and kernels touching the chunk
   const int R = p->R;
   const size_t fpage = (size_t)R * PG, n_f = h.pages * fpage;
   std::vector<float> tp, tm, tv;

@@ -79,6 +79,8 @@ SIGNATURES = {
     "dcgs_pool_device_ids": (P, [P, C.POINTER(INT)]),
     "dcgs_pool_require": (INT, [P, P, INT, I64, C.POINTER(INT), C.POINTER(INT), P]),
     "dcgs_pool_read_chunk": (INT, [P, C.c_uint64, P, P, P, P]),
+    "dcgs_pool_prefetch": (INT, [P, P, INT, I64, C.POINTER(INT), P]),
+    "dcgs_pool_stats": (INT, [P, P, INT]),
     "dcgs_pool_resident": (INT, [P, P, INT, C.POINTER(INT), C.POINTER(I64)]),
     "dcgs_compact": (INT, [P, P, P, INT, P, I64, P, P, I64, C.POINTER(I64), P]),
     "dcgs_state_create": (INT, [P, C.POINTER(P)]),
@@ -88,6 +90,7 @@ SIGNATURES = {
     "dcgs_render_bwd": (INT, [P, P, P, I64, I64, P, P, P, I64, INT, P, P]),
     "dcgs_loss_l1": (INT, [P, P, P, I64, DBL, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
+    "dcgs_autotune": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
     "dcgs_profile_enable": (INT, [P, INT]),
     "dcgs_profile_read": (INT, [P, P, P, INT]),
     "dcgs_state_info": (INT, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)]),
@@ -258,6 +261,21 @@ class Pool:
                                                C.byref(lo), C.byref(ev), stream_handle(stream)))
         return lo.value, ev.value
 
+    def prefetch(self, ids: np.ndarray, now: int, stream=None) -> int:
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        k = INT()
+        self.ctx.check(lib().dcgs_pool_prefetch(self.h, ids.ctypes.data, ids.size, now,
+                                                C.byref(k), stream_handle(stream)))
+        return k.value
+
+    STAT_NAMES = ("loads", "evictions", "prefetched", "misses", "hits", "bytes_h2d", "bytes_d2h",
+                  "resident")
+
+    def stats(self) -> dict:
+        out = np.zeros(8, np.int64)
+        self.ctx.check(lib().dcgs_pool_stats(self.h, out.ctypes.data, 8))
+        return dict(zip(self.STAT_NAMES, out.tolist()))
+
     def read_chunk(self, cid: int, count: int):
         p = np.zeros((self.R, count), np.float32)
         m = np.zeros_like(p)
@@ -345,6 +363,22 @@ class RenderState:
                                              grad.stride(0), int(accumulate), ptr(grad2d),
                                              stream_handle(stream)))
         return grad
+
+    def autotune(self, params, n: int, sh_degree: int, cams: list, gmask=None, force=False,
+                 stream=None):
+        """Fastest raster shape (tile_w, tile_h, pixels_per_lane) for this
+        window, and the per-shape forward+backward times in ms (empty when
+        the context's cache answered)."""
+        shape = (C.c_int * 3)()
+        times = np.zeros(16, np.float64)
+        k = INT()
+        arr = (Camera * len(cams))(*[Camera.of(c) for c in cams])
+        times[:] = -1.0
+        self.ctx.check(lib().dcgs_autotune(self.ctx.h, self.h, ptr(params), n, params.stride(0),
+                                           sh_degree, ptr(gmask), C.cast(arr, P), len(cams),
+                                           int(force), shape, times.ctypes.data, C.byref(k),
+                                           stream_handle(stream)))
+        return (shape[0], shape[1], shape[2]), [t for t in times[:k.value] if t >= 0]
 
     def info(self):
         n, p, tx, ty = I64(), I64(), I32(), I32()

@@ -6,12 +6,15 @@ this class owns the device buffers and sequences the calls.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 
 import numpy as np
 import torch
 
 from . import dcgs as D
+
+_nullctx = contextlib.nullcontext
 
 DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4)
 
@@ -33,43 +36,54 @@ class MappingLoop:
         self.depth = torch.empty(height, width, dtype=torch.float32, device=dev)
         self.dl = torch.empty(3, height, width, dtype=torch.float32, device=dev)
         self.stats = torch.zeros(2, dtype=torch.float64, device=dev)
-        self.sel_ids = torch.empty(4096, dtype=torch.int64, device=dev)
-        self.sel_mask = torch.empty(4096, dtype=torch.int16, device=dev)
-        self.sel_count = torch.zeros(1, dtype=torch.int32, device=dev)
         self.state = D.RenderState(ctx)
         self.adam = D.AdamConfig.of(lr)
         self.iter = 0
         self.last = {}
 
+    def _sel_buffers(self, n: int, side: bool):
+        key = "_side_sel" if side else "_sel"
+        buf = getattr(self, key, None)
+        if buf is None or buf[0].numel() < n:
+            dev = self.params.device
+            m = max(n, 4096)
+            buf = (torch.empty(m, dtype=torch.int64, device=dev),
+                   torch.empty(m, dtype=torch.int16, device=dev),
+                   torch.zeros(1, dtype=torch.int32, device=dev))
+            setattr(self, key, buf)
+        return buf
+
+    def select_window(self, cams: list, stream: torch.cuda.Stream | None = None
+                      ) -> tuple[np.ndarray, np.ndarray]:
+        """Union of the chunks the views see (ascending ids) and each chunk's
+        view mask (host copies).  Runs on `stream` (default: the current
+        stream) and waits for that stream only."""
+        addr, n = self.pool.device_ids()
+        ids_t, mask_t, count_t = self._sel_buffers(n, stream is not None)
+        arr = (D.Camera * len(cams))(*[D.Camera.of(c) for c in cams])
+        with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            self.ctx.check(D.lib().dcgs_select_chunks(
+                self.ctx.h, C.cast(arr, C.c_void_p), len(cams), addr, n, self.s, D.ptr(ids_t),
+                D.ptr(mask_t), D.ptr(count_t), D.stream_handle(stream)))
+            k = int(count_t.item())
+            return (ids_t[:k].cpu().numpy().view(np.uint64),
+                    mask_t[:k].cpu().numpy().view(np.uint16))
+
     def select(self, cam: dict) -> np.ndarray:
         """Visible chunk ids of `cam` (host copy; one sync)."""
-        addr, n = self.pool.device_ids()
-        if n > self.sel_ids.numel():
-            dev = self.sel_ids.device
-            self.sel_ids = torch.empty(n, dtype=torch.int64, device=dev)
-            self.sel_mask = torch.empty(n, dtype=torch.int16, device=dev)
-        camc = D.Camera.of(cam)
-        self.ctx.check(D.lib().dcgs_select_chunks(
-            self.ctx.h, C.byref(camc), 1, addr, n, self.s, D.ptr(self.sel_ids),
-            D.ptr(self.sel_mask), D.ptr(self.sel_count), D.stream_handle()))
-        k = int(self.sel_count.item())
-        return self.sel_ids[:k].cpu().numpy().view(np.uint64)
+        return self.select_window([cam])[0]
 
-    def select_window(self, cams: list) -> tuple[np.ndarray, np.ndarray]:
-        """Union of the chunks the views see (ascending ids) and each chunk's
-        view mask (host copies; one sync)."""
-        addr, n = self.pool.device_ids()
-        if n > self.sel_ids.numel():
-            dev = self.sel_ids.device
-            self.sel_ids = torch.empty(n, dtype=torch.int64, device=dev)
-            self.sel_mask = torch.empty(n, dtype=torch.int16, device=dev)
-        arr = (D.Camera * len(cams))(*[D.Camera.of(c) for c in cams])
-        self.ctx.check(D.lib().dcgs_select_chunks(
-            self.ctx.h, C.cast(arr, C.c_void_p), len(cams), addr, n, self.s, D.ptr(self.sel_ids),
-            D.ptr(self.sel_mask), D.ptr(self.sel_count), D.stream_handle()))
-        k = int(self.sel_count.item())
-        return (self.sel_ids[:k].cpu().numpy().view(np.uint64),
-                self.sel_mask[:k].cpu().numpy().view(np.uint16))
+    def prefetch_window(self, cams: list) -> tuple[np.ndarray, np.ndarray]:
+        """Select the chunks of an upcoming window on a side stream (so the
+        work already queued on the compute stream keeps running) and stage
+        the missing ones on the pool's copy stream, evicting only chunks the
+        frame just queued does not use.  Returns the selection, to be handed
+        to that window's step so it is not computed twice."""
+        if getattr(self, "_side_stream", None) is None:
+            self._side_stream = torch.cuda.Stream(device=self.params.device)
+        sel = self.select_window(cams, stream=self._side_stream)
+        self.pool.prefetch(sel[0], now=self.iter - 1)
+        return sel
 
     def _window_buffers(self, V: int):
         if getattr(self, "_wv", 0) != V:
@@ -81,14 +95,27 @@ class MappingLoop:
             self.gmask = torch.empty(self.cap, dtype=torch.int16, device=dev)
             self._wv = V
 
-    def window_step(self, cams: list, targets: torch.Tensor) -> dict:
-        """One batched mapping iteration over a window of keyframes: one
-        selection, one compaction of the union with per-Gaussian view masks,
-        one forward and one backward launch sequence for all views, the loss
-        summed over views, one Adam step."""
+    def autotune(self, cams: list) -> tuple:
+        """Pick the fastest raster shape for windows like `cams` (timed on
+        this window's real Gaussians) and use it from now on."""
         V = len(cams)
         self._window_buffers(V)
         ids, masks = self.select_window(cams)
+        self.pool.require(ids, now=self.iter)
+        n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
+        shape, times = self.state.autotune(self.params, n, self.deg, list(cams), gmask=self.gmask)
+        self.tile, self.ppt = shape[:2], shape[2]
+        return shape, times
+
+    def window_step(self, cams: list, targets: torch.Tensor, sel=None) -> dict:
+        """One batched mapping iteration over a window of keyframes: one
+        selection, one compaction of the union with per-Gaussian view masks,
+        one forward and one backward launch sequence for all views, the loss
+        summed over views, one Adam step.  `sel`: this window's selection
+        if already made (prefetch_window)."""
+        V = len(cams)
+        self._window_buffers(V)
+        ids, masks = self.select_window(cams) if sel is None else sel
         loaded, evicted = self.pool.require(ids, now=self.iter)
         n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
         self.state.forward(self.params, n, self.deg, list(cams), self.bg, self.tile, self.rgb_v,
@@ -102,13 +129,13 @@ class MappingLoop:
                          views=V)
         return self.last
 
-    def window_step_sequential(self, cams: list, targets: torch.Tensor) -> dict:
+    def window_step_sequential(self, cams: list, targets: torch.Tensor, sel=None) -> dict:
         """The same update as window_step computed as one single-view forward
         and backward per view, accumulating gradients, then one Adam step
         (the per-view comparator of the batched path)."""
         V = len(cams)
         self._window_buffers(V)
-        ids, masks = self.select_window(cams)
+        ids, masks = self.select_window(cams) if sel is None else sel
         loaded, evicted = self.pool.require(ids, now=self.iter)
         n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
         H, W = self.rgb.shape[1], self.rgb.shape[2]

@@ -145,12 +145,15 @@ def perturb(params: np.ndarray, seed: int = 12, dc_sd: float = 0.1, logit_sd: fl
             mean_sd: float = 0.01) -> np.ndarray:
     """A perturbed copy of a scene, the starting point of optimisation."""
     rng = _rng(seed)
-    out = params.astype(np.float64).copy()
+    out = params.copy()
     n = out.shape[1]
-    out[0:3] += rng.normal(0.0, mean_sd, (3, n))
-    out[ROW_OPACITY] += rng.normal(0.0, logit_sd, n)
-    out[ROW_SH:ROW_SH + 3] += rng.normal(0.0, dc_sd, (3, n))
-    return out.astype(np.float32)
+    # sums in float64, rounded once to float32; only the touched rows widen
+    out[0:3] = (params[0:3].astype(np.float64) + rng.normal(0.0, mean_sd, (3, n))).astype(np.float32)
+    out[ROW_OPACITY] = (params[ROW_OPACITY].astype(np.float64)
+                        + rng.normal(0.0, logit_sd, n)).astype(np.float32)
+    out[ROW_SH:ROW_SH + 3] = (params[ROW_SH:ROW_SH + 3].astype(np.float64)
+                              + rng.normal(0.0, dc_sd, (3, n))).astype(np.float32)
+    return out
 
 
 def room_trajectory(n_frames: int, seed: int = 11, width: int = 1200, height: int = 680,
@@ -222,3 +225,124 @@ def adam_inputs(n_rows_: int, n: int, seed: int, n_slots: int | None = None) -> 
         step=rng.integers(0, 50, n_slots).astype(np.int32),
         grad=(rng.normal(0.0, 1e-4, (n_rows_, n)) * (rng.uniform(0, 1, (n_rows_, n)) > 0.1)).astype(np.float32),
         src=src)
+
+
+# --------------------------------------------------------------------------
+# Driving corridor: road and facades along a piecewise-straight path.
+# --------------------------------------------------------------------------
+CELL = 50.0          # grid cell of the corridor layout (m)
+GRID = 64            # cells per side
+ROAD_HALF = 15.0     # half width of the road (m)
+FACADE_H = 10.0      # facade height (m)
+
+
+def driving_path(seed: int = 20, length: float = 4000.0, max_tries: int = 200) -> np.ndarray:
+    """Centre line of a corridor: straight segments of 200-600 m (multiples of
+    50 m) joined by +-90 degree turns, inside a 64 x 64 grid of 50 m cells,
+    never re-entering a cell it already crossed.  Returns [m, 2] points 1 m
+    apart."""
+    for attempt in range(max_tries):
+        rng = _rng(seed * 1000 + attempt)
+        cx, cy = 4, 4
+        dirs = [(1, 0), (0, 1), (-1, 0), (0, -1)]
+        d = int(rng.integers(0, 2))
+        used = {(cx, cy)}
+        cells = [(cx, cy)]
+        total = 0.0
+        ok = True
+        while total < length:
+            seg = int(rng.integers(4, 13))          # 200..600 m
+            dx, dy = dirs[d]
+            path = [(cx + dx * k, cy + dy * k) for k in range(1, seg + 1)]
+            if any(not (3 <= x < GRID - 3 and 3 <= y < GRID - 3) or (x, y) in used
+                   or any((x + ex, y + ey) in used and (x + ex, y + ey) != (cx, cy)
+                          and (x + ex, y + ey) not in path
+                          for ex, ey in ((1, 0), (-1, 0), (0, 1), (0, -1)))
+                   for x, y in path):
+                ok = False
+                break
+            used.update(path)
+            cells.extend(path)
+            cx, cy = path[-1]
+            total += seg * CELL
+            d = (d + (1 if rng.uniform() < 0.5 else 3)) % 4
+        if ok:
+            pts = np.array(cells, np.float64) * CELL + CELL / 2
+            out = [pts[0]]
+            for a, b in zip(pts[:-1], pts[1:]):
+                n = int(round(np.linalg.norm(b - a)))
+                for k in range(1, n + 1):
+                    out.append(a + (b - a) * k / n)
+            return np.array(out)[: int(length) + 1]
+    raise RuntimeError("no corridor layout found")
+
+
+def driving_scene(n: int, seed: int = 20, sh_degree: int = 3, path: np.ndarray | None = None,
+                  jitter: float = 0.02, log_scale_mu: float = -2.5, log_scale_sd: float = 0.5,
+                  rest_sd: float = 0.05, chunked: int = 1 << 22) -> dict:
+    """Gaussians on the road (z = 0, 30 m wide) and two facades (+-15 m,
+    z in [0, 10]) along the corridor, allocated by area, N(0, jitter^2)
+    offsets; SH degree 3 colours as in the indoor scene.  Generated in
+    blocks to bound memory."""
+    P = driving_path(seed) if path is None else path
+    rng = _rng(seed + 7)
+    seg_len = np.linalg.norm(np.diff(P, axis=0), axis=1)
+    L = seg_len.sum()
+    road, facade = 2 * ROAD_HALF * L, 2 * FACADE_H * L
+    n_road = int(round(n * road / (road + facade)))
+    params = np.zeros((n_rows(sh_degree), n), np.float32)
+    cum = np.concatenate([[0.0], np.cumsum(seg_len)])
+    for s0 in range(0, n, chunked):
+        m = min(chunked, n - s0)
+        idx = np.arange(s0, s0 + m)
+        t = rng.uniform(0.0, L, m)
+        k = np.clip(np.searchsorted(cum, t, "right") - 1, 0, len(seg_len) - 1)
+        f = (t - cum[k]) / np.maximum(seg_len[k], 1e-9)
+        base = P[k] + (P[k + 1] - P[k]) * f[:, None]
+        tang = (P[k + 1] - P[k]) / np.maximum(seg_len[k], 1e-9)[:, None]
+        nrm = np.stack([-tang[:, 1], tang[:, 0]], 1)
+        is_road = idx < n_road
+        lateral = np.where(is_road, rng.uniform(-ROAD_HALF, ROAD_HALF, m),
+                           np.where(rng.uniform(0, 1, m) < 0.5, -ROAD_HALF, ROAD_HALF))
+        z = np.where(is_road, 0.0, rng.uniform(0.0, FACADE_H, m))
+        xy = base + nrm * lateral[:, None]
+        block = np.zeros((n_rows(sh_degree), m), np.float64)
+        block[0], block[1], block[2] = xy[:, 0], xy[:, 1], z
+        block[0:3] += rng.normal(0.0, jitter, (3, m))
+        _fill_common(rng, block, m, log_scale_mu, log_scale_sd, sh_degree, rest_sd)
+        params[:, s0:s0 + m] = block
+    return dict(params=params, sh_degree=sh_degree, path=P)
+
+
+def driving_trajectory(path: np.ndarray, n_frames: int | None = None, width: int = 1241,
+                       height: int = 376, focal: float = 718.0, z_far: float = 350.0,
+                       z_near: float = 0.2, cam_height: float = 1.65, start: int = 0,
+                       turn_frames: int = 15) -> list:
+    """Forward-facing camera on the centre line at 1 m per frame; the yaw is
+    eased over +-turn_frames around each corner."""
+    m = len(path) if n_frames is None else min(len(path), start + n_frames)
+    d = np.diff(path, axis=0)
+    yaw = np.unwrap(np.arctan2(d[:, 1], d[:, 0]))
+    yaw = np.concatenate([yaw, yaw[-1:]])
+    kern = np.ones(2 * turn_frames + 1) / (2 * turn_frames + 1)
+    pad = np.pad(yaw, turn_frames, mode="edge")
+    yaw_s = np.convolve(pad, kern, mode="valid")
+    cams = []
+    for k in range(start, m):
+        pos = np.array([path[k, 0], path[k, 1], cam_height])
+        cams.append(look_camera(pos, float(yaw_s[k]), 0.0, focal, focal, width, height, z_near,
+                                z_far, cx=width / 2.0, cy=height / 2.0))
+    return cams
+
+
+def mlp_init(seed: int, in_dim: int = 59, hidden: int = 256, bias_sd: float = 0.0) -> np.ndarray:
+    """Initial flat float32 parameters of the prefetch network (layout W1
+    [hidden][in], b1, W2 [hidden][hidden], b2, w3 [hidden], b3): weights
+    U(-1/sqrt(fan_in), 1/sqrt(fan_in)), biases N(0, bias_sd^2)."""
+    rng = _rng(seed)
+    parts = []
+    for fan_in, n_out in ((in_dim, hidden), (hidden, hidden), (hidden, 1)):
+        a = 1.0 / math.sqrt(fan_in)
+        parts.append(rng.uniform(-a, a, fan_in * n_out))
+        parts.append(rng.normal(0.0, 1.0, n_out) * bias_sd)
+    return np.concatenate(parts).astype(np.float32)

@@ -90,3 +90,19 @@ def test_window_step_equals_sequential_comparator(ctx, room):
             assert (x == y).all()
     pool_a.close()
     pool_b.close()
+
+
+def test_autotuner_picks_a_supported_shape_and_caches(ctx, room):
+    params, cams_all = room
+    V = 4
+    cams = cams_all[::20][:V]
+    pool, loop = _loop(ctx, params, V)
+    shape, times = loop.autotune(cams)
+    assert shape in {(16, 16, 1), (16, 16, 2), (16, 16, 4), (8, 8, 1), (32, 16, 2), (32, 16, 4),
+                     (32, 16, 8)}
+    assert len(times) == 7 and all(t > 0 for t in times)
+    assert abs(min(times) - times[[(16, 16, 1), (16, 16, 2), (16, 16, 4), (8, 8, 1), (32, 16, 2),
+                                   (32, 16, 4), (32, 16, 8)].index(shape)]) < 1e-9
+    shape2, times2 = loop.autotune(cams)          # cached: no timing
+    assert shape2 == shape and times2 == []
+    pool.close()
