@@ -286,6 +286,95 @@ int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params,
                   int force, int *out_shape, double *times_ms, int *n_shapes,
                   void *stream);
 
+/* ---- learned chunk prefetch --------------------------------------------- */
+/*
+ * Not part of the paper's method: the paper selects chunks by the exact
+ * frustum test of the current frame (Sec. III-D "Frustum Culling") and
+ * loads the missing ones (Sec. III-E "Optimization"); these calls predict,
+ * from the last 8 camera poses, which cells that test will select in the
+ * next frames, so that their staging (dcgs_pool_prefetch) starts early.
+ * The exact test stays in charge: a needed chunk that was not staged is
+ * loaded by dcgs_pool_require.
+ *
+ * Candidates of frame t: the 64 x 64 cells (Eq. 5) of the horizontal layer
+ * holding the camera centre c0, candidate q = j*64 + i at cell
+ * (bx + i - 32, by + j - 32, bz).  Input row (59 floats): for history entry
+ * k = 0..7 (frame max(t-k, 0)), R0 (c_k - c0) / pos_unit and the unit
+ * quaternion (w, x, y, z), w >= 0, of R0 R_k^T (R = world-to-camera
+ * rotation); then R0 (cell_centre - c0) / (8 s).
+ *
+ * Network: 59 -> 256 -> 256 -> 1, z1 = W1 x + b1, h1 = GELU(z1) (exact erf
+ * form), z2 = W2 h1 + b2, h2 = GELU(z2), logit = w3 . h2 + b3.  theta: the
+ * float32 master vector of DCGS_MLP_PARAMS values, W1 [256][59] row-major,
+ * b1 [256], W2 [256][256], b2 [256], w3 [256], b3 [1].  wbf16: the
+ * bfloat16 copy (raw bits) of W1, W2, w3 back to back (DCGS_MLP_BF16
+ * values); the forward and backward use these weights and the float32
+ * biases, accumulating in float32 on the matrix cores.  All arrays are
+ * device memory owned by the caller unless stated otherwise.
+ */
+#define DCGS_MLP_PARAMS 81409
+#define DCGS_MLP_BF16 80896
+#define DCGS_PREFETCH_CANDIDATES 4096
+#define DCGS_PREFETCH_IN 59
+#define DCGS_PREFETCH_HIDDEN 256
+
+/* labels [n_frames][4096] (uint8): 1 when candidate q of frame t meets the
+ * frustum of one of frames t+1 .. t+horizon (1 <= horizon <= 16), else 0.
+ * cams: host array of the whole trajectory (copied through the context's
+ * pinned staging; the call waits for the previous staging copy). */
+int dcgs_prefetch_labels(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames, int horizon,
+                         double chunk_size, uint8_t *labels, void *stream);
+
+/* Input rows for the frames listed in `frames` (host int32, n_sel <= 65535,
+ * each in [0, n_frames)): X [n_sel][4096][59] float32; cell_ids (nullable)
+ * [n_sel][4096] EncodedIDs (all ones for cells outside Eq. 6's range);
+ * y (nullable, requires labels) [n_sel][4096] = labels[frame][q]. */
+int dcgs_prefetch_features(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames,
+                           const int32_t *frames, int n_sel, double chunk_size, double pos_unit,
+                           const uint8_t *labels, float *X, uint64_t *cell_ids, uint8_t *y,
+                           void *stream);
+
+/* Forward of n rows of X [n][59] (n <= 4194240): z1, h1, z2, h2 [n][256] and
+ * logit [n], all written. */
+int dcgs_mlp_forward(dcgs_ctx *ctx, const float *theta, const uint16_t *wbf16, const float *X,
+                     int64_t n, float *z1, float *h1, float *z2, float *h2, float *logit,
+                     void *stream);
+
+/* Gradient of the weighted binary cross-entropy, mean over the n rows of
+ * pos_weight * y * softplus(-logit) + (1 - y) * softplus(logit), with
+ * respect to theta (the weights' gradient taken at their bfloat16 values),
+ * written (not accumulated) to grad [DCGS_MLP_PARAMS].  Inputs are the
+ * forward's outputs for the same X; y [n] uint8 (0 or 1).  loss (device
+ * double, nullable) gets the loss.  Reductions run in a fixed order
+ * (deterministic).  Scratch is owned by ctx. */
+int dcgs_mlp_backward(dcgs_ctx *ctx, const float *theta, const uint16_t *wbf16, const float *X,
+                      const float *z1, const float *h1, const float *z2, const float *h2,
+                      const float *logit, const uint8_t *y, int64_t n, float pos_weight,
+                      float *grad, double *loss, void *stream);
+
+/* One Adam step (step >= 1 counts from 1) on theta with moments m, v
+ * [DCGS_MLP_PARAMS] (float32, updated in place; arithmetic in float64 with
+ * bias corrections 1 - beta^step), then wbf16 = theta's weights rounded to
+ * bfloat16 (nearest, ties to even). */
+int dcgs_mlp_adam(dcgs_ctx *ctx, float *theta, uint16_t *wbf16, float *m, float *v,
+                  const float *grad, int64_t step, double lr, double beta1, double beta2,
+                  double eps, void *stream);
+
+/* wbf16 = theta's weights rounded to bfloat16 (nearest, ties to even); for
+ * a freshly initialised or loaded theta. */
+int dcgs_mlp_round(dcgs_ctx *ctx, const float *theta, uint16_t *wbf16, void *stream);
+
+/* Inference for the current frame: history = host array of the last 8
+ * cameras, history[0] the current one, history[k] k frames back.  Writes
+ * the EncodedIDs of the candidates with logit >= threshold_logit, in
+ * candidate order, to out_ids [4096] and their number to out_count (device
+ * int32); out_logit (nullable) [4096] gets every candidate's logit.
+ * Scratch is owned by ctx. */
+int dcgs_prefetch_predict(dcgs_ctx *ctx, const float *theta, const uint16_t *wbf16,
+                          const dcgs_camera *history, double chunk_size, double pos_unit,
+                          float threshold_logit, uint64_t *out_ids, int32_t *out_count,
+                          float *out_logit, void *stream);
+
 /* ---- stage timers -------------------------------------------------------- */
 
 /* Stages timed with HIP events recorded on the stream each kernel runs on. */

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libdcgs.so")
 ARCH = "gfx950"
-SOURCES = ["chunks.hip", "sort.hip", "render.hip", "stream_ops.hip", "pool.cpp", "api.cpp"]
+SOURCES = ["chunks.hip", "sort.hip", "render.hip", "stream_ops.hip", "prefetch.hip", "pool.cpp",
+           "api.cpp"]
 
 
 def hipcc() -> str:
@@ -50,7 +51,8 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread",
+           "-Wl,--no-undefined", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -94,6 +94,11 @@ void dcgs_destroy(dcgs_ctx *ctx) {
     (void)hipEventDestroy(m.b);
   }
   for (auto e : ctx->spare_events) (void)hipEventDestroy(e);
+  if (ctx->pf.staged) {
+    (void)hipEventSynchronize(ctx->pf.staged);
+    (void)hipEventDestroy(ctx->pf.staged);
+  }
+  if (ctx->pf.pinned) (void)hipHostFree(ctx->pf.pinned);
   delete ctx;
 }
 
@@ -379,6 +384,70 @@ int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n,
     std::array<int, 3> a{kShapes[bi][0], kShapes[bi][1], kShapes[bi][2]};
     ctx->tune_cache[key] = a;
     for (int k = 0; k < 3; ++k) out_shape[k] = a[k];
+  });
+}
+
+int dcgs_prefetch_labels(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames, int horizon,
+                         double chunk_size, uint8_t *labels, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::prefetch_labels(ctx, cams, n_frames, horizon, chunk_size, labels, S(stream));
+  });
+}
+
+int dcgs_prefetch_features(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames,
+                           const int32_t *frames, int n_sel, double chunk_size, double pos_unit,
+                           const uint8_t *labels, float *X, uint64_t *cell_ids, uint8_t *y,
+                           void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::prefetch_features(ctx, cams, n_frames, frames, n_sel, chunk_size, pos_unit, labels, X,
+                            cell_ids, y, S(stream));
+  });
+}
+
+int dcgs_mlp_forward(dcgs_ctx *ctx, const float *theta, const uint16_t *wbf16, const float *X,
+                     int64_t n, float *z1, float *h1, float *z2, float *h2, float *logit,
+                     void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::mlp_forward(ctx, theta, wbf16, X, n, z1, h1, z2, h2, logit, S(stream));
+  });
+}
+
+int dcgs_mlp_backward(dcgs_ctx *ctx, const float *theta, const uint16_t *wbf16, const float *X,
+                      const float *z1, const float *h1, const float *z2, const float *h2,
+                      const float *logit, const uint8_t *y, int64_t n, float pos_weight,
+                      float *grad, double *loss, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::mlp_backward(ctx, theta, wbf16, X, z1, h1, z2, h2, logit, y, n, pos_weight, grad, loss,
+                       S(stream));
+  });
+}
+
+int dcgs_mlp_adam(dcgs_ctx *ctx, float *theta, uint16_t *wbf16, float *m, float *v,
+                  const float *grad, int64_t step, double lr, double beta1, double beta2,
+                  double eps, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::mlp_adam(ctx, theta, wbf16, m, v, grad, step, lr, beta1, beta2, eps, S(stream));
+  });
+}
+
+int dcgs_mlp_round(dcgs_ctx *ctx, const float *theta, uint16_t *wbf16, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] { dcgs::mlp_round(ctx, theta, wbf16, S(stream)); });
+}
+
+int dcgs_prefetch_predict(dcgs_ctx *ctx, const float *theta, const uint16_t *wbf16,
+                          const dcgs_camera *history, double chunk_size, double pos_unit,
+                          float threshold_logit, uint64_t *out_ids, int32_t *out_count,
+                          float *out_logit, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::prefetch_predict(ctx, theta, wbf16, history, chunk_size, pos_unit, threshold_logit,
+                           out_ids, out_count, out_logit, S(stream));
   });
 }
 

@@ -97,6 +97,16 @@ struct dcgs_ctx {
   // autotuner: scratch outputs and the cache (key -> tile_w, tile_h, ppt)
   dcgs::DevBuf<float> tune_img, tune_grad;
   std::unordered_map<uint64_t, std::array<int, 3>> tune_cache;
+  // learned prefetch: camera staging and MLP scratch
+  struct Prefetch {
+    void *pinned = nullptr;
+    size_t pinned_cap = 0;
+    hipEvent_t staged = nullptr;  // last camera upload's copy
+    dcgs::DevBuf<uint8_t> cams;
+    dcgs::DevBuf<float> dz1, dz2, part, split, colpart, X, act;
+    dcgs::DevBuf<double> part_loss;
+    dcgs::DevBuf<uint64_t> ids;
+  } pf;
 };
 
 struct dcgs_state {
@@ -224,6 +234,27 @@ void launch_adam(float *params, float *m, float *v, int32_t *step, int R,
 void launch_loss_l1(const float *rgb, const float *target, int64_t count,
                     double norm, float *dl, double *stats, float *part,
                     hipStream_t st);
+
+// learned prefetch (prefetch.hip)
+void prefetch_labels(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames, int horizon,
+                     double s, uint8_t *labels, hipStream_t st);
+void prefetch_features(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames,
+                       const int32_t *frames, int n_sel, double s, double pos_unit,
+                       const uint8_t *labels, float *X, uint64_t *ids, uint8_t *y,
+                       hipStream_t st);
+void mlp_forward(dcgs_ctx *ctx, const float *theta, const uint16_t *wb, const float *X,
+                 int64_t n, float *z1, float *h1, float *z2, float *h2, float *logit,
+                 hipStream_t st);
+void mlp_backward(dcgs_ctx *ctx, const float *theta, const uint16_t *wb, const float *X,
+                  const float *z1, const float *h1, const float *z2, const float *h2,
+                  const float *logit, const uint8_t *y, int64_t n, float pos_weight,
+                  float *grad, double *loss, hipStream_t st);
+void mlp_adam(dcgs_ctx *ctx, float *theta, uint16_t *wb, float *m, float *v, const float *grad,
+              int64_t step, double lr, double beta1, double beta2, double eps, hipStream_t st);
+void mlp_round(dcgs_ctx *ctx, const float *theta, uint16_t *wb, hipStream_t st);
+void prefetch_predict(dcgs_ctx *ctx, const float *theta, const uint16_t *wb,
+                      const dcgs_camera *hist, double s, double pos_unit, float threshold,
+                      uint64_t *out_ids, int32_t *out_count, float *out_logit, hipStream_t st);
 
 // exclusive scan of in (or of in[gather[i]] when gather != null), n
 // elements; out has n + 1 entries (out[n] = total).

@@ -91,6 +91,13 @@ SIGNATURES = {
     "dcgs_loss_l1": (INT, [P, P, P, I64, DBL, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
     "dcgs_autotune": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
+    "dcgs_prefetch_labels": (INT, [P, P, INT, INT, DBL, P, P]),
+    "dcgs_prefetch_features": (INT, [P, P, INT, P, INT, DBL, DBL, P, P, P, P, P]),
+    "dcgs_mlp_forward": (INT, [P, P, P, P, I64, P, P, P, P, P, P]),
+    "dcgs_mlp_backward": (INT, [P, P, P, P, P, P, P, P, P, P, I64, C.c_float, P, P, P]),
+    "dcgs_mlp_adam": (INT, [P, P, P, P, P, P, I64, DBL, DBL, DBL, DBL, P]),
+    "dcgs_mlp_round": (INT, [P, P, P, P]),
+    "dcgs_prefetch_predict": (INT, [P, P, P, P, DBL, DBL, C.c_float, P, P, P, P]),
     "dcgs_profile_enable": (INT, [P, INT]),
     "dcgs_profile_read": (INT, [P, P, P, INT]),
     "dcgs_state_info": (INT, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)]),
