@@ -286,6 +286,73 @@ int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params,
                   int force, int *out_shape, double *times_ms, int *n_shapes,
                   void *stream);
 
+/* ---- graph-captured mapping window ---------------------------------------- */
+/*
+ * One batched mapping iteration over a window of keyframes (Sec. III-E
+ * "Optimization", one Adam step per window): compaction of the window's
+ * chunks (a kernel launched before the graph), then one HIP graph holding
+ * the projection, depth sort, pair emission, tile sort, ranges, forward
+ * raster, L1 loss, backward raster, projection backward and the Adam step
+ * into the pool.  The graph is recorded once at creation; each launch
+ * replays it.  Results equal dcgs_render_fwd + dcgs_loss_l1 +
+ * dcgs_render_bwd + dcgs_adam_step on the same window bit for bit.
+ *
+ * Grids are sized for `capacity` Gaussians and `pair_capacity` (tile,
+ * Gaussian) pairs; the kernels read the real counts on the device.  A
+ * window whose pairs exceed pair_capacity draws nothing and leaves the pool
+ * unchanged, and so does every later launch: the next launch that reuses
+ * its staging block (two launches later), or dcgs_window_sync, returns
+ * DCGS_E_CAPACITY with the pair count needed; rebuild the window with a
+ * larger pair_capacity and launch the skipped windows again, in order.
+ * All buffers are caller-owned device memory that must stay valid while the
+ * window exists; `targets` is read at every launch (write the window's
+ * targets into it, on the launch stream, before launching).
+ */
+typedef struct dcgs_window dcgs_window;
+
+typedef struct dcgs_window_config {
+  int sh_degree;                 /* must equal the pool's */
+  int width, height, n_views;    /* every camera of a launch has this size; 1..16 views */
+  int tile_w, tile_h, pixels_per_lane;  /* a supported raster shape (see dcgs_autotune) */
+  int64_t capacity;              /* Gaussians: row stride of params and grad;
+                                    capacity * n_views < 2^31 */
+  int64_t pair_capacity;         /* (tile, Gaussian) pairs, < 2^31 */
+  float bg[3];
+  double loss_norm;              /* the L1 loss is sum |rgb - target| / loss_norm */
+  dcgs_adam_config adam;
+  float *params, *grad;          /* [R][capacity] */
+  int32_t *src;                  /* [capacity] pool slot of each compacted Gaussian */
+  uint16_t *gmask;               /* [capacity] view mask of each compacted Gaussian */
+  float *rgb, *depth, *dl_drgb;  /* [V][3][H][W], [V][H][W], [V][3][H][W] */
+  const float *targets;          /* [V][3][H][W] */
+  double *stats;                 /* [2]: sum |d| and sum d^2 of the last launch */
+} dcgs_window_config;
+
+/* SYNC.  Allocate the window's buffers and record its two graph instances. */
+int dcgs_window_create(dcgs_ctx *ctx, dcgs_pool *pool, const dcgs_window_config *cfg,
+                       dcgs_window **out);
+/* Waits for launched work, then frees the window. */
+void dcgs_window_destroy(dcgs_window *win);
+
+/* Enqueue one window on `stream`: compaction of the chunks ids (host,
+ * n_ids, ascending, resident: call dcgs_pool_require first) with view masks
+ * masks (host), then the graph, for the n_views host cameras cams.
+ * *n_active (nullable) gets the compacted count.  Host-asynchronous except
+ * that it waits for the launch two windows back (its staging block) and
+ * reports DCGS_E_CAPACITY if that or any later launch overflowed. */
+int dcgs_window_launch(dcgs_window *win, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                       const dcgs_camera *cams, int64_t *n_active, void *stream);
+
+/* SYNC.  Wait for every launch; DCGS_E_CAPACITY if one overflowed, with
+ * *pairs_required (nullable) = the pair count that did not fit and *skipped
+ * (nullable) = how many of the most recent launches (0..2) changed nothing
+ * and must be launched again after a rebuild.  After DCGS_E_CAPACITY every
+ * further launch fails until the window is rebuilt. */
+int dcgs_window_sync(dcgs_window *win, int64_t *pairs_required, int *skipped);
+
+/* SYNC.  Pair count of the last completed launch. */
+int dcgs_window_pairs(dcgs_window *win, int64_t *n_pairs);
+
 /* ---- learned chunk prefetch --------------------------------------------- */
 /*
  * Not part of the paper's method: the paper selects chunks by the exact

@@ -387,6 +387,33 @@ int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n,
   });
 }
 
+int dcgs_window_create(dcgs_ctx *ctx, dcgs_pool *pool, const dcgs_window_config *cfg,
+                       dcgs_window **out) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] { dcgs::window_create(ctx, pool, cfg, out); });
+}
+
+void dcgs_window_destroy(dcgs_window *win) { dcgs::window_destroy(win); }
+
+int dcgs_window_launch(dcgs_window *win, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                       const dcgs_camera *cams, int64_t *n_active, void *stream) {
+  if (!win) return DCGS_E_INVALID;
+  return guarded(dcgs::window_ctx(win), [&] {
+    dcgs::window_launch(win, ids, masks, n_ids, cams, n_active, S(stream));
+  });
+}
+
+int dcgs_window_sync(dcgs_window *win, int64_t *pairs_required, int *skipped) {
+  if (!win) return DCGS_E_INVALID;
+  return guarded(dcgs::window_ctx(win),
+                 [&] { dcgs::window_sync(win, pairs_required, skipped); });
+}
+
+int dcgs_window_pairs(dcgs_window *win, int64_t *n_pairs) {
+  if (!win || !n_pairs) return DCGS_E_INVALID;
+  return guarded(dcgs::window_ctx(win), [&] { dcgs::window_pairs(win, n_pairs); });
+}
+
 int dcgs_prefetch_labels(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames, int horizon,
                          double chunk_size, uint8_t *labels, void *stream) {
   if (!ctx) return DCGS_E_INVALID;

@@ -131,6 +131,11 @@ struct dcgs_state {
   // per pair
   dcgs::DevBuf<uint64_t> pairs, pairs_tmp;
   dcgs::DevBuf<float4> partial;  // [3 * P] per-pair gradient partials
+  // launch plan: grids sized for n_grid Gaussians, record planes rs apart,
+  // pcap pair slots (planned windows; eager forwards size them exactly).
+  // The device counters [n, nr, pairs, overflow, sticky overflow] follow
+  // the camera constants in cam_dev.
+  int64_t n_grid = 0, rs = 0, pcap = 0;
   // per tile
   dcgs::DevBuf<int2> ranges;
   dcgs::DevBuf<int> frontier;
@@ -140,6 +145,7 @@ struct dcgs_state {
   // radix sort histograms
   dcgs::DevBuf<uint32_t> hist;
   dcgs::DevBuf<float> grad2d;  // [10][n] when the caller passes none
+  dcgs::DevBuf<uint32_t> scan_part;  // block totals of the pair-count scan
 };
 
 struct HostChunk {
@@ -227,10 +233,12 @@ void launch_select(const dcgs_camera *cams, int n_views, const uint64_t *ids,
 void launch_compact(const float *pool, int R, const int4 *seg, int n_seg,
                     const uint16_t *seg_mask, float *out, int64_t out_stride,
                     int32_t *out_src, uint16_t *out_gmask, hipStream_t st);
+// With cnt non-null, n is a capacity and the count is cnt[0]; nothing is
+// updated when cnt[3] != 0 (the window's pair capacity overflowed).
 void launch_adam(float *params, float *m, float *v, int32_t *step, int R,
                  const int32_t *src, const float *grad, int64_t n,
                  int64_t grad_stride, const dcgs_adam_config &cfg,
-                 hipStream_t st);
+                 hipStream_t st, const int64_t *cnt = nullptr);
 void launch_loss_l1(const float *rgb, const float *target, int64_t count,
                     double norm, float *dl, double *stats, float *part,
                     hipStream_t st);
@@ -258,18 +266,20 @@ void prefetch_predict(dcgs_ctx *ctx, const float *theta, const uint16_t *wb,
 
 // exclusive scan of in (or of in[gather[i]] when gather != null), n
 // elements; out has n + 1 entries (out[n] = total).
+// With n_dev non-null, n is a capacity (grids are sized for it) and the
+// element count is min(*n_dev, n), read on the device (graph capture).
 void scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out,
-              int64_t n, uint32_t *part, hipStream_t st);
+              int64_t n, uint32_t *part, hipStream_t st, const int64_t *n_dev = nullptr);
 size_t scan_part_size(int64_t n);
 
 // stable LSD radix sort of (key, value) u32 pairs over key bits [0, bits).
 // Result ends in keys/vals; tmp buffers are n entries each.
 void sort_u32_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
                     uint32_t *vtmp, int64_t n, int bits, DevBuf<uint32_t> &hist,
-                    hipStream_t st);
+                    hipStream_t st, const int64_t *n_dev = nullptr);
 // stable LSD radix sort of u64 words by bits [lo, lo + bits).
 void sort_u64_bits(uint64_t *a, uint64_t *tmp, int64_t n, int lo, int bits,
-                   DevBuf<uint32_t> &hist, hipStream_t st);
+                   DevBuf<uint32_t> &hist, hipStream_t st, const int64_t *n_dev = nullptr);
 
 void render_forward(dcgs_state *s, const float *params, int64_t n,
                     int64_t stride, const uint16_t *gmask, int mask_shift, hipStream_t st,
@@ -278,6 +288,34 @@ void render_backward(dcgs_state *s, const float *params, int64_t n,
                      int64_t stride, const float *dl_drgb,
                      const float *dl_ddepth, float *grad, int64_t grad_stride,
                      int accumulate, float *grad2d, hipStream_t st);
+// Planned (graph-capturable) rendering: buffers for n_cap Gaussians and
+// pcap pairs are allocated by render_plan; the per-window counts and
+// cameras come from the staging block (render_stage writes it, the caller
+// copies it to the device block at state->cam_dev); render_forward_planned
+// and render_backward then enqueue work with no host synchronisation.
+void render_plan(dcgs_state *s, int64_t n_cap, int64_t pcap);
+size_t render_stage_bytes();
+void render_stage(const dcgs_state *s, void *pinned, int64_t n);
+void render_forward_planned(dcgs_state *s, const float *params, int64_t stride,
+                            const uint16_t *gmask, hipStream_t st, float *rgb, float *depth,
+                            float *T);
+int64_t *render_counters(dcgs_state *s, hipStream_t st);
+bool raster_shape_supported(int tw, int th, int ppt);
+// Scratch (32-bit words) of one radix pass over n keys with 8-bit digits.
+size_t radix_scratch(int64_t n);
+
+// graph-captured mapping windows (window.cpp)
+void window_create(dcgs_ctx *ctx, dcgs_pool *pool, const dcgs_window_config *cfg,
+                   dcgs_window **out);
+void window_destroy(dcgs_window *w);
+void window_launch(dcgs_window *w, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                   const dcgs_camera *cams, int64_t *n_active, hipStream_t st);
+void window_sync(dcgs_window *w, int64_t *pairs_required, int *skipped);
+void window_pairs(dcgs_window *w, int64_t *n_pairs);
+dcgs_ctx *window_ctx(dcgs_window *w);
+void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int n_ids,
+                  float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
+                  int64_t capacity, int64_t *n_out, hipStream_t st);
 void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values,
                   int32_t *ranges, int32_t *counts, float *records,
                   int32_t *box, int32_t *last, hipStream_t st);

@@ -233,17 +233,19 @@ __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, in
 }
 
 // One thread per Gaussian; it projects the Gaussian into every view whose
-// bit is set in its chunk's view mask.  Record r = v * n + g.
+// bit is set in its chunk's view mask.  Record r = v * n + g; the three
+// record planes are RS apart.  cnt[0] = n (device counter; the grid may be
+// sized for a capacity).
 __global__ void __launch_bounds__(256)
-    k_preprocess(const float *__restrict__ P, int64_t n, int64_t stride, int deg,
-                 const CamD *__restrict__ cams, int V, const uint16_t *__restrict__ gmask,
-                 int mask_shift, int TW, int TH, float4 *__restrict__ rec,
-                 uint32_t *__restrict__ zkey,
+    k_preprocess(const float *__restrict__ P, const int64_t *__restrict__ cnt, int64_t stride,
+                 int deg, const CamD *__restrict__ cams, int V,
+                 const uint16_t *__restrict__ gmask, int mask_shift, int TW, int TH,
+                 float4 *__restrict__ rec, int64_t RS, uint32_t *__restrict__ zkey,
                  uint32_t *__restrict__ sortkey, uint32_t *__restrict__ order,
                  uint32_t *__restrict__ count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = cnt[0];
   if (i >= n) return;
-  const int64_t nr = n * V;
   Geo g;
   load_gauss(P, stride, i, g);
   const unsigned m = gmask ? ((unsigned)gmask[i] >> mask_shift) : 0xFFFFu;
@@ -263,8 +265,8 @@ __global__ void __launch_bounds__(256)
       count[r] = 0;
       sortkey[r] = kCulledKey;
       rec[r] = make_float4(0, 0, 0, 0);
-      rec[nr + r] = make_float4(0, 0, 0, 0);
-      rec[2 * nr + r] = make_float4(0, 0, 0, 0);
+      rec[RS + r] = make_float4(0, 0, 0, 0);
+      rec[2 * RS + r] = make_float4(0, 0, 0, 0);
       continue;
     }
     double dir[3], dn, Y[16], raw[3];
@@ -275,28 +277,44 @@ __global__ void __launch_bounds__(256)
     const double id = 1.0 / g.det;
     rec[r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(g.c * id),
                          (float)(-g.b * id));
-    rec[nr + r] = make_float4((float)(g.a * id), (float)g.o, (float)fmax(raw[0], 0.0),
+    rec[RS + r] = make_float4((float)(g.a * id), (float)g.o, (float)fmax(raw[0], 0.0),
                               (float)fmax(raw[1], 0.0));
-    rec[2 * nr + r] = make_float4((float)fmax(raw[2], 0.0), zf,
+    rec[2 * RS + r] = make_float4((float)fmax(raw[2], 0.0), zf,
                                   __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
                                   __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
   }
 }
 
-__global__ void k_rank(const uint32_t *__restrict__ order, int64_t n,
+__global__ void k_rank(const uint32_t *__restrict__ order, const int64_t *__restrict__ cnt,
                        uint32_t *__restrict__ rank_of) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) rank_of[order[j]] = (uint32_t)j;
+  if (j < cnt[1]) rank_of[order[j]] = (uint32_t)j;
+}
+
+// Pair total = scan[nr].  cnt[2] = pairs to process; cnt[3] = the total
+// when it exceeds the pair capacity (or any earlier window of this state
+// overflowed, cnt[4] sticky), else 0.  Every later kernel of the window
+// does nothing when cnt[3] != 0.
+__global__ void k_pairs_total(const uint32_t *__restrict__ scan, int64_t *__restrict__ cnt,
+                              int64_t pcap) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t total = scan[cnt[1]];
+  const bool over = total > pcap || cnt[4] != 0;
+  cnt[2] = over ? 0 : total;
+  cnt[3] = over ? (total > 0 ? total : 1) : 0;
+  if (over) cnt[4] = 1;
 }
 
 // Pairs of record r = v n + g: (global tile v T + t) << 32 | r, emitted in
 // depth order, tiles of a record row-major.
 __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
                        const uint32_t *__restrict__ scan, const float4 *__restrict__ recC,
-                       int64_t nr, int64_t n, int TW, int TH, int tiles_x, int tiles_per_view,
-                       uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
+                       const int64_t *__restrict__ cnt, int TW, int TH, int tiles_x,
+                       int tiles_per_view, uint64_t *__restrict__ pairs,
+                       uint32_t *__restrict__ pair_off) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nr) return;
+  const int64_t n = cnt[0], nr = cnt[1];
+  if (j >= nr || cnt[3] != 0) return;
   const uint32_t g = order[j];
   const uint32_t view_base = (uint32_t)(g / (uint64_t)n) * (uint32_t)tiles_per_view;
   const uint32_t c = count[g];
@@ -313,10 +331,11 @@ __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__res
       pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | g;
 }
 
-__global__ void k_ranges(const uint64_t *__restrict__ pairs, int64_t P, int n_tiles,
-                         int2 *__restrict__ ranges) {
+__global__ void k_ranges(const uint64_t *__restrict__ pairs, const int64_t *__restrict__ cnt,
+                         int n_tiles, int2 *__restrict__ ranges) {
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
+  const int64_t P = cnt[3] != 0 ? 0 : cnt[2];  // an overflowed window draws nothing
   auto lower = [&](uint32_t key) {
     int64_t lo = 0, hi = P;
     while (lo < hi) {
@@ -369,7 +388,7 @@ __device__ __forceinline__ Sample sample(int px, int py, const float4 &A, const 
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_fwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
-                 const float4 *__restrict__ rec, int64_t n, int W, int H, int tiles_x,
+                 const float4 *__restrict__ rec, int64_t RS, int W, int H, int tiles_x,
                  int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  float *__restrict__ rgb, float *__restrict__ depth, float *__restrict__ Tout,
                  float *__restrict__ Tstate, int *__restrict__ last_out) {
@@ -411,8 +430,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     if (p < rg.y) {
       const uint32_t g = (uint32_t)pairs[p];
       sA[threadIdx.x] = rec[g];
-      sB[threadIdx.x] = rec[n + g];
-      sC[threadIdx.x] = rec[2 * n + g];
+      sB[threadIdx.x] = rec[RS + g];
+      sC[threadIdx.x] = rec[2 * RS + g];
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
@@ -522,7 +541,7 @@ __device__ __forceinline__ int bitrev4(int l) {
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_bwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
-                 const float4 *__restrict__ rec, int64_t n, int W, int H, int tiles_x,
+                 const float4 *__restrict__ rec, int64_t RS, int W, int H, int tiles_x,
                  int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  const float *__restrict__ Tstate, const int *__restrict__ last_in,
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
@@ -592,8 +611,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const uint32_t g = (uint32_t)pairs[end - 1 - threadIdx.x];
       sG[threadIdx.x] = g;
       sA[threadIdx.x] = rec[g];
-      sB[threadIdx.x] = rec[n + g];
-      sC[threadIdx.x] = rec[2 * n + g];
+      sB[threadIdx.x] = rec[RS + g];
+      sC[threadIdx.x] = rec[2 * RS + g];
     }
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
@@ -771,16 +790,17 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
 // per-tile partials in emission order (only tiles whose backward reached it),
 // written as ten planes s2d[c][r].  Integer box from the packed record.
 __global__ void __launch_bounds__(256)
-    k_sum_partials(int64_t nr, int TW, int TH, int tiles_x, int tiles_per_view, int64_t n,
-                   const float4 *__restrict__ recC, const uint32_t *__restrict__ count,
-                   const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
-                   const int *__restrict__ frontier, const float4 *__restrict__ partial,
-                   float *__restrict__ s2d) {
+    k_sum_partials(const int64_t *__restrict__ cnt, int64_t RS, int TW, int TH, int tiles_x,
+                   int tiles_per_view, const float4 *__restrict__ recC,
+                   const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
+                   const uint32_t *__restrict__ rank_of, const int *__restrict__ frontier,
+                   const float4 *__restrict__ partial, float *__restrict__ s2d) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nr) return;
-  const uint32_t cnt = count[r];
+  const int64_t n = cnt[0], nr = cnt[1];
+  if (r >= nr || cnt[3] != 0) return;
+  const uint32_t tiles = count[r];
   float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (cnt > 0) {
+  if (tiles > 0) {
     const float4 C = recC[r];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
     const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
@@ -789,7 +809,7 @@ __global__ void __launch_bounds__(256)
     const int tile_base = (int)(r / n) * tiles_per_view;
     const uint32_t base = pair_off[r];
     const int rank = (int)rank_of[r];
-    for (uint32_t k = 0; k < cnt; ++k) {
+    for (uint32_t k = 0; k < tiles; ++k) {
       const int t = tile_base + (ty0 + (int)k / wc) * tiles_x + tx0 + (int)k % wc;
       if (frontier[t] < rank) continue;
       const float4 p0 = partial[3 * (int64_t)(base + k)];
@@ -801,7 +821,7 @@ __global__ void __launch_bounds__(256)
     }
   }
 #pragma unroll
-  for (int c = 0; c < 10; ++c) s2d[c * nr + r] = s[c];
+  for (int c = 0; c < 10; ++c) s2d[c * RS + r] = s[c];
 }
 
 // Projection backward over all views: one thread per Gaussian; record
@@ -811,14 +831,14 @@ __global__ void __launch_bounds__(256)
 // accumulate in registers; the SH rows are added in place view by view.
 template <int DEG>
 __global__ void __launch_bounds__(256)
-    k_preprocess_bwd(const float *__restrict__ P, int64_t n, int64_t stride,
-                     const CamD *__restrict__ cams, int V, const uint32_t *__restrict__ count,
-                     const float *__restrict__ s2d, float *__restrict__ grad, int64_t gstride,
-                     int accumulate) {
+    k_preprocess_bwd(const float *__restrict__ P, const int64_t *__restrict__ cnt,
+                     int64_t stride, const CamD *__restrict__ cams, int V,
+                     const uint32_t *__restrict__ count, const float *__restrict__ s2d,
+                     int64_t RS, float *__restrict__ grad, int64_t gstride, int accumulate) {
   constexpr int K = (DEG + 1) * (DEG + 1), R = 11 + 3 * K;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int64_t nr = n * V;
+  const int64_t n = cnt[0];
+  if (i >= n || cnt[3] != 0) return;
   float acc[11];
 #pragma unroll
   for (int r = 0; r < 11; ++r) acc[r] = accumulate ? grad[r * gstride + i] : 0.0f;
@@ -831,7 +851,7 @@ __global__ void __launch_bounds__(256)
     load_geo(P, stride, i, cam, g);
     float s[10];
 #pragma unroll
-    for (int c = 0; c < 10; ++c) s[c] = s2d[c * nr + rr];
+    for (int c = 0; c < 10; ++c) s[c] = s2d[c * RS + rr];
     double out[11], Yb[16], graw[3];
     param_grads(P, stride, i, DEG, g, cam, s, out, Yb, graw);
 #pragma unroll
@@ -862,11 +882,12 @@ __global__ void k_export_keys(const uint64_t *__restrict__ pairs, int64_t P,
   if (values) values[k] = (int32_t)g;
 }
 
-__global__ void k_export_rec(const float4 *__restrict__ rec, const uint32_t *__restrict__ count,
-                             int64_t n, float *__restrict__ out, int32_t *__restrict__ box) {
+__global__ void k_export_rec(const float4 *__restrict__ rec, int64_t RS,
+                             const uint32_t *__restrict__ count, int64_t n,
+                             float *__restrict__ out, int32_t *__restrict__ box) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float4 A = rec[i], B = rec[n + i], C = rec[2 * n + i];
+  const float4 A = rec[i], B = rec[RS + i], C = rec[2 * RS + i];
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int i0 = bx & 0xFFFF, j0 = by & 0xFFFF;
   if (out) {
@@ -897,12 +918,16 @@ __global__ void k_copy_u32_as_i32(const uint32_t *__restrict__ a, int64_t n, int
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+__global__ void k_fill_i64(int64_t *__restrict__ a, int64_t n, int64_t v) {
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a[i] = v;
+}
+
 template <int TW, int TH, int PPT>
 void launch_fwd_t(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *T) {
   const int nt = s->tiles_x * s->tiles_y * s->V;
   const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
   hipLaunchKernelGGL((k_raster_fwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
-                     s->pairs.p, s->ranges.p, s->rec.p, s->n * s->V, s->W, s->H, s->tiles_x, nt,
+                     s->pairs.p, s->ranges.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
                      s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], rgb, depth, T,
                      s->T_final.p, s->last.p);
   DCGS_LAUNCH_CHECK();
@@ -913,7 +938,7 @@ void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const flo
   const int nt = s->tiles_x * s->tiles_y * s->V;
   const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
   hipLaunchKernelGGL((k_raster_bwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
-                     s->pairs.p, s->ranges.p, s->rec.p, s->n * s->V, s->W, s->H, s->tiles_x, nt,
+                     s->pairs.p, s->ranges.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
                      s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], s->T_final.p,
                      s->last.p, dl_drgb, dl_ddepth, s->pair_off.p, s->rank_of.p, s->partial.p,
                      s->frontier.p);
@@ -946,105 +971,207 @@ void launch_bwd(dcgs_state *s, hipStream_t st, const float *dl_drgb, const float
   throw Error{DCGS_E_INVALID, "unsupported raster shape"};
 }
 
-}  // namespace
+// Camera constants and the two host-known counts (n, nr) travel to the
+// device in one copy from pinned staging: [CamD x kMaxViews][int64 x 2].
+// On the device the block continues with the counters the kernels write:
+// [n, nr, pairs, overflow, sticky overflow, unused x 3].
+constexpr size_t kCamBytes = kMaxViews * sizeof(CamD);
+constexpr size_t kStageBytes = kCamBytes + 2 * sizeof(int64_t);
+constexpr size_t kDevBytes = kCamBytes + 8 * sizeof(int64_t);
 
-void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
-                    const uint16_t *gmask, int mask_shift, hipStream_t st, float *rgb,
-                    float *depth, float *T) {
-  dcgs_ctx *ctx = s->ctx;
+void stage_cams(const dcgs_state *s, void *pinned, int64_t n) {
+  CamD *hc = (CamD *)pinned;
+  for (int v = 0; v < s->V; ++v) hc[v] = make_cam(s->cams[v]);
+  int64_t *c = (int64_t *)((char *)pinned + kCamBytes);
+  c[0] = n;
+  c[1] = n * s->V;
+}
+
+// Device block of a state (cameras, then counters); allocated once, the
+// counters zeroed then.
+int64_t *counters(dcgs_state *s, hipStream_t st) {
+  if (!s->cam_dev.p) {
+    s->cam_dev.need(kDevBytes);
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st,
+                       (int64_t *)(s->cam_dev.p + kCamBytes), (int64_t)8, (int64_t)0);
+    DCGS_LAUNCH_CHECK();
+  }
+  return (int64_t *)(s->cam_dev.p + kCamBytes);
+}
+
+// Buffers for records of n_grid Gaussians (record planes RS = n_grid * V
+// apart) and tile/pixel state.  No allocation happens when they are large
+// enough already.
+void size_buffers(dcgs_state *s, int64_t n_grid) {
   const int V = s->V;
-  const int tpv = s->tiles_x * s->tiles_y;
-  const int nt = tpv * V;
-  const int64_t nr = n * V;
+  const int nt = s->tiles_x * s->tiles_y * V;
+  const int64_t nr = n_grid * V;
   const int64_t HW = (int64_t)s->W * s->H;
-  s->n = n;
-  // cameras -> device (the pinned staging copy is complete: every forward
-  // synchronises its stream before returning)
-  if (!s->cam_pinned) DCGS_HIP(hipHostMalloc(&s->cam_pinned, kMaxViews * sizeof(CamD), hipHostMallocDefault));
-  CamD *hc = (CamD *)s->cam_pinned;
-  for (int v = 0; v < V; ++v) hc[v] = make_cam(s->cams[v]);
-  CamD *dc = (CamD *)s->cam_dev.need(kMaxViews * sizeof(CamD));
-  DCGS_HIP(hipMemcpyAsync(dc, hc, V * sizeof(CamD), hipMemcpyHostToDevice, st));
-  float4 *rec = s->rec.need(3 * (size_t)nr + 1);
-  uint32_t *zkey = s->zkey.need(nr + 1), *cnt = s->count.need(nr + 1);
-  uint32_t *order = s->order.need(nr + 1), *sortkey = s->key_tmp.need(2 * (size_t)nr + 2);
-  uint32_t *vtmp = s->val_tmp.need(nr + 1);
+  s->rs = nr;
+  s->rec.need(3 * (size_t)nr + 1);
+  s->zkey.need(nr + 1);
+  s->count.need(nr + 1);
+  s->order.need(nr + 1);
+  s->key_tmp.need(2 * (size_t)nr + 2);
+  s->val_tmp.need(nr + 1);
   s->rank_of.need(nr + 1);
   s->pair_off.need(nr + 1);
-  uint32_t *scan = s->scan.need(nr + 2);
+  s->scan.need(nr + 2);
   s->ranges.need(nt + 1);
   s->frontier.need(nt + 1);
   s->T_final.need(V * HW + 1);
   s->last.need(V * HW + 1);
-  if (n > 0) {
+  s->scan_part.need(scan_part_size(nr) + 2);
+}
+
+// Projection, depth order and pair count for a grid of n_grid Gaussians
+// (the device counter holds the real n <= n_grid).
+void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t stride,
+                   const uint16_t *gmask, int mask_shift, int64_t pcap, hipStream_t st) {
+  dcgs_ctx *ctx = s->ctx;
+  const int V = s->V;
+  const int64_t RS = s->rs, nr = n_grid * V;
+  int64_t *cnt = counters(s, st);
+  const CamD *dc = (const CamD *)s->cam_dev.p;
+  uint32_t *sortkey = s->key_tmp.p, *order = s->order.p;
+  if (n_grid > 0) {
     StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n, 256)), dim3(256), 0, st, params, n,
-                       stride, s->sh_degree, dc, V, gmask, mask_shift, s->TW, s->TH, rec, zkey,
-                       sortkey, order, cnt);
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st, params,
+                       cnt, stride, s->sh_degree, dc, V, gmask, mask_shift, s->TW, s->TH,
+                       s->rec.p, RS, s->zkey.p, sortkey, order, s->count.p);
     DCGS_LAUNCH_CHECK();
   }
   if (nr > 0) {
     StageTimer ts(ctx, DCGS_STAGE_DEPTH_SORT, st);
     // depth order of all records: stable sort of the float32 depth bits
-    sort_u32_pairs(sortkey, order, sortkey + nr + 1, vtmp, nr, 32, s->hist, st);
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, nr,
+    sort_u32_pairs(sortkey, order, sortkey + RS + 1, s->val_tmp.p, nr, 32, s->hist, st,
+                   cnt + 1);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, cnt,
                        s->rank_of.p);
     DCGS_LAUNCH_CHECK();
   }
-  uint32_t *part = s->ctx->scan_part.need(scan_part_size(nr) + 2);
-  {
-    StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-    scan_u32(cnt, order, scan, nr, part, st);
-  }
-  uint32_t total = 0;
-  DCGS_HIP(hipMemcpyAsync(&total, scan + nr, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  DCGS_HIP(hipStreamSynchronize(st));
-  s->n_pairs = total;
-  uint64_t *pairs = s->pairs.need((size_t)total + 1);
-  uint64_t *ptmp = s->pairs_tmp.need((size_t)total + 1);
-  s->partial.need(3 * (size_t)total + 3);
+  StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
+  scan_u32(s->count.p, order, s->scan.p, nr, s->scan_part.p, st, cnt + 1);
+  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, st, s->scan.p, cnt, pcap);
+  DCGS_LAUNCH_CHECK();
+}
+
+// Pair emission, tile sort, ranges and the forward raster for pcap pair
+// slots (the device counter holds the real count).
+void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, float *rgb,
+                  float *depth, float *T) {
+  dcgs_ctx *ctx = s->ctx;
+  const int V = s->V;
+  const int tpv = s->tiles_x * s->tiles_y;
+  const int nt = tpv * V;
+  const int64_t nr = n_grid * V;
+  int64_t *cnt = counters(s, st);
   if (nr > 0) {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, cnt, scan,
-                       rec + 2 * nr, nr, n, s->TW, s->TH, s->tiles_x, tpv, pairs, s->pair_off.p);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->order.p,
+                       s->count.p, s->scan.p, s->rec.p + 2 * s->rs, cnt, s->TW, s->TH,
+                       s->tiles_x, tpv, s->pairs.p, s->pair_off.p);
     DCGS_LAUNCH_CHECK();
   }
   int tile_bits = 0;
   while ((1 << tile_bits) < nt) ++tile_bits;
-  if (total > 0) {
+  if (pcap > 0) {
     StageTimer tt(ctx, DCGS_STAGE_TILE_SORT, st);
-    sort_u64_bits(pairs, ptmp, total, 32, tile_bits, s->hist, st);
+    sort_u64_bits(s->pairs.p, s->pairs_tmp.p, pcap, 32, tile_bits, s->hist, st, cnt + 2);
   }
   {
     StageTimer tr(ctx, DCGS_STAGE_RANGES, st);
-    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(nt, 256)), dim3(256), 0, st, pairs,
-                       (int64_t)total, nt, s->ranges.p);
+    hipLaunchKernelGGL(k_ranges, dim3(blocks_for(nt, 256)), dim3(256), 0, st, s->pairs.p, cnt,
+                       nt, s->ranges.p);
     DCGS_LAUNCH_CHECK();
   }
   StageTimer tf(ctx, DCGS_STAGE_RASTER_FWD, st);
   launch_fwd(s, st, rgb, depth, T);
 }
 
+void size_pairs(dcgs_state *s, int64_t pcap) {
+  s->pairs.need((size_t)pcap + 1);
+  s->pairs_tmp.need((size_t)pcap + 1);
+  s->partial.need(3 * (size_t)pcap + 3);
+}
+
+}  // namespace
+
+void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
+                    const uint16_t *gmask, int mask_shift, hipStream_t st, float *rgb,
+                    float *depth, float *T) {
+  s->n = n;
+  s->n_grid = n;
+  size_buffers(s, n);
+  int64_t *cnt = counters(s, st);
+  // cameras and counts -> device (the pinned staging copy is complete:
+  // every forward synchronises its stream before returning)
+  if (!s->cam_pinned) DCGS_HIP(hipHostMalloc(&s->cam_pinned, kStageBytes, hipHostMallocDefault));
+  stage_cams(s, s->cam_pinned, n);
+  DCGS_HIP(hipMemcpyAsync(s->cam_dev.p, s->cam_pinned, kStageBytes, hipMemcpyHostToDevice, st));
+  // no pair capacity limit here: the pair buffers are sized after the count
+  enqueue_front(s, params, n, stride, gmask, mask_shift, INT64_MAX, st);
+  int64_t total = 0;
+  DCGS_HIP(hipMemcpyAsync(&total, cnt + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  DCGS_HIP(hipStreamSynchronize(st));
+  s->n_pairs = total;
+  size_pairs(s, total);
+  enqueue_back(s, n, total, st, rgb, depth, T);
+}
+
+void render_plan(dcgs_state *s, int64_t n_cap, int64_t pcap) {
+  s->n_grid = n_cap;
+  s->pcap = pcap;
+  size_buffers(s, n_cap);
+  size_pairs(s, pcap);
+  s->hist.need(radix_scratch(std::max(s->rs, pcap)));
+}
+
+bool raster_shape_supported(int tw, int th, int ppt) {
+#define X(a, b, c) \
+  if (tw == a && th == b && ppt == c) return true;
+  DCGS_RASTER_SHAPES(X)
+#undef X
+  return false;
+}
+
+size_t render_stage_bytes() { return kStageBytes; }
+
+void render_stage(const dcgs_state *s, void *pinned, int64_t n) { stage_cams(s, pinned, n); }
+
+void render_forward_planned(dcgs_state *s, const float *params, int64_t stride,
+                            const uint16_t *gmask, hipStream_t st, float *rgb, float *depth,
+                            float *T) {
+  enqueue_front(s, params, s->n_grid, stride, gmask, 0, s->pcap, st);
+  enqueue_back(s, s->n_grid, s->pcap, st, rgb, depth, T);
+}
+
+int64_t *render_counters(dcgs_state *s, hipStream_t st) { return counters(s, st); }
+
 void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
                      const float *dl_drgb, const float *dl_ddepth, float *grad,
                      int64_t grad_stride, int accumulate, float *grad2d, hipStream_t st) {
+  (void)n;
   {
     StageTimer tb(s->ctx, DCGS_STAGE_RASTER_BWD, st);
     launch_bwd(s, st, dl_drgb, dl_ddepth);
   }
-  if (n > 0) {
+  const int64_t n_grid = s->n_grid;
+  if (n_grid > 0) {
     StageTimer tp(s->ctx, DCGS_STAGE_PREPROCESS_BWD, st);
     const CamD *dc = (const CamD *)s->cam_dev.p;
     const int tpv = s->tiles_x * s->tiles_y;
-    const int64_t nr = n * s->V;
-    float *s2d = grad2d ? grad2d : s->grad2d.need(10 * (size_t)nr + 1);
-    hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, nr, s->TW,
-                       s->TH, s->tiles_x, tpv, n, s->rec.p + 2 * nr, s->count.p, s->pair_off.p,
-                       s->rank_of.p, s->frontier.p, s->partial.p, s2d);
+    const int64_t nr = n_grid * s->V;
+    float *s2d = grad2d ? grad2d : s->grad2d.need(10 * (size_t)s->rs + 1);
+    int64_t *cnt = counters(s, st);
+    hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, cnt,
+                       s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p + 2 * s->rs, s->count.p,
+                       s->pair_off.p, s->rank_of.p, s->frontier.p, s->partial.p, s2d);
     DCGS_LAUNCH_CHECK();
-#define DCGS_PBWD(D)                                                                         \
-  hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks_for(n, 256)), dim3(256), 0, st, params, \
-                     n, stride, dc, s->V, s->count.p, s2d, grad, grad_stride, accumulate)
+#define DCGS_PBWD(D)                                                                        \
+  hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st,   \
+                     params, cnt, stride, dc, s->V, s->count.p, s2d, s->rs, grad,            \
+                     grad_stride, accumulate)
     switch (s->sh_degree) {
       case 0: DCGS_PBWD(0); break;
       case 1: DCGS_PBWD(1); break;
@@ -1075,7 +1202,7 @@ void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values, int32_t 
   }
   if ((records || box) && nr > 0) {
     hipLaunchKernelGGL(k_export_rec, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->rec.p,
-                       s->count.p, nr, records, box);
+                       s->rs, s->count.p, nr, records, box);
     DCGS_LAUNCH_CHECK();
   }
   if (last)

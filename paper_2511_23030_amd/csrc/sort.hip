@@ -45,6 +45,12 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *excl) {
   return tot;
 }
 
+// Element count of a launch: the host value, or (when the launch was made
+// for a capacity) the device counter clamped to that capacity.
+__device__ inline int64_t count_of(const int64_t *n_dev, int64_t n) {
+  return n_dev ? min(*n_dev, n) : n;
+}
+
 __device__ inline uint32_t load_item(const uint32_t *in, const uint32_t *gather,
                                      int64_t i, int64_t n) {
   if (i >= n) return 0;
@@ -53,8 +59,9 @@ __device__ inline uint32_t load_item(const uint32_t *in, const uint32_t *gather,
 
 __global__ void __launch_bounds__(kScanThreads)
     k_scan_reduce(const uint32_t *__restrict__ in,
-                  const uint32_t *__restrict__ gather, int64_t n,
-                  uint32_t *__restrict__ part) {
+                  const uint32_t *__restrict__ gather, const int64_t *__restrict__ n_dev,
+                  int64_t n, uint32_t *__restrict__ part) {
+  n = count_of(n_dev, n);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   uint32_t s = 0;
 #pragma unroll
@@ -87,9 +94,10 @@ __global__ void __launch_bounds__(kScanThreads)
 
 __global__ void __launch_bounds__(kScanThreads)
     k_scan_down(const uint32_t *__restrict__ in,
-                const uint32_t *__restrict__ gather, int64_t n,
-                const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
+                const uint32_t *__restrict__ gather, const int64_t *__restrict__ n_dev,
+                int64_t n, const uint32_t *__restrict__ part, uint32_t *__restrict__ out) {
   __shared__ uint32_t tile[kScanTile + kScanTile / 32];
+  n = count_of(n_dev, n);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   auto pad = [](int i) { return i + (i >> 5); };
 #pragma unroll
@@ -119,7 +127,7 @@ __global__ void __launch_bounds__(kScanThreads)
     int li = k * kScanThreads + threadIdx.x;
     if (base + li < n) out[base + li] = tile[pad(li)];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = part[gridDim.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = part[gridDim.x];
 }
 
 // ---------------------------------------------------------------- radix --
@@ -135,9 +143,10 @@ __device__ inline uint32_t digit_of(K key, int shift, uint32_t mask) {
 
 template <typename K>
 __global__ void __launch_bounds__(kSortThreads)
-    k_rs_hist(const K *__restrict__ keys, int64_t n, int shift, int width,
-              uint32_t *__restrict__ hist, int64_t nb) {
+    k_rs_hist(const K *__restrict__ keys, const int64_t *__restrict__ n_dev, int64_t n,
+              int shift, int width, uint32_t *__restrict__ hist, int64_t nb) {
   __shared__ uint32_t h[256];
+  n = count_of(n_dev, n);
   const uint32_t bins = 1u << width, mask = bins - 1;
   for (int t = threadIdx.x; t < 256; t += kSortThreads) h[t] = 0;
   __syncthreads();
@@ -155,10 +164,11 @@ __global__ void __launch_bounds__(kSortThreads)
 template <typename K, bool kVals>
 __global__ void __launch_bounds__(kSortThreads)
     k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-                 K *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n,
-                 int shift, int width, const uint32_t *__restrict__ offs,
-                 int64_t nb) {
+                 K *__restrict__ kout, uint32_t *__restrict__ vout,
+                 const int64_t *__restrict__ n_dev, int64_t n, int shift, int width,
+                 const uint32_t *__restrict__ offs, int64_t nb) {
   __shared__ uint32_t run[256];
+  n = count_of(n_dev, n);
   __shared__ uint32_t wcnt[kSortWaves][256];
   const uint32_t bins = 1u << width, mask = bins - 1;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -201,23 +211,44 @@ __global__ void __launch_bounds__(kSortThreads)
   }
 }
 
+template <typename T>
+__global__ void k_copy_n(const T *__restrict__ a, const int64_t *__restrict__ n_dev, int64_t n,
+                         T *__restrict__ b) {
+  n = count_of(n_dev, n);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+template <typename T>
+void copy_n(const T *a, const int64_t *n_dev, int64_t n, T *b, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_copy_n<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n_dev,
+                     n, b);
+  DCGS_LAUNCH_CHECK();
+}
+
+size_t radix_scratch_bins(int64_t n, int64_t bins) {
+  const int64_t tab = bins * ((n + kSortTile - 1) / kSortTile);
+  return 2 * (size_t)(tab + 1) + scan_part_size(tab) + 16;
+}
+
 template <typename K, bool kVals>
 void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
-                int64_t n, int shift, int width, DevBuf<uint32_t> &hist,
-                hipStream_t st) {
+                const int64_t *n_dev, int64_t n, int shift, int width,
+                DevBuf<uint32_t> &hist, hipStream_t st) {
   const int64_t nb = (n + kSortTile - 1) / kSortTile;
   const int64_t bins = int64_t(1) << width;
   const int64_t tab = bins * nb;
   // histogram table, then its scan (part area after table + 1)
-  uint32_t *h = hist.need(2 * (tab + 1) + scan_part_size(tab) + 16);
+  uint32_t *h = hist.need(radix_scratch_bins(n, bins));
   uint32_t *scanned = h + tab + 1;
   uint32_t *part = scanned + tab + 1;
   hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(kSortThreads), 0,
-                     st, kin, n, shift, width, h, nb);
+                     st, kin, n_dev, n, shift, width, h, nb);
   DCGS_LAUNCH_CHECK();
   scan_u32(h, nullptr, scanned, tab, part, st);
   hipLaunchKernelGGL((k_rs_scatter<K, kVals>), dim3((unsigned)nb),
-                     dim3(kSortThreads), 0, st, kin, vin, kout, vout, n, shift,
+                     dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, n, shift,
                      width, scanned, nb);
   DCGS_LAUNCH_CHECK();
 }
@@ -228,55 +259,55 @@ size_t scan_part_size(int64_t n) {
   return (size_t)((n + kScanTile - 1) / kScanTile) + 2;
 }
 
+size_t radix_scratch(int64_t n) { return radix_scratch_bins(n, 256); }
+
 void scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out,
-              int64_t n, uint32_t *part, hipStream_t st) {
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  if (n == 0) {
-    DCGS_HIP(hipMemsetAsync(out, 0, sizeof(uint32_t), st));
-    return;
-  }
+              int64_t n, uint32_t *part, hipStream_t st, const int64_t *n_dev) {
+  // one block at least, so that out[count] is always written
+  const int64_t nb = std::max<int64_t>(1, (n + kScanTile - 1) / kScanTile);
   hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0,
-                     st, in, gather, n, part);
+                     st, in, gather, n_dev, n, part);
   DCGS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, part, nb);
   DCGS_LAUNCH_CHECK();
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0,
-                     st, in, gather, n, part, out);
+                     st, in, gather, n_dev, n, part, out);
   DCGS_LAUNCH_CHECK();
 }
 
 void sort_u32_pairs(uint32_t *keys, uint32_t *vals, uint32_t *ktmp,
                     uint32_t *vtmp, int64_t n, int bits, DevBuf<uint32_t> &hist,
-                    hipStream_t st) {
+                    hipStream_t st, const int64_t *n_dev) {
+  if (n == 0) return;
   int passes, width;
   digit_plan(bits, &passes, &width);
   uint32_t *ka = keys, *va = vals, *kb = ktmp, *vb = vtmp;
   for (int p = 0; p < passes; ++p) {
     int shift = p * width;
     int w = (shift + width > bits) ? bits - shift : width;
-    radix_pass<uint32_t, true>(ka, va, kb, vb, n, shift, w, hist, st);
+    radix_pass<uint32_t, true>(ka, va, kb, vb, n_dev, n, shift, w, hist, st);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
   if (ka != keys) {
-    DCGS_HIP(hipMemcpyAsync(keys, ka, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-    DCGS_HIP(hipMemcpyAsync(vals, va, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+    copy_n(ka, n_dev, n, keys, st);
+    copy_n(va, n_dev, n, vals, st);
   }
 }
 
 void sort_u64_bits(uint64_t *a, uint64_t *tmp, int64_t n, int lo, int bits,
-                   DevBuf<uint32_t> &hist, hipStream_t st) {
+                   DevBuf<uint32_t> &hist, hipStream_t st, const int64_t *n_dev) {
+  if (n == 0) return;
   int passes, width;
   digit_plan(bits, &passes, &width);
   uint64_t *x = a, *y = tmp;
   for (int p = 0; p < passes; ++p) {
     int shift = p * width;
     int w = (shift + width > bits) ? bits - shift : width;
-    radix_pass<uint64_t, false>(x, nullptr, y, nullptr, n, lo + shift, w, hist, st);
+    radix_pass<uint64_t, false>(x, nullptr, y, nullptr, n_dev, n, lo + shift, w, hist, st);
     std::swap(x, y);
   }
-  if (x != a)
-    DCGS_HIP(hipMemcpyAsync(a, x, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+  if (x != a) copy_n(x, n_dev, n, a, st);
 }
 
 }  // namespace dcgs

@@ -44,9 +44,14 @@ struct AdamArgs {
 __global__ void __launch_bounds__(256)
     k_adam(float *__restrict__ P, float *__restrict__ M, float *__restrict__ V,
            int32_t *__restrict__ step, int R, const int32_t *__restrict__ src,
-           const float *__restrict__ grad, int64_t n, int64_t gs, AdamArgs a) {
+           const float *__restrict__ grad, int64_t n, int64_t gs, AdamArgs a,
+           const int64_t *__restrict__ cnt) {
   constexpr int PG = dcgs_pool::PG, L2 = dcgs_pool::PG_LOG2;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cnt) {
+    if (cnt[3] != 0) return;  // the window overflowed its pair capacity
+    n = min(n, cnt[0]);
+  }
   if (i >= n) return;
   const int32_t slot = src[i];
   const int64_t page = slot >> L2, k = slot & (PG - 1);
@@ -135,7 +140,7 @@ void launch_compact(const float *pool, int R, const int4 *seg, int n_seg, const 
 
 void launch_adam(float *params, float *m, float *v, int32_t *step, int R, const int32_t *src,
                  const float *grad, int64_t n, int64_t grad_stride, const dcgs_adam_config &cfg,
-                 hipStream_t st) {
+                 hipStream_t st, const int64_t *cnt) {
   if (n == 0) return;
   AdamArgs a{};
   for (int k = 0; k < 6; ++k) a.lr[k] = cfg.lr[k];
@@ -143,7 +148,7 @@ void launch_adam(float *params, float *m, float *v, int32_t *step, int R, const 
   a.b2 = cfg.beta2;
   a.eps = cfg.eps;
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, params, m, v,
-                     step, R, src, grad, n, grad_stride, a);
+                     step, R, src, grad, n, grad_stride, a, cnt);
   DCGS_LAUNCH_CHECK();
 }
 

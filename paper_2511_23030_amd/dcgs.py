@@ -58,6 +58,17 @@ class AdamConfig(C.Structure):
         return a
 
 
+class WindowConfig(C.Structure):
+    _fields_ = [("sh_degree", C.c_int), ("width", C.c_int), ("height", C.c_int),
+                ("n_views", C.c_int), ("tile_w", C.c_int), ("tile_h", C.c_int),
+                ("pixels_per_lane", C.c_int), ("capacity", C.c_int64),
+                ("pair_capacity", C.c_int64), ("bg", C.c_float * 3), ("loss_norm", C.c_double),
+                ("adam", AdamConfig), ("params", C.c_void_p), ("grad", C.c_void_p),
+                ("src", C.c_void_p), ("gmask", C.c_void_p), ("rgb", C.c_void_p),
+                ("depth", C.c_void_p), ("dl_drgb", C.c_void_p), ("targets", C.c_void_p),
+                ("stats", C.c_void_p)]
+
+
 P = C.c_void_p
 I64 = C.c_int64
 I32 = C.c_int32
@@ -91,6 +102,11 @@ SIGNATURES = {
     "dcgs_loss_l1": (INT, [P, P, P, I64, DBL, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
     "dcgs_autotune": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
+    "dcgs_window_create": (INT, [P, P, P, C.POINTER(P)]),
+    "dcgs_window_destroy": (None, [P]),
+    "dcgs_window_launch": (INT, [P, P, P, INT, P, C.POINTER(I64), P]),
+    "dcgs_window_sync": (INT, [P, C.POINTER(I64), C.POINTER(INT)]),
+    "dcgs_window_pairs": (INT, [P, C.POINTER(I64)]),
     "dcgs_prefetch_labels": (INT, [P, P, INT, INT, DBL, P, P]),
     "dcgs_prefetch_features": (INT, [P, P, INT, P, INT, DBL, DBL, P, P, P, P, P]),
     "dcgs_mlp_forward": (INT, [P, P, P, P, I64, P, P, P, P, P, P]),
@@ -419,3 +435,66 @@ class RenderState:
         if V == 1:
             out["last"] = out["last"][0]
         return out
+
+
+class Window:
+    """A graph-captured mapping window (dcgs_window_*): compaction, then one
+    graph replay of forward, loss, backward and Adam for all views."""
+
+    def __init__(self, ctx: "Context", pool: "Pool", sh_degree: int, width: int, height: int,
+                 n_views: int, tile, ppt: int, capacity: int, pair_capacity: int, bg, adam,
+                 params, grad, src, gmask, rgb, depth, dl, targets, stats, loss_norm: float):
+        self.ctx, self.pool = ctx, pool
+        c = WindowConfig()
+        c.sh_degree, c.width, c.height, c.n_views = sh_degree, width, height, n_views
+        c.tile_w, c.tile_h, c.pixels_per_lane = int(tile[0]), int(tile[1]), int(ppt)
+        c.capacity, c.pair_capacity = int(capacity), int(pair_capacity)
+        c.bg[:] = [float(x) for x in bg]
+        c.loss_norm = float(loss_norm)
+        c.adam = adam
+        for name, t in (("params", params), ("grad", grad), ("src", src), ("gmask", gmask),
+                        ("rgb", rgb), ("depth", depth), ("dl_drgb", dl), ("targets", targets),
+                        ("stats", stats)):
+            setattr(c, name, ptr(t))
+        self._keep = (params, grad, src, gmask, rgb, depth, dl, targets, stats)
+        self.cfg = c
+        h = P()
+        ctx.check(lib().dcgs_window_create(ctx.h, pool.h, C.byref(c), C.byref(h)))
+        self.h = h
+        self.n_views = n_views
+
+    def launch(self, ids: np.ndarray, masks: np.ndarray, cams: list, stream=None) -> int:
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        masks = np.ascontiguousarray(masks, dtype=np.uint16)
+        arr = (Camera * len(cams))(*[Camera.of(c) for c in cams])
+        n = I64()
+        self.ctx.check(lib().dcgs_window_launch(self.h, ids.ctypes.data, masks.ctypes.data,
+                                                ids.size, C.cast(arr, P), C.byref(n),
+                                                stream_handle(stream)))
+        return n.value
+
+    def sync(self) -> tuple:
+        """Wait for the launches; (pairs needed, launches skipped) after an
+        overflow, else (0, 0)."""
+        need, skipped = I64(), INT()
+        st = lib().dcgs_window_sync(self.h, C.byref(need), C.byref(skipped))
+        if st == 2:
+            return need.value, skipped.value
+        self.ctx.check(st)
+        return 0, 0
+
+    def pairs(self) -> int:
+        v = I64()
+        self.ctx.check(lib().dcgs_window_pairs(self.h, C.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dcgs_window_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

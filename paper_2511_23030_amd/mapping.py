@@ -154,6 +154,73 @@ class MappingLoop:
                          views=V)
         return self.last
 
+    def build_graph(self, V: int, pair_capacity: int):
+        """(Re)build the graph-captured window for V views with room for
+        `pair_capacity` (tile, Gaussian) pairs, using the current raster
+        shape."""
+        self._window_buffers(V)
+        H, W = self.rgb.shape[1], self.rgb.shape[2]
+        if getattr(self, "gtargets", None) is None or self.gtargets.shape[0] != V:
+            self.gtargets = torch.empty(V, 3, H, W, dtype=torch.float32, device=self.rgb.device)
+        if getattr(self, "win", None) is not None:
+            self.win.close()
+        ppt = self.ppt or {8: 1, 16: 2}.get(self.tile[0], 4)
+        self.win = D.Window(self.ctx, self.pool, self.deg, W, H, V, self.tile, ppt, self.cap,
+                            int(pair_capacity), self.bg, self.adam, self.params, self.grad,
+                            self.src, self.gmask, self.rgb_v, self.depth_v, self.dl_v,
+                            self.gtargets, self.stats, 3.0 * H * W)
+        self.win_pairs = int(pair_capacity)
+        self._pending = []
+        return self.win
+
+    def _launch_graph(self, cams, targets, sel) -> int:
+        ids, masks = sel
+        self.gtargets.copy_(targets)
+        return self.win.launch(ids, masks, cams)
+
+    def window_step_graph(self, cams: list, targets: torch.Tensor, sel=None) -> dict:
+        """window_step through the graph-captured window (build_graph first).
+        If a window overflowed its pair capacity (it and every later launch
+        then changed nothing), the window is rebuilt with room for the
+        pairs and the skipped windows run again, in order."""
+        V = len(cams)
+        ids, masks = self.select_window(cams) if sel is None else sel
+        loaded, evicted = self.pool.require(ids, now=self.iter)
+        try:
+            n = self._launch_graph(cams, targets, (ids, masks))
+        except D.DcgsError as e:
+            if e.status != 2:
+                raise
+            n = self._recover_graph(cams, targets, (ids, masks))
+        self._pending = (self._pending + [(cams, targets, (ids, masks))])[-2:]
+        self.iter += 1
+        self.last = dict(n_active=n, n_chunks=int(ids.size), loaded=loaded, evicted=evicted,
+                         views=V)
+        return self.last
+
+    def _redo(self, need: int, skipped: int, V: int):
+        """Rebuild with room for `need` pairs and launch the `skipped` most
+        recent windows again, in order."""
+        redo = self._pending[len(self._pending) - skipped:] if skipped else []
+        self.build_graph(V, max(int(need * 1.25) + 1024, 2 * self.win_pairs))
+        for c, t, s_ in redo:
+            self.pool.require(s_[0], now=self.iter)
+            self._launch_graph(c, t, s_)
+        self._pending = list(redo)
+
+    def _recover_graph(self, cams, targets, sel) -> int:
+        need, skipped = self.win.sync()
+        self._redo(need, skipped, len(cams))
+        self.pool.require(sel[0], now=self.iter)
+        return self._launch_graph(cams, targets, sel)
+
+    def sync_graph(self):
+        """Wait for the graph launches; run again any that overflowed."""
+        need, skipped = self.win.sync()
+        while need:
+            self._redo(need, skipped, self.win.n_views)
+            need, skipped = self.win.sync()
+
     def step(self, cam: dict, target: torch.Tensor, ids: np.ndarray | None = None) -> dict:
         """One plain mapping iteration for one keyframe; returns host stats."""
         if ids is None:
