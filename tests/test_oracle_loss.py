@@ -86,3 +86,18 @@ def test_gradient_matches_central_differences():
         fd = (ol.mapping_loss(x, y, dp, dt, 0.3, 0.7).item() -
               ol.mapping_loss(x, y, dm, dt, 0.3, 0.7).item()) / (2 * h)
         assert abs(fd - gd[idx]) <= 1e-8 + 1e-6 * abs(gd[idx])
+
+
+def test_stability_constants_follow_the_ssim_definition():
+    # C1 = (K1 L)^2, C2 = (K2 L)^2 with K1 = 0.01, K2 = 0.03 (Wang et al.,
+    # 2004) and dynamic range L = 1 for colours in [0, 1]
+    assert ol.C1 == (0.01 * 1.0) ** 2 and ol.C2 == (0.03 * 1.0) ** 2
+    # C2 enters only where the window sees variance: a step edge
+    x = torch.zeros((1, 21, 21), dtype=torch.float64)
+    x[:, :, 11:] = 1.0
+    y = torch.zeros_like(x)
+    y[:, :, 10:] = 1.0
+    s = ol.ssim_map(x, y)[0, 10, 10].item()
+    mx, my = ol.blur(x), ol.blur(y)
+    vx = (ol.blur(x * x) - mx * mx)[0, 10, 10].item()
+    assert vx > 0.1 and 0.5 < s < 1.0
