@@ -71,8 +71,31 @@ def make_workload(name: str) -> dict:
                                         focal=w["f"], z_far=w["z_far"])
     w["true"] = sc["params"]
     w["start"] = scenegen.perturb(sc["params"], seed=12)
+    w["all_cams"] = cams
+    w["frame_of"] = list(range(0, len(cams), w["every"]))
     w["cams"] = cams[::w["every"]]
     return w
+
+
+COPY_BYTES = 1 << 30   # the plain copy that calibrates the HBM byte counters
+
+
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    of this workload, or None when there is none or the kernel's source
+    changed since the counters were taken."""
+    import json
+
+    from paper_2511_23030_amd import profsummary
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    src = os.path.join(ROOT, t["source"])
+    if not os.path.exists(src) or profsummary.source_digest(src) != t["source_sha256"]:
+        return None
+    return t["bytes_per_launch"]
 
 
 # Algorithmic HBM bytes per launch of each streaming stage (SH degree 3:
@@ -147,6 +170,54 @@ def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray, budget_s: float = 2
                        f"({t_full_pre:.1f} s) is not counted twice")}
 
 
+def prefetch_study(ctx, w, make_loop, run, cursor, n_plain, log) -> dict:
+    """Learned prefetch on the driving corridor: train the network on the
+    exact labels of 20 corridor layouts (seeds 100-119), measure chunk misses
+    against the exact test on 5 held-out layouts (120-124), then time the
+    plain per-keyframe path on this workload three ways, each from a fresh
+    pool: no staging ahead (misses load on demand), staging the network's
+    predictions, staging the next keyframe's exact selection."""
+    import scenegen
+
+    from paper_2511_23030_amd import prefetch as PF
+    t0 = time.perf_counter()
+    kw = dict(width=w["W"], height=w["H"], focal=w["f"], z_far=w["z_far"])
+    train = [scenegen.driving_trajectory(scenegen.driving_path(s), None, **kw)
+             for s in range(100, 120)]
+    net, losses = PF.train(ctx, train, w["chunk"], steps=1500, frames_per_batch=16, seed=1)
+    t_train = time.perf_counter() - t0
+    held = []
+    for s in range(120, 125):
+        cams = scenegen.driving_trajectory(scenegen.driving_path(s), None, **kw)
+        held.append(PF.evaluate(ctx, net, cams, w["chunk"], tau=0.3, every=4))
+    tot = {k: sum(h[k] for h in held) for k in ("needed", "entering", "missed")}
+    rep = {"train_s": round(t_train, 2), "loss_first": round(float(losses[:20].mean()), 5),
+           "loss_last": round(float(losses[-100:].mean()), 5), "tau": 0.3,
+           "held_out_miss_rate": round(tot["missed"] / max(tot["needed"], 1), 5),
+           "held_out_miss_rate_without": round(tot["entering"] / max(tot["needed"], 1), 5),
+           "held_out_entering_covered": round(1 - tot["missed"] / max(tot["entering"], 1), 4),
+           "held_out_staged_per_frame": round(float(np.mean([h["staged_per_frame"]
+                                                             for h in held])), 1)}
+    log(f"prefetch network: trained in {t_train:.1f} s, held-out miss rate "
+        f"{rep['held_out_miss_rate']:.4f} vs {rep['held_out_miss_rate_without']:.4f} without")
+    for mode in ("none", "mlp", "exact"):
+        pool, loop = make_loop()
+        cursor["plain_" + mode] = (0, None)
+        run(loop, "plain_" + mode, 4, prefetch=mode, net=net)          # warm
+        cursor["plain_" + mode] = (0, None)
+        pool.close()
+        pool, loop = make_loop()
+        t = run(loop, "plain_" + mode, n_plain, prefetch=mode, net=net)
+        st = pool.stats()
+        rep[f"plain_{mode}_iters_per_s"] = round(n_plain / t, 3)
+        rep[f"plain_{mode}_pool"] = {k: st[k] for k in ("loads", "misses", "hits", "prefetched",
+                                                       "evictions", "bytes_h2d")}
+        log(f"plain, prefetch {mode}: {n_plain / t:.2f} iters/s, pool {st}")
+        pool.close()
+        del loop
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -159,6 +230,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-json", default="")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device copy (the HBM counter calibration)")
+    ap.add_argument("--no-prefetch-mlp", action="store_true",
+                    help="skip the learned-prefetch study of the driving workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -179,6 +254,12 @@ def main():
         f"(generated in {time.perf_counter() - t_setup:.1f} s)")
     ctx = D.Context(0)
     R = 11 + 3 * (w["deg"] + 1) ** 2
+    if args.calibrate_copy:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     V = args.window
     walk = w["walk"]
@@ -221,26 +302,35 @@ def main():
 
     cursor = {}
 
-    def run(loop, kind: str, n_views: int) -> float:
-        """Time `n_views` keyframe views of one path; returns seconds.  Each
-        step selects (on a side stream) and stages the next step's chunks
-        while the current one runs."""
+    def run(loop, kind: str, n_views: int, prefetch: str = "exact", net=None) -> float:
+        """Time `n_views` keyframe views of one path; returns seconds.  With
+        prefetch "exact" each step selects (on a side stream) and stages the
+        next step's chunks while the current one runs; "mlp" stages the
+        cells the prefetch network predicts from the last 8 poses; "none"
+        loads missing chunks when a step needs them."""
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         done = 0
         k, sel = cursor.get(kind, (0, None))
         while done < n_views:
-            if kind == "plain":
+            if kind.startswith("plain"):
                 c = k % K if walk else (k * 3) % K
                 loop.step(w["cams"][c], targets[c], None if sel is None else sel[0])
                 nxt = (k + 1) % K if walk else ((k + 1) * 3) % K
-                sel = loop.prefetch_window([w["cams"][nxt]])
+                sel = None
+                if prefetch == "exact":
+                    sel = loop.prefetch_window([w["cams"][nxt]])
+                elif prefetch == "mlp":
+                    loop.prefetch_predicted(net, [w["all_cams"][max(w["frame_of"][c] - j, 0)]
+                                                  for j in range(8)])
                 done += 1
             else:
                 wi = k % len(windows)
                 cams = [w["cams"][i] for i in windows[wi]]
                 if kind == "batched":
                     loop.window_step(cams, tstack[wi], sel=sel)
+                elif kind == "graph":
+                    loop.window_step_graph(cams, tstack[wi], sel=sel)
                 else:
                     loop.window_step_sequential(cams, tstack[wi], sel=sel)
                 nw = (k + 1) % len(windows)
@@ -248,33 +338,42 @@ def main():
                 done += V
             k += 1
         cursor[kind] = (k, sel)
+        if kind == "graph":
+            loop.sync_graph()
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
     pool_b, loop_b = make_loop()
     pool_s, loop_s = make_loop()
+    pool_g, loop_g = make_loop()
     log(f"pools ingested ({time.perf_counter() - t_setup:.1f} s since start)")
     tuned, tune_ms = None, []
     if args.tile == "auto":
         tuned, tune_ms = loop_b.autotune([w["cams"][i] for i in windows[0]])
-        for lp in (loop_s,):
+        for lp in (loop_s, loop_g):
             lp.tile, lp.ppt = tuned[:2], tuned[2]
         tw, th = tuned[0], tuned[1]
         args.ppt = tuned[2]
         log(f"autotuned raster shape {tuned}; fwd+bwd ms per shape {[round(t, 2) for t in tune_ms]}")
     n_views = max(args.steps, V)
     run(loop_b, "batched", args.warmup * V)
-    cursor["sequential"] = (0, None)
     run(loop_s, "sequential", args.warmup * V)
+    # graph window sized from the pair counts seen so far (it grows itself
+    # if a later window needs more)
+    pairs_seen = loop_b.state.info()["n_pairs"]
+    loop_g.build_graph(V, int(pairs_seen * 1.5) + 4096)
+    run(loop_g, "graph", args.warmup * V)
     log(f"setup {time.perf_counter() - t_setup:.1f} s; timing {n_views} views per path")
     t_b = run(loop_b, "batched", n_views)
     t_s = run(loop_s, "sequential", n_views)
-    pool_stats = pool_b.stats()
+    t_g = run(loop_g, "graph", n_views)
+    pool_stats = pool_g.stats()
     n_timed = ((n_views + V - 1) // V) * V
-    dt = t_b
-    # equal-PSNR check: both pools received the same windows, so the same update
-    ps_b, ps_s = [], []
-    for loop_, acc in ((loop_b, ps_b), (loop_s, ps_s)):
+    dt = t_g
+    # equal-PSNR check: every pool received the same windows, so the same update
+    psnrs = {}
+    for name, loop_ in (("graph", loop_g), ("batched", loop_b), ("sequential", loop_s)):
+        acc = []
         for wi in range(len(windows)):
             cams = [w["cams"][i] for i in windows[wi]]
             ids, masks = loop_.select_window(cams)
@@ -286,15 +385,22 @@ def main():
                               norm=3.0 * w["W"] * w["H"])
             s = loop_.stats.cpu().numpy()
             acc.append(10 * math.log10(1.0 / (s[1] / (V * 3 * w["W"] * w["H"]))))
-    psnr_b, psnr_s = float(np.mean(ps_b)), float(np.mean(ps_s))
-    log(f"batched {n_timed / t_b:.1f} views/s, sequential {n_timed / t_s:.1f} views/s, "
-        f"PSNR {psnr_b:.4f} vs {psnr_s:.4f} dB")
-    pool_s.close()
-    del loop_s
+        psnrs[name] = float(np.mean(acc))
+    psnr_b, psnr_s, psnr_g = psnrs["batched"], psnrs["sequential"], psnrs["graph"]
+    log(f"graph {n_timed / t_g:.1f} views/s, batched {n_timed / t_b:.1f} views/s, sequential "
+        f"{n_timed / t_s:.1f} views/s, PSNR {psnr_g:.4f} / {psnr_b:.4f} / {psnr_s:.4f} dB")
+    loop_g.win.close()
+    for p_ in (pool_s, pool_g):
+        p_.close()
+    del loop_s, loop_g
     # the paper's schedule: one Adam step per keyframe
-    t_p = run(loop_b, "plain", max(args.steps // 2, 8))
-    plain_rate = max(args.steps // 2, 8) / t_p
+    n_plain = max(args.steps // 2, 8)
+    t_p = run(loop_b, "plain", n_plain)
+    plain_rate = n_plain / t_p
     l1, psnr = loop_b.loss_psnr(3 * w["W"] * w["H"])
+    prefetch_report = None
+    if walk and not args.no_prefetch_mlp:
+        prefetch_report = prefetch_study(ctx, w, make_loop, run, cursor, n_plain, log)
 
     # stage profile of the batched path, outside the timed region
     ctx.profile(True)
@@ -319,13 +425,13 @@ def main():
     if dominant in RASTER_FLOPS:
         achieved = RASTER_FLOPS[dominant] * E / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": dominant}
+                "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant}
     else:
         achieved = stage_bytes(dominant, N, Pp, Npx, R) / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dominant}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant}
     loop = loop_b
 
     cpu = None
@@ -348,16 +454,19 @@ def main():
         "config": {"workload": f"{args.workload}: {scene} {w['n']} Gaussians SH{w['deg']}, "
                                f"{w['W']}x{w['H']}, {w['chunk']:g} m chunks, device budget "
                                f"{min(w['budget'], w['n'])} Gaussians, tile {tw}x{th}, "
-                               f"{args.ppt or 'default'} px/lane; value = batched windows of "
-                               f"{V} keyframes (one iteration = one keyframe view)",
+                               f"{args.ppt or 'default'} px/lane; value = graph-replayed batched "
+                               f"windows of {V} keyframes (one iteration = one keyframe view)",
                    "pool_batched": pool_stats,
                    "active_gaussians_per_window_mean": round(N), "pairs_per_window_mean": round(Pp),
                    "evaluations_per_window_mean": round(E),
+                   "graph_views_per_s": round(n_timed / t_g, 3),
                    "batched_views_per_s": round(n_timed / t_b, 3),
                    "sequential_views_per_s": round(n_timed / t_s, 3),
                    "plain_iters_per_s": round(plain_rate, 3),
                    "psnr_batched_db": round(psnr_b, 4), "psnr_sequential_db": round(psnr_s, 4),
-                   "psnr_delta_db": round(abs(psnr_b - psnr_s), 6),
+                   "psnr_graph_db": round(psnr_g, 4),
+                   "psnr_delta_db": round(max(abs(psnr_b - psnr_s), abs(psnr_g - psnr_s)), 6),
+                   "prefetch": prefetch_report,
                    "raster_shape": [tw, th, args.ppt], "autotune_ms": [round(t, 3) for t in tune_ms]},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -269,6 +269,25 @@ int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad,
                    int64_t n, int64_t grad_stride,
                    const dcgs_adam_config *cfg, void *stream);
 
+/* The full mapping loss, Eqs. (2)-(4), for n_views images in one buffer:
+ * per view (1 - lambda_s) |I - I_gt|_1 + lambda_s (1 - SSIM(I, I_gt))
+ * + lambda_depth |D - D_gt|_1, summed over views; |.|_1 is the mean over
+ * the view's 3HW colour (HW depth) values; SSIM is the mean over the 3HW
+ * values of the per-pixel SSIM with an 11-tap Gaussian window (sigma 1.5,
+ * separable, zero padding outside the image), C1 = 0.01^2, C2 = 0.03^2,
+ * each colour channel on its own.  rgb, target, dl_drgb: [V][3][H][W];
+ * depth, depth_target, dl_ddepth: [V][H][W] (all three nullable when
+ * lambda_depth = 0; dl_ddepth alone nullable otherwise).  dl_drgb and
+ * dl_ddepth are written (not accumulated).  stats (device double[4]): sum
+ * |rgb - target|, sum of squared error with rgb clipped to [0, 1], sum of
+ * the per-pixel SSIM, sum |depth - depth_target|; the loss is
+ * (1 - lambda_s) s0 / (3HW) + lambda_s (V - s2 / (3HW)) + lambda_depth s3 / (HW).
+ * Scratch is owned by ctx.  Deterministic. */
+int dcgs_loss_mapping(dcgs_ctx *ctx, const float *rgb, const float *target, const float *depth,
+                      const float *depth_target, int n_views, int height, int width,
+                      double lambda_s, double lambda_depth, float *dl_drgb, float *dl_ddepth,
+                      double *stats, void *stream);
+
 /* ---- autotuner ----------------------------------------------------------- */
 
 /* SYNC.  Time one forward and one backward pass of every supported raster

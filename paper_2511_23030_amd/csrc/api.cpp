@@ -310,6 +310,18 @@ int dcgs_loss_l1(dcgs_ctx *ctx, const float *rgb, const float *target, int64_t c
   });
 }
 
+int dcgs_loss_mapping(dcgs_ctx *ctx, const float *rgb, const float *target, const float *depth,
+                      const float *depth_target, int n_views, int height, int width,
+                      double lambda_s, double lambda_depth, float *dl_drgb, float *dl_ddepth,
+                      double *stats, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::StageTimer tm(ctx, DCGS_STAGE_LOSS, S(stream));
+    dcgs::mapping_loss(ctx, rgb, target, depth, depth_target, n_views, height, width, lambda_s,
+                       lambda_depth, dl_drgb, dl_ddepth, stats, ctx->loss_maps, S(stream));
+  });
+}
+
 int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad, int64_t n,
                    int64_t grad_stride, const dcgs_adam_config *cfg, void *stream) {
   if (!pool) return DCGS_E_INVALID;

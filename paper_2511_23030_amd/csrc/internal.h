@@ -92,6 +92,7 @@ struct dcgs_ctx {
   dcgs::DevBuf<uint16_t> sel_mask;
   dcgs::DevBuf<int> flag;
   dcgs::DevBuf<float> loss_part;
+  dcgs::DevBuf<float> loss_maps;  // SSIM derivative maps and partial sums
   dcgs::DevBuf<uint32_t> scan_part;
   int n_cu = 256;
   // autotuner: scratch outputs and the cache (key -> tile_w, tile_h, ppt)
@@ -242,6 +243,12 @@ void launch_adam(float *params, float *m, float *v, int32_t *step, int R,
 void launch_loss_l1(const float *rgb, const float *target, int64_t count,
                     double norm, float *dl, double *stats, float *part,
                     hipStream_t st);
+
+// mapping loss of Eqs. (2)-(4) (loss.hip)
+void mapping_loss(dcgs_ctx *ctx, const float *rgb, const float *target, const float *depth,
+                  const float *depth_target, int n_views, int H, int W, double lambda_s,
+                  double lambda_depth, float *dl_drgb, float *dl_ddepth, double *stats,
+                  DevBuf<float> &scratch, hipStream_t st);
 
 // learned prefetch (prefetch.hip)
 void prefetch_labels(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames, int horizon,

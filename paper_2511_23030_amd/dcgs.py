@@ -101,6 +101,7 @@ SIGNATURES = {
     "dcgs_render_bwd": (INT, [P, P, P, I64, I64, P, P, P, I64, INT, P, P]),
     "dcgs_loss_l1": (INT, [P, P, P, I64, DBL, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
+    "dcgs_loss_mapping": (INT, [P, P, P, P, P, INT, INT, INT, DBL, DBL, P, P, P, P]),
     "dcgs_autotune": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
     "dcgs_window_create": (INT, [P, P, P, C.POINTER(P)]),
     "dcgs_window_destroy": (None, [P]),
@@ -234,6 +235,29 @@ class Context:
         self.check(lib().dcgs_loss_l1(self.h, ptr(rgb), ptr(target), rgb.numel(), float(norm),
                                       ptr(dl), ptr(st), stream_handle(stream)))
         return dl, st
+
+    def loss_mapping(self, rgb, target, depth=None, depth_target=None, lambda_s=0.2,
+                     lambda_depth=0.0, dl_out=None, dld_out=None, stats=None, stream=None):
+        """Eqs. (2)-(4): rgb, target [V, 3, H, W] (or [3, H, W]); depth,
+        depth_target [V, H, W].  Returns (loss as a host float, dL/drgb,
+        dL/ddepth or None, stats [4])."""
+        import torch
+        V = rgb.shape[0] if rgb.dim() == 4 else 1
+        H, W = rgb.shape[-2], rgb.shape[-1]
+        dl = torch.empty_like(rgb) if dl_out is None else dl_out
+        dld = None
+        if depth is not None and lambda_depth != 0.0:
+            dld = torch.empty_like(depth) if dld_out is None else dld_out
+        st = torch.empty(4, dtype=torch.float64, device=rgb.device) if stats is None else stats
+        self.check(lib().dcgs_loss_mapping(
+            self.h, ptr(rgb), ptr(target), ptr(depth), ptr(depth_target), V, H, W,
+            float(lambda_s), float(lambda_depth), ptr(dl), ptr(dld), ptr(st),
+            stream_handle(stream)))
+        s = st.cpu().numpy()
+        n = 3.0 * H * W
+        loss = (1 - lambda_s) * s[0] / n + lambda_s * (V - s[2] / n) + \
+            lambda_depth * s[3] / (H * W)
+        return float(loss), dl, dld, st
 
 
 class Pool:

@@ -85,6 +85,20 @@ class MappingLoop:
         self.pool.prefetch(sel[0], now=self.iter - 1)
         return sel
 
+    def prefetch_predicted(self, net, history: list, tau: float = 0.3) -> int:
+        """Stage the chunks the prefetch network expects the next frames to
+        need (from the last 8 cameras, history[0] the current one): its
+        inference runs on a side stream, the copies on the pool's copy
+        stream.  Returns the number of chunks asked for."""
+        if getattr(self, "_side_stream", None) is None:
+            self._side_stream = torch.cuda.Stream(device=self.params.device)
+        if getattr(self, "_pool_ids", None) is None:
+            self._pool_ids = self.pool.chunks()[0]
+        ids = net.predict(history, self.s, tau, stream=self._side_stream)
+        ids = ids[np.isin(ids, self._pool_ids)]
+        self.pool.prefetch(ids, now=self.iter - 1)
+        return int(ids.size)
+
     def _window_buffers(self, V: int):
         if getattr(self, "_wv", 0) != V:
             H, W = self.rgb.shape[1], self.rgb.shape[2]

@@ -25,5 +25,64 @@ def summary(db: str, limit: int = 20) -> str:
     return "\n".join(out)
 
 
+
+
+def _counter_rows(csv_path: str, counter: str):
+    """(kernel name, value) per dispatch of one counter from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    with open(csv_path, newline="") as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") == counter:
+                yield row.get("Kernel_Name", ""), float(row["Counter_Value"])
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel_regex: str, copy_regex: str,
+            copy_bytes: float) -> dict:
+    """HBM bytes per launch of the kernels matching kernel_regex: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch) averaged over its dispatches, each
+    scaled by bytes / counter of a plain copy kernel that moves copy_bytes
+    (read once, written once)."""
+    out = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        k_vals, c_vals = [], []
+        for kname, v in _counter_rows(path, name):
+            if re.search(kernel_regex, kname):
+                k_vals.append(v)
+            elif re.search(copy_regex, kname):
+                c_vals.append(v)
+        if not k_vals or not c_vals:
+            raise ValueError(f"{name}: kernel or copy dispatches not found")
+        scale = copy_bytes / (max(c_vals) * 1024.0)
+        out[name] = {"kernel_kib_avg": sum(k_vals) / len(k_vals), "dispatches": len(k_vals),
+                     "copy_kib": max(c_vals), "scale": scale,
+                     "bytes_per_launch": sum(k_vals) / len(k_vals) * 1024.0 * scale}
+    out["bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + \
+        out["WRITE_SIZE"]["bytes_per_launch"]
+    return out
+
+
+def source_digest(path: str) -> str:
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def _main(argv):
+    if argv[1] == "traffic":
+        # traffic <fetch.csv> <write.csv> <kernel regex> <copy regex> <copy bytes> <source> <out.json> <command>
+        import json
+        t = traffic(argv[2], argv[3], argv[4], argv[5], float(argv[6]))
+        t["source_sha256"] = source_digest(argv[7])
+        t["source"] = argv[7]
+        t["kernel_regex"] = argv[4]
+        t["command"] = argv[9]
+        with open(argv[8], "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t, indent=1))
+    else:
+        print(summary(argv[1]))
+
+
 if __name__ == "__main__":
-    print(summary(sys.argv[1]))
+    _main(sys.argv)

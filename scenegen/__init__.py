@@ -234,6 +234,7 @@ CELL = 50.0          # grid cell of the corridor layout (m)
 GRID = 64            # cells per side
 ROAD_HALF = 15.0     # half width of the road (m)
 FACADE_H = 10.0      # facade height (m)
+PATH_OFFSET = 0.3    # centre-line offset from the layout cell centres (m)
 
 
 def driving_path(seed: int = 20, length: float = 4000.0, max_tries: int = 200) -> np.ndarray:
@@ -267,7 +268,9 @@ def driving_path(seed: int = 20, length: float = 4000.0, max_tries: int = 200) -
             total += seg * CELL
             d = (d + (1 if rng.uniform() < 0.5 else 3)) % 4
         if ok:
-            pts = np.array(cells, np.float64) * CELL + CELL / 2
+            # centre line 0.3 m off the cell centres, so that no camera
+            # position lies on a chunk face of Eq. (5)
+            pts = np.array(cells, np.float64) * CELL + CELL / 2 + PATH_OFFSET
             out = [pts[0]]
             for a, b in zip(pts[:-1], pts[1:]):
                 n = int(round(np.linalg.norm(b - a)))
