@@ -114,21 +114,9 @@ def stage_bytes(stage: str, N: float, P: float, Npx: float, R: int) -> float:
 
 
 # FP32 operations per (pixel, Gaussian) evaluation of the raster kernels,
-# counted from the kernels' arithmetic (an FMA counts 2, exp counts 1).
+# counted from the kernels' arithmetic (an FMA counts 2, exp counts 1);
+# evaluations are counted inside the Gaussian's pixel box only.
 RASTER_FLOPS = {"raster_fwd": 30.0, "raster_bwd": 80.0}
-
-
-def processed_evaluations(st_export: dict, tw: int, th: int, W: int, H: int) -> float:
-    """Sum over pixels of the list positions a pixel walks (tile start to its
-    last composited Gaussian): the evaluations both raster kernels perform."""
-    last = st_export["last"].cpu().numpy()
-    ranges = st_export["ranges"].cpu().numpy()
-    tx = -(-W // tw)
-    jj, ii = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
-    tile = (jj // th) * tx + (ii // tw)
-    start = ranges[tile, 0]
-    walk = np.where(last >= 0, last - start + 1, 0)
-    return float(walk.sum())
 
 
 def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray, budget_s: float = 20.0) -> dict:
@@ -230,6 +218,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extra-json", default="")
+    ap.add_argument("--counters-only", action="store_true",
+                    help="run warmup + profile-steps batched windows only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy (the HBM counter calibration)")
     ap.add_argument("--no-prefetch-mlp", action="store_true",
@@ -255,9 +245,10 @@ def main():
     ctx = D.Context(0)
     R = 11 + 3 * (w["deg"] + 1) ** 2
     if args.calibrate_copy:
+        # one elementwise kernel that reads COPY_BYTES and writes COPY_BYTES
         a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
         b = torch.empty_like(a)
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -344,6 +335,17 @@ def main():
         return time.perf_counter() - t0
 
     pool_b, loop_b = make_loop()
+    if args.counters_only:
+        # hardware-counter runs: the batched windows of the timed path only
+        if args.tile == "auto":
+            tuned, _ = loop_b.autotune([w["cams"][i] for i in windows[0]])
+        for k in range(args.warmup + args.profile_steps):
+            wi = k % len(windows)
+            loop_b.window_step([w["cams"][i] for i in windows[wi]], tstack[wi])
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_only": args.workload, "windows": args.profile_steps,
+                          "raster_shape": [loop_b.tile[0], loop_b.tile[1], loop_b.ppt]}))
+        return
     pool_s, loop_s = make_loop()
     pool_g, loop_g = make_loop()
     log(f"pools ingested ({time.perf_counter() - t_setup:.1f} s since start)")
@@ -404,20 +406,30 @@ def main():
 
     # stage profile of the batched path, outside the timed region
     ctx.profile(True)
-    Ns, Ps, Es = [], [], []
+    Ns, Ps, Es, Ews = [], [], [], []
     for k in range(args.profile_steps):
         wi = k % len(windows)
         cams = [w["cams"][i] for i in windows[wi]]
         loop_b.window_step(cams, tstack[wi])
         Ns.append(loop_b.last["n_active"])
         Ps.append(loop_b.state.info()["n_pairs"])
-        ex = loop_b.state.export(torch.device("cuda"), w["H"], w["W"])
-        Es.append(sum(processed_evaluations({"last": ex["last"][v], "ranges": ex["ranges"][
-            v * (ex["ranges"].shape[0] // V):(v + 1) * (ex["ranges"].shape[0] // V)]}, tw, th,
-            w["W"], w["H"]) for v in range(V)))
     torch.cuda.synchronize()
     prof = ctx.profile_read()
     ctx.profile(False)
+    # work of the profiled windows, measured after the timing: positions the
+    # compositing walks, and the (pixel, Gaussian) evaluations inside the
+    # Gaussian's pixel box (the ones no raster kernel can skip)
+    for k in range(args.profile_steps):
+        wi = k % len(windows)
+        cams = [w["cams"][i] for i in windows[wi]]
+        ids, masks = loop_b.select_window(cams)
+        loop_b.pool.require(ids, now=loop_b.iter)
+        n = loop_b.pool.compact(ids, loop_b.params, loop_b.src, masks=masks, out_gmask=loop_b.gmask)
+        loop_b.state.forward(loop_b.params, n, w["deg"], cams, (0, 0, 0), (tw, th), loop_b.rgb_v,
+                             loop_b.depth_v, ppt=args.ppt, gmask=loop_b.gmask)
+        walked, inbox = loop_b.state.work()
+        Ews.append(walked)
+        Es.append(inbox)
     N, Pp, E, Npx = float(np.mean(Ns)), float(np.mean(Ps)), float(np.mean(Es)), w["W"] * w["H"] * V
     stages = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
     dominant = max(stages, key=stages.get)
@@ -459,6 +471,7 @@ def main():
                    "pool_batched": pool_stats,
                    "active_gaussians_per_window_mean": round(N), "pairs_per_window_mean": round(Pp),
                    "evaluations_per_window_mean": round(E),
+                   "walked_positions_per_window_mean": round(float(np.mean(Ews))),
                    "graph_views_per_s": round(n_timed / t_g, 3),
                    "batched_views_per_s": round(n_timed / t_b, 3),
                    "sequential_views_per_s": round(n_timed / t_s, 3),

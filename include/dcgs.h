@@ -494,6 +494,13 @@ int dcgs_profile_read(dcgs_ctx *ctx, double *ms, int64_t *calls, int n_stages);
 int dcgs_state_info(const dcgs_state *st, int64_t *n, int64_t *n_pairs,
                     int32_t *tiles_x, int32_t *tiles_y);
 
+/* SYNC.  Work of the last forward (a measurement, outside the hot path):
+ * *walk = sum over pixels of the list positions its compositing walked
+ * (tile start to its last contributor), *inbox = how many of those had the
+ * pixel inside the record's pixel box (the (pixel, Gaussian) evaluations
+ * the raster kernels cannot skip). */
+int dcgs_state_work(const dcgs_state *st, int64_t *walk, int64_t *inbox, void *stream);
+
 /* Copy results of the last forward into device buffers (null to skip):
  *   keys [n_pairs] uint64 (tile << 32 | float32 depth bits), values [n_pairs]
  *   int32 Gaussian index, ranges [tiles][2] int32, counts [n] int32 tiles

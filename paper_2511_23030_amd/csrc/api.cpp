@@ -536,6 +536,11 @@ int dcgs_state_info(const dcgs_state *st, int64_t *n, int64_t *n_pairs, int32_t 
   return DCGS_OK;
 }
 
+int dcgs_state_work(const dcgs_state *st, int64_t *walk, int64_t *inbox, void *stream) {
+  if (!st || !walk || !inbox) return DCGS_E_INVALID;
+  return guarded(st->ctx, [&] { dcgs::state_work(st, walk, inbox, S(stream)); });
+}
+
 int dcgs_state_export(const dcgs_state *st, uint64_t *keys, int32_t *values, int32_t *ranges,
                       int32_t *counts, float *records, int32_t *box, int32_t *last,
                       void *stream) {

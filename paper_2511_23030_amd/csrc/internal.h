@@ -323,6 +323,7 @@ dcgs_ctx *window_ctx(dcgs_window *w);
 void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int n_ids,
                   float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
                   int64_t capacity, int64_t *n_out, hipStream_t st);
+void state_work(const dcgs_state *s, int64_t *walk, int64_t *inbox, hipStream_t st);
 void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values,
                   int32_t *ranges, int32_t *counts, float *records,
                   int32_t *box, int32_t *last, hipStream_t st);

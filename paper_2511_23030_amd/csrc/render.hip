@@ -385,6 +385,23 @@ __device__ __forceinline__ Sample sample(int px, int py, const float4 &A, const 
   return s;
 }
 
+// Pixel rows [wy0, wy1] covered by this thread's wavefront: lane t of the
+// workgroup owns column t % TW and rows (t / TW) * PPT .. + PPT - 1, and a
+// wavefront spans whole tile rows (TW divides 64).
+template <int TW, int PPT>
+__device__ __forceinline__ void wave_rows(int tile_y0, int &wy0, int &wy1) {
+  static_assert(kWave % TW == 0, "a wavefront must span whole tile rows");
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  wy0 = tile_y0 + (w * kWave / TW) * PPT;
+  wy1 = tile_y0 + ((w * kWave + kWave - 1) / TW) * PPT + PPT - 1;
+}
+
+// The record's pixel box (packed rows in C.w) meets rows [wy0, wy1].
+__device__ __forceinline__ bool box_meets_rows(const float4 &C, int wy0, int wy1) {
+  const uint32_t by = __float_as_uint(C.w);
+  return (int)(by >> 16) >= wy0 && (int)(by & 0xFFFF) <= wy1;
+}
+
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_fwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
@@ -411,6 +428,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   // lane t owns PPT vertically adjacent pixels of the tile
   const int px = tx * TW + (threadIdx.x % TW);
   const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
+  int wy0, wy1;
+  wave_rows<TW, PPT>(ty * TH, wy0, wy1);
   const int2 rg = ranges[gt];
   float T[PPT], c0[PPT], c1[PPT], c2[PPT], D[PPT];
   int last[PPT];
@@ -436,7 +455,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     __syncthreads();
     const int nb = min(BS, rg.y - base);
     for (int k = 0; k < nb && n_live > 0; ++k) {
-      const float4 A = sA[k], B = sB[k], C = sC[k];
+      const float4 C = sC[k];
+      if (!box_meets_rows(C, wy0, wy1)) continue;  // no pixel of this wave is in the box
+      const float4 A = sA[k], B = sB[k];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         if (done[j]) continue;
@@ -568,6 +589,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   }
   const int px = tx * TW + (threadIdx.x % TW);
   const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
+  int wy0, wy1;
+  wave_rows<TW, PPT>(ty * TH, wy0, wy1);
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int2 rg = ranges[gt];
   const int64_t HW = (int64_t)W * H;
@@ -617,11 +640,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
       const int pos = end - 1 - k;
-      if (__ballot(pos <= my_last) == 0) {  // no pixel of this wave reaches pos
+      const float4 C = sC[k];
+      // no pixel of this wave reaches pos, or none is in the record's box
+      if (__ballot(pos <= my_last) == 0 || !box_meets_rows(C, wy0, wy1)) {
         if (lane < NC) red[wv][k][lane] = 0.0f;
         continue;
       }
-      const float4 A = sA[k], B = sB[k], C = sC[k];
+      const float4 A = sA[k], B = sB[k];
       float v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = 0.0f;
@@ -843,12 +868,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int r = 0; r < 11; ++r) acc[r] = accumulate ? grad[r * gstride + i] : 0.0f;
   bool sh_written = accumulate != 0;
+  Geo g;
+  load_gauss(P, stride, i, g);  // camera-independent: once for all views
   for (int v = 0; v < V; ++v) {
     const int64_t rr = v * n + i;
     if (count[rr] == 0) continue;
     const CamD &cam = cams[v];
-    Geo g;
-    load_geo(P, stride, i, cam, g);
+    project(cam, g);
     float s[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) s[c] = s2d[c * RS + rr];
@@ -868,6 +894,44 @@ __global__ void __launch_bounds__(256)
   for (int r = 0; r < 11; ++r) grad[r * gstride + i] = acc[r];
   if (!sh_written)
     for (int r = 11; r < R; ++r) grad[r * gstride + i] = 0.0f;
+}
+
+// ---- work measurement (outside the hot path) ----
+// Per tile: the list positions each pixel's compositing walks (start to its
+// last contributor) and how many of them have the pixel inside the record's
+// box.  out[2 * tile] / out[2 * tile + 1].
+__global__ void __launch_bounds__(256)
+    k_work(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
+           const float4 *__restrict__ recC, int W, int H, int TW, int TH, int tiles_x,
+           int tiles_per_view, const int *__restrict__ last, long long *__restrict__ out) {
+  __shared__ unsigned long long s_walk, s_in;
+  const int gt = blockIdx.x;
+  const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int2 rg = ranges[gt];
+  if (threadIdx.x == 0) s_walk = s_in = 0;
+  __syncthreads();
+  unsigned long long walk = 0, inbox = 0;
+  for (int t = threadIdx.x; t < TW * TH; t += blockDim.x) {
+    const int px = tx * TW + t % TW, py = ty * TH + t / TW;
+    if (px >= W || py >= H) continue;
+    const int l = last[(int64_t)view * W * H + (int64_t)py * W + px];
+    if (l < rg.x) continue;
+    walk += (unsigned long long)(l - rg.x + 1);
+    for (int p = rg.x; p <= l; ++p) {
+      const float4 C = recC[(uint32_t)pairs[p]];
+      const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+      inbox += (px >= (int)(bx & 0xFFFF) && px <= (int)(bx >> 16) && py >= (int)(by & 0xFFFF) &&
+                py <= (int)(by >> 16));
+    }
+  }
+  atomicAdd(&s_walk, walk);
+  atomicAdd(&s_in, inbox);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * gt] = (long long)s_walk;
+    out[2 * gt + 1] = (long long)s_in;
+  }
 }
 
 // ---- export helpers (tests) ----
@@ -1181,6 +1245,31 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
 #undef DCGS_PBWD
     DCGS_LAUNCH_CHECK();
   }
+}
+
+void state_work(const dcgs_state *s, int64_t *walk, int64_t *inbox, hipStream_t st) {
+  const int tpv = s->tiles_x * s->tiles_y, nt = tpv * s->V;
+  DCGS_CHECK(nt > 0 && s->ranges.p && s->last.p, DCGS_E_INVALID, "state_work: no forward");
+  long long *d = nullptr;
+  DCGS_HIP(hipMalloc(&d, 2 * (size_t)nt * sizeof(long long)));
+  struct Free {
+    void *p;
+    ~Free() { (void)hipFree(p); }
+  } fr{d};
+  hipLaunchKernelGGL(k_work, dim3(nt), dim3(256), 0, st, s->pairs.p, s->ranges.p,
+                     s->rec.p + 2 * s->rs, s->W, s->H, s->TW, s->TH, s->tiles_x, tpv, s->last.p,
+                     d);
+  DCGS_LAUNCH_CHECK();
+  std::vector<long long> h(2 * (size_t)nt);
+  DCGS_HIP(hipMemcpyAsync(h.data(), d, h.size() * sizeof(long long), hipMemcpyDeviceToHost, st));
+  DCGS_HIP(hipStreamSynchronize(st));
+  int64_t a = 0, b = 0;
+  for (int t = 0; t < nt; ++t) {
+    a += h[2 * t];
+    b += h[2 * t + 1];
+  }
+  *walk = a;
+  *inbox = b;
 }
 
 void export_state(const dcgs_state *s, uint64_t *keys, int32_t *values, int32_t *ranges,

@@ -118,6 +118,7 @@ SIGNATURES = {
     "dcgs_profile_enable": (INT, [P, INT]),
     "dcgs_profile_read": (INT, [P, P, P, INT]),
     "dcgs_state_info": (INT, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)]),
+    "dcgs_state_work": (INT, [P, C.POINTER(I64), C.POINTER(I64), P]),
     "dcgs_state_export": (INT, [P, P, P, P, P, P, P, P, P]),
 }
 
@@ -239,8 +240,8 @@ class Context:
     def loss_mapping(self, rgb, target, depth=None, depth_target=None, lambda_s=0.2,
                      lambda_depth=0.0, dl_out=None, dld_out=None, stats=None, stream=None):
         """Eqs. (2)-(4): rgb, target [V, 3, H, W] (or [3, H, W]); depth,
-        depth_target [V, H, W].  Returns (loss as a host float, dL/drgb,
-        dL/ddepth or None, stats [4])."""
+        depth_target [V, H, W].  Returns (dL/drgb, dL/ddepth or None,
+        stats [4]); no host synchronisation (see loss_value)."""
         import torch
         V = rgb.shape[0] if rgb.dim() == 4 else 1
         H, W = rgb.shape[-2], rgb.shape[-1]
@@ -253,11 +254,16 @@ class Context:
             self.h, ptr(rgb), ptr(target), ptr(depth), ptr(depth_target), V, H, W,
             float(lambda_s), float(lambda_depth), ptr(dl), ptr(dld), ptr(st),
             stream_handle(stream)))
-        s = st.cpu().numpy()
+        return dl, dld, st
+
+    @staticmethod
+    def loss_value(stats, n_views: int, H: int, W: int, lambda_s: float,
+                   lambda_depth: float) -> float:
+        """The loss of Eq. (2) summed over views from loss_mapping's stats."""
+        s = stats.cpu().numpy()
         n = 3.0 * H * W
-        loss = (1 - lambda_s) * s[0] / n + lambda_s * (V - s[2] / n) + \
-            lambda_depth * s[3] / (H * W)
-        return float(loss), dl, dld, st
+        return float((1 - lambda_s) * s[0] / n + lambda_s * (n_views - s[2] / n) +
+                     lambda_depth * s[3] / (H * W))
 
 
 class Pool:
@@ -426,6 +432,13 @@ class RenderState:
                                            int(force), shape, times.ctypes.data, C.byref(k),
                                            stream_handle(stream)))
         return (shape[0], shape[1], shape[2]), [t for t in times[:k.value] if t >= 0]
+
+    def work(self, stream=None) -> tuple:
+        """(list positions walked, in-box evaluations) of the last forward."""
+        a, b = I64(), I64()
+        self.ctx.check(lib().dcgs_state_work(self.h, C.byref(a), C.byref(b),
+                                             stream_handle(stream)))
+        return a.value, b.value
 
     def info(self):
         n, p, tx, ty = I64(), I64(), I32(), I32()

@@ -22,7 +22,7 @@ DEFAULT_LR = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1.25e-4)
 class MappingLoop:
     def __init__(self, ctx: D.Context, pool: D.Pool, sh_degree: int, chunk_size: float,
                  capacity: int, width: int, height: int, tile=(16, 16), bg=(0.0, 0.0, 0.0),
-                 lr=DEFAULT_LR, ppt: int = 0):
+                 lr=DEFAULT_LR, ppt: int = 0, lambda_s: float = 0.0, lambda_depth: float = 0.0):
         self.ctx, self.pool = ctx, pool
         self.deg, self.s, self.tile, self.bg = sh_degree, float(chunk_size), tuple(tile), bg
         self.ppt = ppt
@@ -35,7 +35,10 @@ class MappingLoop:
         self.rgb = torch.empty(3, height, width, dtype=torch.float32, device=dev)
         self.depth = torch.empty(height, width, dtype=torch.float32, device=dev)
         self.dl = torch.empty(3, height, width, dtype=torch.float32, device=dev)
-        self.stats = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.stats = torch.zeros(4, dtype=torch.float64, device=dev)
+        # Eq. (3)'s SSIM weight and Eq. (2)'s depth weight (0: L1 only)
+        self.lambda_s, self.lambda_depth = float(lambda_s), float(lambda_depth)
+        self.dld = torch.empty(height, width, dtype=torch.float32, device=dev)
         self.state = D.RenderState(ctx)
         self.adam = D.AdamConfig.of(lr)
         self.iter = 0
@@ -68,6 +71,20 @@ class MappingLoop:
             k = int(count_t.item())
             return (ids_t[:k].cpu().numpy().view(np.uint64),
                     mask_t[:k].cpu().numpy().view(np.uint16))
+
+    def _loss(self, rgb, target, depth, target_depth, dl, dld, stats=None):
+        """The mapping loss of the rendered views (L1 only when both weights
+        are 0); returns the depth gradient buffer or None."""
+        H, W = rgb.shape[-2], rgb.shape[-1]
+        st = self.stats if stats is None else stats
+        if self.lambda_s == 0.0 and (self.lambda_depth == 0.0 or target_depth is None):
+            self.ctx.loss_l1(rgb, target, dl, st, norm=3.0 * H * W)
+            return None
+        lam_d = self.lambda_depth if target_depth is not None else 0.0
+        _, g, _ = self.ctx.loss_mapping(rgb, target, depth if lam_d else None,
+                                        target_depth if lam_d else None, self.lambda_s, lam_d,
+                                        dl_out=dl, dld_out=dld, stats=st)
+        return g
 
     def select(self, cam: dict) -> np.ndarray:
         """Visible chunk ids of `cam` (host copy; one sync)."""
@@ -106,6 +123,7 @@ class MappingLoop:
             self.rgb_v = torch.empty(V, 3, H, W, dtype=torch.float32, device=dev)
             self.depth_v = torch.empty(V, H, W, dtype=torch.float32, device=dev)
             self.dl_v = torch.empty(V, 3, H, W, dtype=torch.float32, device=dev)
+            self.dld_v = torch.empty(V, H, W, dtype=torch.float32, device=dev)
             self.gmask = torch.empty(self.cap, dtype=torch.int16, device=dev)
             self._wv = V
 
@@ -121,7 +139,8 @@ class MappingLoop:
         self.tile, self.ppt = shape[:2], shape[2]
         return shape, times
 
-    def window_step(self, cams: list, targets: torch.Tensor, sel=None) -> dict:
+    def window_step(self, cams: list, targets: torch.Tensor, sel=None,
+                    target_depths: torch.Tensor | None = None) -> dict:
         """One batched mapping iteration over a window of keyframes: one
         selection, one compaction of the union with per-Gaussian view masks,
         one forward and one backward launch sequence for all views, the loss
@@ -134,16 +153,16 @@ class MappingLoop:
         n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
         self.state.forward(self.params, n, self.deg, list(cams), self.bg, self.tile, self.rgb_v,
                            self.depth_v, ppt=self.ppt, gmask=self.gmask)
-        H, W = self.rgb.shape[1], self.rgb.shape[2]
-        self.ctx.loss_l1(self.rgb_v, targets, self.dl_v, self.stats, norm=3.0 * H * W)
-        self.state.backward(self.params, n, self.dl_v, None, self.grad, accumulate=False)
+        dld = self._loss(self.rgb_v, targets, self.depth_v, target_depths, self.dl_v, self.dld_v)
+        self.state.backward(self.params, n, self.dl_v, dld, self.grad, accumulate=False)
         self.pool.adam_step(self.src, self.grad, n, self.adam)
         self.iter += 1
         self.last = dict(n_active=n, n_chunks=int(ids.size), loaded=loaded, evicted=evicted,
                          views=V)
         return self.last
 
-    def window_step_sequential(self, cams: list, targets: torch.Tensor, sel=None) -> dict:
+    def window_step_sequential(self, cams: list, targets: torch.Tensor, sel=None,
+                               target_depths: torch.Tensor | None = None) -> dict:
         """The same update as window_step computed as one single-view forward
         and backward per view, accumulating gradients, then one Adam step
         (the per-view comparator of the batched path)."""
@@ -153,14 +172,16 @@ class MappingLoop:
         loaded, evicted = self.pool.require(ids, now=self.iter)
         n = self.pool.compact(ids, self.params, self.src, masks=masks, out_gmask=self.gmask)
         H, W = self.rgb.shape[1], self.rgb.shape[2]
-        stats = torch.zeros(2, dtype=torch.float64, device=self.rgb.device)
+        stats = torch.zeros(4, dtype=torch.float64, device=self.rgb.device)
         for v in range(V):
             self.state.forward(self.params, n, self.deg, cams[v], self.bg, self.tile,
                                self.rgb_v[v], self.depth_v[v], ppt=self.ppt, gmask=self.gmask,
                                mask_shift=v)
-            self.ctx.loss_l1(self.rgb_v[v], targets[v], self.dl_v[v], self.stats)
+            dld = self._loss(self.rgb_v[v], targets[v], self.depth_v[v],
+                             None if target_depths is None else target_depths[v],
+                             self.dl_v[v], self.dld_v[v])
             stats += self.stats
-            self.state.backward(self.params, n, self.dl_v[v], None, self.grad, accumulate=v > 0)
+            self.state.backward(self.params, n, self.dl_v[v], dld, self.grad, accumulate=v > 0)
         self.stats.copy_(stats)
         self.pool.adam_step(self.src, self.grad, n, self.adam)
         self.iter += 1
@@ -235,7 +256,8 @@ class MappingLoop:
             self._redo(need, skipped, self.win.n_views)
             need, skipped = self.win.sync()
 
-    def step(self, cam: dict, target: torch.Tensor, ids: np.ndarray | None = None) -> dict:
+    def step(self, cam: dict, target: torch.Tensor, ids: np.ndarray | None = None,
+             target_depth: torch.Tensor | None = None) -> dict:
         """One plain mapping iteration for one keyframe; returns host stats."""
         if ids is None:
             ids = self.select(cam)
@@ -243,8 +265,8 @@ class MappingLoop:
         n = self.pool.compact(ids, self.params, self.src)
         self.state.forward(self.params, n, self.deg, cam, self.bg, self.tile, self.rgb, self.depth,
                            ppt=self.ppt)
-        self.ctx.loss_l1(self.rgb, target, self.dl, self.stats)
-        self.state.backward(self.params, n, self.dl, None, self.grad, accumulate=False)
+        dld = self._loss(self.rgb, target, self.depth, target_depth, self.dl, self.dld)
+        self.state.backward(self.params, n, self.dl, dld, self.grad, accumulate=False)
         self.pool.adam_step(self.src, self.grad, n, self.adam)
         self.iter += 1
         self.last = dict(n_active=n, n_chunks=int(ids.size), loaded=loaded, evicted=evicted)

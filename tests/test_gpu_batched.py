@@ -106,3 +106,30 @@ def test_autotuner_picks_a_supported_shape_and_caches(ctx, room):
     shape2, times2 = loop.autotune(cams)          # cached: no timing
     assert shape2 == shape and times2 == []
     pool.close()
+
+
+def test_window_with_ssim_and_depth_equals_sequential(ctx, room):
+    """Eq. (2)-(4) with both weights set: the batched window and the
+    per-view comparator update the pool identically."""
+    params, cams_all = room
+    V = 6
+    cams = cams_all[7::14][:V]
+    rng = np.random.default_rng(70)
+    targets = torch.from_numpy(np.stack([scenegen.target_image(W, H, seed=80 + v)
+                                         for v in range(V)])).cuda()
+    depths = torch.from_numpy(rng.uniform(0.5, 4.0, size=(V, H, W)).astype(np.float32)).cuda()
+    pool_a, loop_a = _loop(ctx, params, V)
+    pool_b, loop_b = _loop(ctx, params, V)
+    for lp in (loop_a, loop_b):
+        lp.lambda_s, lp.lambda_depth = 0.2, 0.1
+    for it in range(2):
+        loop_a.window_step(cams, targets, target_depths=depths)
+        loop_b.window_step_sequential(cams, targets, target_depths=depths)
+    torch.cuda.synchronize()
+    assert loop_a.stats[2].item() > 0 and loop_a.stats[3].item() > 0
+    ids, counts = pool_a.chunks()
+    for cid, c in list(zip(ids, counts))[::5]:
+        for x, y in zip(pool_a.read_chunk(cid, c), pool_b.read_chunk(cid, c)):
+            assert (x == y).all()
+    pool_a.close()
+    pool_b.close()

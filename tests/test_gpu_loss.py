@@ -27,7 +27,8 @@ def test_loss_and_gradient_match_oracle(ctx, V, H, W):
     ls, ld = 0.2, 0.5
     xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
     dtt, dtgt = torch.from_numpy(d).cuda(), torch.from_numpy(dt).cuda()
-    loss, dl, dld, st = ctx.loss_mapping(xt, yt, dtt, dtgt, lambda_s=ls, lambda_depth=ld)
+    dl, dld, st = ctx.loss_mapping(xt, yt, dtt, dtgt, lambda_s=ls, lambda_depth=ld)
+    loss = ctx.loss_value(st, V, H, W, ls, ld)
     L, gx, gd = ol.mapping_loss_grad(x.astype(np.float64), y.astype(np.float64),
                                      d.astype(np.float64), dt.astype(np.float64), ls, ld)
     print(f"case loss V={V} {H}x{W}: {loss:.8f} vs {L:.8f}", flush=True)
@@ -46,10 +47,11 @@ def test_loss_and_gradient_match_oracle(ctx, V, H, W):
 def test_l1_only_equals_l1_kernel_and_identical_images(ctx):
     x, y, _, _ = _inputs(2, 40, 33, 7)
     xt, yt = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
-    _, dl, _, st = ctx.loss_mapping(xt, yt, lambda_s=0.0)
+    dl, _, st = ctx.loss_mapping(xt, yt, lambda_s=0.0)
     dl1, st1 = ctx.loss_l1(xt, yt, norm=3.0 * 40 * 33)
     assert torch.equal(dl, dl1)
     assert abs(st[0].item() - st1[0].item()) <= 1e-6 * st1[0].item()
-    loss, dl, _, st = ctx.loss_mapping(xt, xt.clone(), lambda_s=1.0)
+    dl, _, st = ctx.loss_mapping(xt, xt.clone(), lambda_s=1.0)
+    loss = ctx.loss_value(st, 2, 40, 33, 1.0, 0.0)
     assert abs(loss) < 1e-5
     assert abs(st[2].item() - 2 * 3 * 40 * 33) < 1e-3
