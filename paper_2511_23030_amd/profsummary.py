@@ -86,3 +86,31 @@ def _main(argv):
 
 if __name__ == "__main__":
     _main(sys.argv)
+
+
+def trace_summary(trace_csv: str, focus_regex: str, limit: int = 16) -> str:
+    """Markdown of a rocprofv3 kernel_trace.csv: per kernel and launch size
+    (grid threads), calls and average/min/max duration."""
+    import csv
+    from collections import defaultdict
+    d = defaultdict(list)
+    with open(trace_csv, newline="") as f:
+        for r in csv.DictReader(f):
+            n = short_name(r["Kernel_Name"])
+            g = int(r.get("Grid_Size_X") or 0) * int(r.get("Grid_Size_Y") or 1) * \
+                int(r.get("Grid_Size_Z") or 1)
+            d[(n, g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in d.values())
+    rows = sorted(d.items(), key=lambda kv: -sum(kv[1]))[:limit]
+    out = ["| kernel | grid threads | calls | total ms | avg us | min us | max us | % |",
+           "|---|---|---|---|---|---|---|---|"]
+    for (n, g), v in rows:
+        out.append(f"| `{n}` | {g} | {len(v)} | {sum(v) / 1e3:.1f} | {sum(v) / len(v):.1f} | "
+                   f"{min(v):.1f} | {max(v):.1f} | {100 * sum(v) / total:.1f} |")
+    foc = [(k, v) for k, v in d.items() if re.search(focus_regex, k[0])]
+    if foc:
+        (n, g), v = max(foc, key=lambda kv: kv[0][1])
+        out.append("")
+        out.append(f"Largest launch of `{n}` (grid {g} threads): {len(v)} calls, average "
+                   f"{sum(v) / len(v) / 1e3:.3f} ms.")
+    return "\n".join(out)
