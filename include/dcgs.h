@@ -288,6 +288,19 @@ int dcgs_loss_mapping(dcgs_ctx *ctx, const float *rgb, const float *target, cons
                       double lambda_s, double lambda_depth, float *dl_drgb, float *dl_ddepth,
                       double *stats, void *stream);
 
+/* The LoG sampling map of the Sampling section: P_s = max(P_L - P~, 0)
+ * with P_L = min(1, beta |LoG(image)|) and P~ = min(1, beta |LoG(render)|),
+ * |.| the Euclidean norm over colour channels of the per-channel LoG (sum
+ * of the second-derivative Gaussian filters along rows and columns, sigma
+ * in px, radius ceil(4 sigma) <= 12, mirror boundary with the edge sample
+ * repeated).  image, render: [3][H][W]; u: [H][W] uniform draws (the
+ * caller's); ps (nullable): [H][W] the map; out_idx [H*W]: indices y*W + x
+ * of the pixels with u < P_s in raster order; out_count (device int32)
+ * their number.  Scratch is owned by ctx. */
+int dcgs_sample_pixels(dcgs_ctx *ctx, const float *image, const float *render, const float *u,
+                       int height, int width, double beta, double sigma, float *ps,
+                       int32_t *out_idx, int32_t *out_count, void *stream);
+
 /* ---- autotuner ----------------------------------------------------------- */
 
 /* SYNC.  Time one forward and one backward pass of every supported raster

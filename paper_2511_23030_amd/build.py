@@ -17,8 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libdcgs.so")
 ARCH = "gfx950"
-SOURCES = ["chunks.hip", "sort.hip", "render.hip", "stream_ops.hip", "loss.hip", "prefetch.hip",
-           "pool.cpp", "window.cpp", "api.cpp"]
+SOURCES = ["chunks.hip", "sort.hip", "render.hip", "stream_ops.hip", "loss.hip", "sampling.hip",
+           "prefetch.hip", "pool.cpp", "window.cpp", "api.cpp"]
 
 
 def hipcc() -> str:

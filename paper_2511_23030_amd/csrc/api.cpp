@@ -322,6 +322,16 @@ int dcgs_loss_mapping(dcgs_ctx *ctx, const float *rgb, const float *target, cons
   });
 }
 
+int dcgs_sample_pixels(dcgs_ctx *ctx, const float *image, const float *render, const float *u,
+                       int height, int width, double beta, double sigma, float *ps,
+                       int32_t *out_idx, int32_t *out_count, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    dcgs::sample_pixels(ctx, image, render, u, height, width, beta, sigma, ps, out_idx,
+                        out_count, S(stream));
+  });
+}
+
 int dcgs_adam_step(dcgs_pool *pool, const int32_t *src, const float *grad, int64_t n,
                    int64_t grad_stride, const dcgs_adam_config *cfg, void *stream) {
   if (!pool) return DCGS_E_INVALID;

@@ -93,6 +93,7 @@ struct dcgs_ctx {
   dcgs::DevBuf<int> flag;
   dcgs::DevBuf<float> loss_part;
   dcgs::DevBuf<float> loss_maps;  // SSIM derivative maps and partial sums
+  dcgs::DevBuf<uint32_t> samp;    // sampling flags and their scan
   dcgs::DevBuf<uint32_t> scan_part;
   int n_cu = 256;
   // autotuner: scratch outputs and the cache (key -> tile_w, tile_h, ppt)
@@ -249,6 +250,11 @@ void mapping_loss(dcgs_ctx *ctx, const float *rgb, const float *target, const fl
                   const float *depth_target, int n_views, int H, int W, double lambda_s,
                   double lambda_depth, float *dl_drgb, float *dl_ddepth, double *stats,
                   DevBuf<float> &scratch, hipStream_t st);
+
+// LoG sampling map (sampling.hip)
+void sample_pixels(dcgs_ctx *ctx, const float *image, const float *render, const float *u,
+                   int H, int W, double beta, double sigma, float *ps, int32_t *out_idx,
+                   int32_t *out_count, hipStream_t st);
 
 // learned prefetch (prefetch.hip)
 void prefetch_labels(dcgs_ctx *ctx, const dcgs_camera *cams, int n_frames, int horizon,

@@ -66,26 +66,27 @@ CamD make_cam(const dcgs_camera &c) {
 }
 
 // Real orthonormal SH basis (no Condon-Shortley phase), k = l*l + l + m.
-__device__ inline void sh_eval(int deg, double x, double y, double z, double *Y) {
+template <typename T>
+__device__ inline void sh_eval(int deg, T x, T y, T z, T *Y) {
   constexpr double kPi = 3.14159265358979323846;
-  Y[0] = 0.5 / sqrt(kPi);
+  Y[0] = T(0.5 / sqrt(kPi));
   if (deg < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  const T c1 = T(sqrt(3.0 / (4.0 * kPi)));
   Y[1] = c1 * y;
   Y[2] = c1 * z;
   Y[3] = c1 * x;
   if (deg < 2) return;
-  const double c2a = 0.5 * sqrt(15.0 / kPi), c20 = 0.25 * sqrt(5.0 / kPi),
-               c22 = 0.25 * sqrt(15.0 / kPi);
+  const T c2a = T(0.5 * sqrt(15.0 / kPi)), c20 = T(0.25 * sqrt(5.0 / kPi)),
+          c22 = T(0.25 * sqrt(15.0 / kPi));
   Y[4] = c2a * x * y;
   Y[5] = c2a * y * z;
   Y[6] = c20 * (3.0 * z * z - 1.0);
   Y[7] = c2a * x * z;
   Y[8] = c22 * (x * x - y * y);
   if (deg < 3) return;
-  const double c33 = 0.25 * sqrt(35.0 / (2.0 * kPi)), c32 = 0.5 * sqrt(105.0 / kPi),
-               c31 = 0.25 * sqrt(21.0 / (2.0 * kPi)), c30 = 0.25 * sqrt(7.0 / kPi),
-               c32b = 0.25 * sqrt(105.0 / kPi);
+  const T c33 = T(0.25 * sqrt(35.0 / (2.0 * kPi))), c32 = T(0.5 * sqrt(105.0 / kPi)),
+          c31 = T(0.25 * sqrt(21.0 / (2.0 * kPi))), c30 = T(0.25 * sqrt(7.0 / kPi)),
+          c32b = T(0.25 * sqrt(105.0 / kPi));
   Y[9] = c33 * y * (3.0 * x * x - y * y);
   Y[10] = c32 * x * y * z;
   Y[11] = c31 * y * (5.0 * z * z - 1.0);
@@ -97,25 +98,25 @@ __device__ inline void sh_eval(int deg, double x, double y, double z, double *Y)
 
 // gd = sum_k f[k] grad Y_k(x, y, z), with (x, y, z) treated as independent
 // (the caller projects onto the sphere's tangent plane); k >= 1.
-__device__ inline void sh_grad_dot(int deg, double x, double y, double z, const double *f,
-                                   double gd[3]) {
+template <typename T>
+__device__ inline void sh_grad_dot(int deg, T x, T y, T z, const T *f, T gd[3]) {
   constexpr double kPi = 3.14159265358979323846;
-  gd[0] = gd[1] = gd[2] = 0.0;
+  gd[0] = gd[1] = gd[2] = T(0);
   if (deg < 1) return;
-  const double c1 = sqrt(3.0 / (4.0 * kPi));
+  const T c1 = T(sqrt(3.0 / (4.0 * kPi)));
   gd[0] += c1 * f[3];
   gd[1] += c1 * f[1];
   gd[2] += c1 * f[2];
   if (deg < 2) return;
-  const double c2a = 0.5 * sqrt(15.0 / kPi), c20 = 0.25 * sqrt(5.0 / kPi),
-               c22 = 0.25 * sqrt(15.0 / kPi);
+  const T c2a = T(0.5 * sqrt(15.0 / kPi)), c20 = T(0.25 * sqrt(5.0 / kPi)),
+          c22 = T(0.25 * sqrt(15.0 / kPi));
   gd[0] += c2a * y * f[4] + c2a * z * f[7] + 2.0 * c22 * x * f[8];
   gd[1] += c2a * x * f[4] + c2a * z * f[5] - 2.0 * c22 * y * f[8];
   gd[2] += c2a * y * f[5] + 6.0 * c20 * z * f[6] + c2a * x * f[7];
   if (deg < 3) return;
-  const double c33 = 0.25 * sqrt(35.0 / (2.0 * kPi)), c32 = 0.5 * sqrt(105.0 / kPi),
-               c31 = 0.25 * sqrt(21.0 / (2.0 * kPi)), c30 = 0.25 * sqrt(7.0 / kPi),
-               c32b = 0.25 * sqrt(105.0 / kPi);
+  const T c33 = T(0.25 * sqrt(35.0 / (2.0 * kPi))), c32 = T(0.5 * sqrt(105.0 / kPi)),
+          c31 = T(0.25 * sqrt(21.0 / (2.0 * kPi))), c30 = T(0.25 * sqrt(7.0 / kPi)),
+          c32b = T(0.25 * sqrt(105.0 / kPi));
   gd[0] += 6.0 * c33 * x * y * f[9] + c32 * y * z * f[10] + c31 * (5.0 * z * z - 1.0) * f[13] +
            2.0 * c32b * x * z * f[14] + c33 * (3.0 * x * x - 3.0 * y * y) * f[15];
   gd[1] += c33 * (3.0 * x * x - 3.0 * y * y) * f[9] + c32 * x * z * f[10] +
@@ -124,34 +125,40 @@ __device__ inline void sh_grad_dot(int deg, double x, double y, double z, const 
            10.0 * c31 * x * z * f[13] + c32b * (x * x - y * y) * f[14];
 }
 
-// Forward geometry of one Gaussian, float64.
-struct Geo {
-  double mu[3], s[3], qn[4], qnorm, o, Rg[9], M[9], Sig[6];
-  double X, Y, Z, A0[3], A1[3], a, b, c, det;
-  double u, v;
+// Geometry of one Gaussian.  The forward projection runs in float64 (T =
+// double) so every integer decision matches a float64 reference; the
+// backward chain rule runs in float32 (T = float), which halves its
+// registers.
+template <typename T>
+struct GeoT {
+  T mu[3], s[3], qn[4], qnorm, o, Rg[9], M[9], Sig[6];
+  T X, Y, Z, A0[3], A1[3], a, b, c, det;
+  T u, v;
   bool culled;
   int i0, i1, j0, j1;
 };
+using Geo = GeoT<double>;
 
 // Camera-independent part: activations, rotation, covariance.
+template <typename T>
 __device__ inline void load_gauss(const float *__restrict__ P, int64_t stride, int64_t i,
-                                  Geo &g) {
-  for (int k = 0; k < 3; ++k) g.mu[k] = (double)P[k * stride + i];
-  for (int k = 0; k < 3; ++k) g.s[k] = exp((double)P[(3 + k) * stride + i]);
-  double q[4];
-  for (int k = 0; k < 4; ++k) q[k] = (double)P[(6 + k) * stride + i];
-  g.o = 1.0 / (1.0 + exp(-(double)P[10 * stride + i]));
+                                  GeoT<T> &g) {
+  for (int k = 0; k < 3; ++k) g.mu[k] = (T)P[k * stride + i];
+  for (int k = 0; k < 3; ++k) g.s[k] = exp((T)P[(3 + k) * stride + i]);
+  T q[4];
+  for (int k = 0; k < 4; ++k) q[k] = (T)P[(6 + k) * stride + i];
+  g.o = T(1) / (T(1) + exp(-(T)P[10 * stride + i]));
   g.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   for (int k = 0; k < 4; ++k) g.qn[k] = q[k] / g.qnorm;
-  const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
-  double *R = g.Rg;
+  const T w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+  T *R = g.Rg;
   R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
   R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
   R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c) g.M[3 * r + c] = R[3 * r + c] * g.s[c];
   // Sigma = M M^T: xx, xy, xz, yy, yz, zz
-  const double *M = g.M;
+  const T *M = g.M;
   g.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
   g.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
   g.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
@@ -161,64 +168,69 @@ __device__ inline void load_gauss(const float *__restrict__ P, int64_t stride, i
 }
 
 // Camera-dependent part: camera coordinates, culling, EWA, conic, pixel box.
-__device__ inline void project(const CamD &cam, Geo &g) {
-  const double *Rc = cam.R;
-  g.X = Rc[0] * g.mu[0] + Rc[1] * g.mu[1] + Rc[2] * g.mu[2] + cam.t[0];
-  g.Y = Rc[3] * g.mu[0] + Rc[4] * g.mu[1] + Rc[5] * g.mu[2] + cam.t[1];
-  g.Z = Rc[6] * g.mu[0] + Rc[7] * g.mu[1] + Rc[8] * g.mu[2] + cam.t[2];
-  g.culled = !(g.Z > cam.zn);
+template <typename T>
+__device__ inline void project(const CamD &cam, GeoT<T> &g) {
+  T Rc[9];
+  for (int k = 0; k < 9; ++k) Rc[k] = (T)cam.R[k];
+  g.X = Rc[0] * g.mu[0] + Rc[1] * g.mu[1] + Rc[2] * g.mu[2] + (T)cam.t[0];
+  g.Y = Rc[3] * g.mu[0] + Rc[4] * g.mu[1] + Rc[5] * g.mu[2] + (T)cam.t[1];
+  g.Z = Rc[6] * g.mu[0] + Rc[7] * g.mu[1] + Rc[8] * g.mu[2] + (T)cam.t[2];
+  g.culled = !(g.Z > (T)cam.zn);
   if (!g.culled) {
-    const double rx = fabs(g.X / g.Z), ry = fabs(g.Y / g.Z);
-    g.culled = (rx > cam.limx) || (ry > cam.limy) || (g.o < 1.0 / 255.0);
+    const T rx = fabs(g.X / g.Z), ry = fabs(g.Y / g.Z);
+    g.culled = (rx > (T)cam.limx) || (ry > (T)cam.limy) || (g.o < T(1.0 / 255.0));
   }
   if (g.culled) return;
-  const double iz = 1.0 / g.Z;
-  const double j00 = cam.fx * iz, j02 = -cam.fx * g.X * iz * iz;
-  const double j11 = cam.fy * iz, j12 = -cam.fy * g.Y * iz * iz;
+  const T fx = (T)cam.fx, fy = (T)cam.fy;
+  const T iz = T(1) / g.Z;
+  const T j00 = fx * iz, j02 = -fx * g.X * iz * iz;
+  const T j11 = fy * iz, j12 = -fy * g.Y * iz * iz;
   for (int c = 0; c < 3; ++c) {
     g.A0[c] = j00 * Rc[c] + j02 * Rc[6 + c];
     g.A1[c] = j11 * Rc[3 + c] + j12 * Rc[6 + c];
   }
-  const double *S = g.Sig;
-  auto quad = [&](const double *p, const double *q) {
-    const double sx = S[0] * q[0] + S[1] * q[1] + S[2] * q[2];
-    const double sy = S[1] * q[0] + S[3] * q[1] + S[4] * q[2];
-    const double sz = S[2] * q[0] + S[4] * q[1] + S[5] * q[2];
+  const T *S = g.Sig;
+  auto quad = [&](const T *p, const T *q) {
+    const T sx = S[0] * q[0] + S[1] * q[1] + S[2] * q[2];
+    const T sy = S[1] * q[0] + S[3] * q[1] + S[4] * q[2];
+    const T sz = S[2] * q[0] + S[4] * q[1] + S[5] * q[2];
     return p[0] * sx + p[1] * sy + p[2] * sz;
   };
-  g.a = quad(g.A0, g.A0) + kDilation;
+  g.a = quad(g.A0, g.A0) + T(kDilation);
   g.b = quad(g.A0, g.A1);
-  g.c = quad(g.A1, g.A1) + kDilation;
+  g.c = quad(g.A1, g.A1) + T(kDilation);
   g.det = g.a * g.c - g.b * g.b;
-  if (!(g.det > 0.0)) {
+  if (!(g.det > T(0))) {
     g.culled = true;
     return;
   }
-  g.u = cam.fx * g.X / g.Z + cam.cx;
-  g.v = cam.fy * g.Y / g.Z + cam.cy;
-  const double r2 = 2.0 * log(255.0 * g.o);
-  const double ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
-  const double big = 1e9;
-  const double e0 = fmin(fmax(g.u - ex - 0.5, -big), big), e1 = fmin(fmax(g.u + ex - 0.5, -big), big);
-  const double f0 = fmin(fmax(g.v - ey - 0.5, -big), big), f1 = fmin(fmax(g.v + ey - 0.5, -big), big);
-  g.i0 = (int)fmax(ceil(e0), 0.0);
-  g.i1 = (int)fmin(floor(e1), (double)(cam.W - 1));
-  g.j0 = (int)fmax(ceil(f0), 0.0);
-  g.j1 = (int)fmin(floor(f1), (double)(cam.H - 1));
+  g.u = fx * g.X / g.Z + (T)cam.cx;
+  g.v = fy * g.Y / g.Z + (T)cam.cy;
+  const T r2 = T(2) * log(T(255) * g.o);
+  const T ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
+  const T big = T(1e9);
+  const T e0 = fmin(fmax(g.u - ex - T(0.5), -big), big), e1 = fmin(fmax(g.u + ex - T(0.5), -big), big);
+  const T f0 = fmin(fmax(g.v - ey - T(0.5), -big), big), f1 = fmin(fmax(g.v + ey - T(0.5), -big), big);
+  g.i0 = (int)fmax(ceil(e0), T(0));
+  g.i1 = (int)fmin(floor(e1), (T)(cam.W - 1));
+  g.j0 = (int)fmax(ceil(f0), T(0));
+  g.j1 = (int)fmin(floor(f1), (T)(cam.H - 1));
   if (g.i0 > g.i1 || g.j0 > g.j1) g.culled = true;
 }
 
+template <typename T>
 __device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int64_t i,
-                                const CamD &cam, Geo &g) {
+                                const CamD &cam, GeoT<T> &g) {
   load_gauss(P, stride, i, g);
   project(cam, g);
 }
 
-// Colour before the clamp (raw) for each channel, float64.
+// Colour before the clamp (raw) for each channel.
+template <typename T>
 __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, int64_t i,
-                                 int deg, const Geo &g, const CamD &cam, double *dir,
-                                 double &dnorm, double *Y, double raw[3]) {
-  double d0 = g.mu[0] - cam.C[0], d1 = g.mu[1] - cam.C[1], d2 = g.mu[2] - cam.C[2];
+                                 int deg, const GeoT<T> &g, const CamD &cam, T *dir, T &dnorm,
+                                 T *Y, T raw[3]) {
+  T d0 = g.mu[0] - (T)cam.C[0], d1 = g.mu[1] - (T)cam.C[1], d2 = g.mu[2] - (T)cam.C[2];
   dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
   dir[0] = d0 / dnorm;
   dir[1] = d1 / dnorm;
@@ -226,9 +238,12 @@ __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, in
   sh_eval(deg, dir[0], dir[1], dir[2], Y);
   const int K = (deg + 1) * (deg + 1);
   for (int ch = 0; ch < 3; ++ch) {
-    double acc = 0.0;
-    for (int k = 0; k < K; ++k) acc += (double)P[(11 + 3 * k + ch) * stride + i] * Y[k];
-    raw[ch] = acc + 0.5;
+    T acc = T(0);
+    // not unrolled: the 48 coefficient loads would otherwise be hoisted
+    // into registers and cap the occupancy of the backward kernel
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) acc += (T)P[(11 + 3 * k + ch) * stride + i] * Y[k];
+    raw[ch] = acc + T(0.5);
   }
 }
 
@@ -718,91 +733,94 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 // Chain the ten screen-space gradient terms s[] of one (view, Gaussian)
 // record to the raw parameters: out[0..10] for mean, log-scale, quaternion
 // and opacity logit; Yb[k] * graw[c] for SH coefficient k of channel c.
+template <typename T>
 __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, int64_t i,
-                                   int deg, const Geo &g, const CamD &cam, const float s[10],
-                                   double out[11], double Yb[16], double graw[3]) {
-  const double gu = s[0], gv = s[1], gQ00 = s[2], gQ01 = s[3], gQ11 = s[4];
-  const double go = s[5], gz_depth = s[9];
+                                   int deg, const GeoT<T> &g, const CamD &cam, const float s[10],
+                                   T out[11], T Yb[16], T graw[3]) {
+  const T gu = s[0], gv = s[1], gQ00 = s[2], gQ01 = s[3], gQ11 = s[4];
+  const T go = s[5], gz_depth = s[9];
   // conic Q = Sigma2^-1 -> Sigma2 entries a, b, c
-  const double det = g.det, a = g.a, b = g.b, c = g.c;
-  const double gdet = -(gQ00 * c - gQ01 * b + gQ11 * a) / (det * det);
-  const double ga = gQ11 / det + gdet * c;
-  const double gb = -gQ01 / det - 2.0 * b * gdet;
-  const double gc = gQ00 / det + gdet * a;
+  const T det = g.det, a = g.a, b = g.b, c = g.c;
+  const T gdet = -(gQ00 * c - gQ01 * b + gQ11 * a) / (det * det);
+  const T ga = gQ11 / det + gdet * c;
+  const T gb = -gQ01 / det - T(2) * b * gdet;
+  const T gc = gQ00 / det + gdet * a;
   // Sigma2 = A Sigma A^T: G_Sigma = A^T G2 A, G_A = 2 G2 A Sigma
-  const double G2[2][2] = {{ga, 0.5 * gb}, {0.5 * gb, gc}};
-  const double A[2][3] = {{g.A0[0], g.A0[1], g.A0[2]}, {g.A1[0], g.A1[1], g.A1[2]}};
-  const double *Sg = g.Sig;
-  const double Sig[3][3] = {{Sg[0], Sg[1], Sg[2]}, {Sg[1], Sg[3], Sg[4]}, {Sg[2], Sg[4], Sg[5]}};
-  double GA[2][3], GS[3][3];
+  const T G2[2][2] = {{ga, T(0.5) * gb}, {T(0.5) * gb, gc}};
+  const T A[2][3] = {{g.A0[0], g.A0[1], g.A0[2]}, {g.A1[0], g.A1[1], g.A1[2]}};
+  const T *Sg = g.Sig;
+  const T Sig[3][3] = {{Sg[0], Sg[1], Sg[2]}, {Sg[1], Sg[3], Sg[4]}, {Sg[2], Sg[4], Sg[5]}};
+  T GA[2][3], GS[3][3];
   {
-    double G2A[2][3];
+    T G2A[2][3];
     for (int r = 0; r < 2; ++r)
       for (int k = 0; k < 3; ++k) G2A[r][k] = G2[r][0] * A[0][k] + G2[r][1] * A[1][k];
     for (int r = 0; r < 2; ++r)
       for (int k = 0; k < 3; ++k)
-        GA[r][k] = 2.0 * (G2A[r][0] * Sig[0][k] + G2A[r][1] * Sig[1][k] + G2A[r][2] * Sig[2][k]);
+        GA[r][k] = T(2) * (G2A[r][0] * Sig[0][k] + G2A[r][1] * Sig[1][k] + G2A[r][2] * Sig[2][k]);
     for (int r = 0; r < 3; ++r)
       for (int k = 0; k < 3; ++k) GS[r][k] = A[0][r] * G2A[0][k] + A[1][r] * G2A[1][k];
   }
   // A = J Rc -> G_J = G_A Rc^T
-  const double *Rc = cam.R;
-  double GJ[2][3];
+  T Rc[9];
+  for (int k = 0; k < 9; ++k) Rc[k] = (T)cam.R[k];
+  T GJ[2][3];
   for (int r = 0; r < 2; ++r)
     for (int k = 0; k < 3; ++k)
       GJ[r][k] = GA[r][0] * Rc[3 * k] + GA[r][1] * Rc[3 * k + 1] + GA[r][2] * Rc[3 * k + 2];
-  const double iz = 1.0 / g.Z, iz2 = iz * iz, iz3 = iz2 * iz;
-  const double fx = cam.fx, fy = cam.fy, X = g.X, Y = g.Y;
-  double gX = GJ[0][2] * (-fx * iz2) + gu * fx * iz;
-  double gY = GJ[1][2] * (-fy * iz2) + gv * fy * iz;
-  double gZ = GJ[0][0] * (-fx * iz2) + GJ[0][2] * (2.0 * fx * X * iz3) +
-              GJ[1][1] * (-fy * iz2) + GJ[1][2] * (2.0 * fy * Y * iz3) +
+  const T iz = T(1) / g.Z, iz2 = iz * iz, iz3 = iz2 * iz;
+  const T fx = (T)cam.fx, fy = (T)cam.fy, X = g.X, Y = g.Y;
+  T gX = GJ[0][2] * (-fx * iz2) + gu * fx * iz;
+  T gY = GJ[1][2] * (-fy * iz2) + gv * fy * iz;
+  T gZ = GJ[0][0] * (-fx * iz2) + GJ[0][2] * (T(2) * fx * X * iz3) +
+              GJ[1][1] * (-fy * iz2) + GJ[1][2] * (T(2) * fy * Y * iz3) +
               gu * (-fx * X * iz2) + gv * (-fy * Y * iz2) + gz_depth;
-  double gmu[3];
+  T gmu[3];
   for (int k = 0; k < 3; ++k) gmu[k] = Rc[k] * gX + Rc[3 + k] * gY + Rc[6 + k] * gZ;
   // Sigma = M M^T, M = Rg diag(s)
-  double GM[3][3];
+  T GM[3][3];
   for (int r = 0; r < 3; ++r)
     for (int k = 0; k < 3; ++k)
-      GM[r][k] = 2.0 * (GS[r][0] * g.M[k] + GS[r][1] * g.M[3 + k] + GS[r][2] * g.M[6 + k]);
-  double GR[3][3], gls[3];
+      GM[r][k] = T(2) * (GS[r][0] * g.M[k] + GS[r][1] * g.M[3 + k] + GS[r][2] * g.M[6 + k]);
+  T GR[3][3], gls[3];
   for (int k = 0; k < 3; ++k) {
-    double gsk = 0.0;
+    T gsk = T(0);
     for (int r = 0; r < 3; ++r) {
       GR[r][k] = GM[r][k] * g.s[k];
       gsk += GM[r][k] * g.Rg[3 * r + k];
     }
     gls[k] = gsk * g.s[k];
   }
-  const double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
-  double gqn[4];
-  gqn[0] = 2.0 * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
-  gqn[1] = 2.0 * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.0 * x * GR[1][1] - w * GR[1][2] +
-                  z * GR[2][0] + w * GR[2][1] - 2.0 * x * GR[2][2]);
-  gqn[2] = 2.0 * (-2.0 * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] -
-                  w * GR[2][0] + z * GR[2][1] - 2.0 * y * GR[2][2]);
-  gqn[3] = 2.0 * (-2.0 * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - 2.0 * z * GR[1][1] +
+  const T w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+  T gqn[4];
+  gqn[0] = T(2) * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+  gqn[1] = T(2) * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - T(2) * x * GR[1][1] - w * GR[1][2] +
+                  z * GR[2][0] + w * GR[2][1] - T(2) * x * GR[2][2]);
+  gqn[2] = T(2) * (-T(2) * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] -
+                  w * GR[2][0] + z * GR[2][1] - T(2) * y * GR[2][2]);
+  gqn[3] = T(2) * (-T(2) * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] - T(2) * z * GR[1][1] +
                   y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
-  const double dq = g.qn[0] * gqn[0] + g.qn[1] * gqn[1] + g.qn[2] * gqn[2] + g.qn[3] * gqn[3];
-  double gq[4];
+  const T dq = g.qn[0] * gqn[0] + g.qn[1] * gqn[1] + g.qn[2] * gqn[2] + g.qn[3] * gqn[3];
+  T gq[4];
   for (int k = 0; k < 4; ++k) gq[k] = (gqn[k] - g.qn[k] * dq) / g.qnorm;
-  const double glogit = go * g.o * (1.0 - g.o);
+  const T glogit = go * g.o * (T(1) - g.o);
   // colour
-  double dir[3], dn, raw[3];
+  T dir[3], dn, raw[3];
   color_raw(P, stride, i, deg, g, cam, dir, dn, Yb, raw);
-  for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > 0.0 ? (double)s[6 + ch] : 0.0;
+  for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > T(0) ? (T)s[6 + ch] : T(0);
   const int K = (deg + 1) * (deg + 1);
   if (deg > 0) {
-    double f[16];
-    f[0] = 0.0;
+    T f[16];
+    f[0] = T(0);
+#pragma unroll 1
     for (int k = 1; k < K; ++k) {
-      double a = 0.0;
-      for (int ch = 0; ch < 3; ++ch) a += (double)P[(11 + 3 * k + ch) * stride + i] * graw[ch];
+      T a = T(0);
+      for (int ch = 0; ch < 3; ++ch) a += (T)P[(11 + 3 * k + ch) * stride + i] * graw[ch];
       f[k] = a;
     }
-    double gd[3];
+    T gd[3];
     sh_grad_dot(deg, dir[0], dir[1], dir[2], f, gd);
-    const double dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
+    const T dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
     for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) / dn;
   }
   out[0] = gmu[0]; out[1] = gmu[1]; out[2] = gmu[2];
@@ -868,7 +886,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
   for (int r = 0; r < 11; ++r) acc[r] = accumulate ? grad[r * gstride + i] : 0.0f;
   bool sh_written = accumulate != 0;
-  Geo g;
+  GeoT<float> g;
   load_gauss(P, stride, i, g);  // camera-independent: once for all views
   for (int v = 0; v < V; ++v) {
     const int64_t rr = v * n + i;
@@ -878,14 +896,15 @@ __global__ void __launch_bounds__(256)
     float s[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) s[c] = s2d[c * RS + rr];
-    double out[11], Yb[16], graw[3];
+    float out[11], Yb[16], graw[3];
     param_grads(P, stride, i, DEG, g, cam, s, out, Yb, graw);
 #pragma unroll
-    for (int r = 0; r < 11; ++r) acc[r] += (float)out[r];
+    for (int r = 0; r < 11; ++r) acc[r] += out[r];
+#pragma unroll 1
     for (int k = 0; k < K; ++k)
       for (int ch = 0; ch < 3; ++ch) {
         const int64_t idx = (int64_t)(11 + 3 * k + ch) * gstride + i;
-        const float val = (float)(Yb[k] * graw[ch]);
+        const float val = Yb[k] * graw[ch];
         grad[idx] = sh_written ? grad[idx] + val : 0.0f + val;
       }
     sh_written = true;

@@ -102,6 +102,7 @@ SIGNATURES = {
     "dcgs_loss_l1": (INT, [P, P, P, I64, DBL, P, P, P]),
     "dcgs_adam_step": (INT, [P, P, P, I64, I64, P, P]),
     "dcgs_loss_mapping": (INT, [P, P, P, P, P, INT, INT, INT, DBL, DBL, P, P, P, P]),
+    "dcgs_sample_pixels": (INT, [P, P, P, P, INT, INT, DBL, DBL, P, P, P, P]),
     "dcgs_autotune": (INT, [P, P, P, I64, I64, INT, P, P, INT, INT, P, P, P, P]),
     "dcgs_window_create": (INT, [P, P, P, C.POINTER(P)]),
     "dcgs_window_destroy": (None, [P]),
@@ -255,6 +256,19 @@ class Context:
             float(lambda_s), float(lambda_depth), ptr(dl), ptr(dld), ptr(st),
             stream_handle(stream)))
         return dl, dld, st
+
+    def sample_pixels(self, image, render, u, beta=2.0, sigma=1.0, stream=None):
+        """LoG sampling: (P_s map [H, W], raster indices of the sampled
+        pixels) for image, render [3, H, W] and draws u [H, W]."""
+        import torch
+        H, W = image.shape[-2], image.shape[-1]
+        ps = torch.empty(H, W, dtype=torch.float32, device=image.device)
+        idx = torch.empty(H * W, dtype=torch.int32, device=image.device)
+        cnt = torch.zeros(1, dtype=torch.int32, device=image.device)
+        self.check(lib().dcgs_sample_pixels(self.h, ptr(image), ptr(render), ptr(u), H, W,
+                                            float(beta), float(sigma), ptr(ps), ptr(idx),
+                                            ptr(cnt), stream_handle(stream)))
+        return ps, idx[:int(cnt.item())]
 
     @staticmethod
     def loss_value(stats, n_views: int, H: int, W: int, lambda_s: float,
