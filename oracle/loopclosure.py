@@ -16,16 +16,19 @@ Readings (the paper describes the steps, not their arithmetic):
   rotation quaternion q = (w, x, y, z) becomes q_R (x) q (Hamilton product),
   q_R the unit quaternion of R with w >= 0; scales, opacity and colour
   coefficients are unchanged, and so are its Adam moments and step count;
-* redistribution: every Gaussian's chunk is recomputed (Eq. 5) from its
-  float32 mean; the store is regrouped by chunk in ascending EncodedID,
-  keeping the previous order (ascending old EncodedID, then stored order)
-  among the Gaussians of a chunk;
+* redistribution: a transformed Gaussian's chunk is recomputed (Eq. 5)
+  from its corrected float32 mean; every other Gaussian stays in the chunk
+  the store holds it in (optimisation may have moved its mean across a
+  chunk face: only the correction reassigns); the store is regrouped by
+  chunk in ascending EncodedID, keeping the previous order (ascending old
+  EncodedID, then stored order) among the Gaussians of a chunk;
 * refinement reset, after redistribution: for every Gaussian of the chunks
   a junction camera selects, the opacity logit becomes min(logit,
   logit(0.01)), its Adam moments 0 and its step count 0.
 
 The store is the flat [R][N] parameter array (and moments [R][N], steps
-[N]) in store order: ascending EncodedID, stored order inside a chunk.
+[N]) with the EncodedID of the chunk holding each Gaussian [N], in store
+order: ascending EncodedID, stored order inside a chunk.
 
 What pins each function (tests/test_oracle_loopclosure.py): the identity
 correction changes nothing; a pure translation by one chunk side shifts
@@ -33,7 +36,8 @@ every transformed Gaussian's chunk coordinate by one; the rotation matrix
 of the corrected quaternion equals R times the old rotation (textbook
 quaternion-to-matrix formula); overlapping keyframes apply the first
 correction only; the regrouped order against a brute-force stable sort;
-the reset touches exactly the junction chunks.
+the reset touches exactly the junction chunks; an untransformed Gaussian
+whose mean left its chunk stays there.
 """
 from __future__ import annotations
 
@@ -64,9 +68,9 @@ def store_ids(params: np.ndarray, s: float) -> np.ndarray:
     return oc.encode_id(oc.chunk_coord(params[0:3].T, s))
 
 
-def assign(params: np.ndarray, s: float, keyframes: list) -> np.ndarray:
-    """Index of the correction applied to each Gaussian (-1: none)."""
-    ids = store_ids(params, s)
+def assign(ids: np.ndarray, s: float, keyframes: list) -> np.ndarray:
+    """Index of the correction applied to each Gaussian (-1: none), given
+    the EncodedID of the chunk holding it."""
     chunk_ids = np.unique(ids)
     owner = {}
     for k, (cam, _, _) in enumerate(keyframes):
@@ -75,12 +79,16 @@ def assign(params: np.ndarray, s: float, keyframes: list) -> np.ndarray:
     return np.array([owner.get(int(c), -1) for c in ids], np.int64)
 
 
-def loop_closure(params, m, v, step, s: float, keyframes: list, junctions: list) -> dict:
+def loop_closure(params, m, v, step, ids, s: float, keyframes: list, junctions: list) -> dict:
     """Apply the correction; returns the regrouped store (params, m, v,
-    step as float32/int32 arrays), the applied correction per Gaussian in
-    the new order (-1: none), and the reset mask in the new order."""
+    step as float32/int32 arrays, chunk ids), the applied correction per
+    Gaussian in the new order (-1: none), and the reset mask in the new
+    order."""
     P = np.array(params, np.float32, copy=True)
-    own = assign(P, s, keyframes)
+    old_ids = np.asarray(ids, np.uint64)
+    if (old_ids[1:] < old_ids[:-1]).any():
+        raise ValueError("the store must be in ascending EncodedID order")
+    own = assign(old_ids, s, keyframes)
     for k, (_, R, t) in enumerate(keyframes):
         sel = own == k
         if not sel.any():
@@ -94,10 +102,7 @@ def loop_closure(params, m, v, step, s: float, keyframes: list, junctions: list)
         q = quat_mul(qr[None, :], P[ROW_QUAT:ROW_QUAT + 4, sel].T.astype(np.float64)).T
         P[0:3, sel] = mu.astype(np.float32)
         P[ROW_QUAT:ROW_QUAT + 4, sel] = q.astype(np.float32)
-    old_ids = store_ids(np.asarray(params, np.float32), s)
-    if (np.diff(old_ids.astype(np.float64)) < 0).any():
-        raise ValueError("the store must be in ascending EncodedID order")
-    new_ids = store_ids(P, s)
+    new_ids = np.where(own >= 0, store_ids(P, s), old_ids)
     # the store is already in the previous order: a stable sort keeps it
     order = np.argsort(new_ids, kind="stable")
     out = dict(params=P[:, order], m=np.asarray(m, np.float32)[:, order].copy(),

@@ -9,17 +9,21 @@ from oracle import chunks as oc
 from oracle import loopclosure as olc
 
 
-def _scene(n=6000, seed=3):
+def _scene(n=6000, seed=3, drift=True):
     sc = scenegen.room_scene(n, seed=seed, sh_degree=0)
     P = sc["params"]
     ids = oc.encode_id(oc.chunk_coord(P[0:3].T, 2.0))
     order = np.lexsort((np.arange(P.shape[1]), ids))   # store order
-    P = P[:, order]
+    P, ids = P[:, order], ids[order]
+    # optimisation has moved some means across a chunk face since they were
+    # assigned: their stored chunk is not the one their mean lies in
+    if drift:
+        P[0, ::7] += np.float32(1.5)
     rng = np.random.default_rng(seed)
     m = rng.normal(size=P.shape).astype(np.float32)
     v = rng.uniform(size=P.shape).astype(np.float32)
     step = rng.integers(1, 50, P.shape[1]).astype(np.int32)
-    return P, m, v, step
+    return P, m, v, step, ids
 
 
 def _cam(pos, yaw):
@@ -34,18 +38,19 @@ def _rot_from_quat(q):
 
 
 def test_identity_correction_changes_nothing():
-    P, m, v, step = _scene()
-    out = olc.loop_closure(P, m, v, step, 2.0, [(_cam((4, 4, 1.5), 0.3), np.eye(3), np.zeros(3))],
+    P, m, v, step, ids = _scene(drift=False)
+    out = olc.loop_closure(P, m, v, step, ids, 2.0, [(_cam((4, 4, 1.5), 0.3), np.eye(3), np.zeros(3))],
                            [])
     assert (out["params"] == P).all() and (out["m"] == m).all() and (out["step"] == step).all()
+    assert (out["ids"] == ids).all()
     assert (out["owner"] >= 0).any()
 
 
 def test_translation_by_one_chunk_moves_chunks_by_one():
-    P, m, v, step = _scene()
+    P, m, v, step, ids = _scene()
     kf = [(_cam((4, 4, 1.5), 0.3), np.eye(3), np.array([2.0, 0.0, 0.0]))]
-    own = olc.assign(P, 2.0, kf)
-    out = olc.loop_closure(P, m, v, step, 2.0, kf, [])
+    own = olc.assign(ids, 2.0, kf)
+    out = olc.loop_closure(P, m, v, step, ids, 2.0, kf, [])
     moved = out["owner"] == 0
     assert moved.sum() == (own == 0).sum() > 100
     # the moved Gaussians, in their old store order, are the ones assigned
@@ -61,17 +66,16 @@ def test_translation_by_one_chunk_moves_chunks_by_one():
 
 
 def test_rotation_composes_and_first_keyframe_wins():
-    P, m, v, step = _scene()
+    P, m, v, step, ids = _scene()
     R1 = Rotation.from_euler("z", 7, degrees=True).as_matrix()
     R2 = Rotation.from_euler("x", 11, degrees=True).as_matrix()
     kf = [(_cam((4, 4, 1.5), 0.0), R1, np.array([0.1, -0.2, 0.05])),
           (_cam((4, 4, 1.5), 0.4), R2, np.array([0.3, 0.0, 0.0]))]
-    own = olc.assign(P, 2.0, kf)
-    both = set(oc.select_chunks([kf[0][0]], np.unique(olc.store_ids(P, 2.0)), 2.0)["union_ids"].tolist())
-    ids = olc.store_ids(P, 2.0)
+    own = olc.assign(ids, 2.0, kf)
+    both = set(oc.select_chunks([kf[0][0]], np.unique(ids), 2.0)["union_ids"].tolist())
     assert ((own == 0) == np.isin(ids, np.array(sorted(both), np.uint64))).all()
     assert (own == 1).any() and (own == -1).any()
-    out = olc.loop_closure(P, m, v, step, 2.0, kf, [])
+    out = olc.loop_closure(P, m, v, step, ids, 2.0, kf, [])
     for k, R in ((0, R1), (1, R2)):
         sel_old = np.nonzero(own == k)[0][:20]
         for i in sel_old:
@@ -88,16 +92,16 @@ def test_rotation_composes_and_first_keyframe_wins():
 
 
 def test_regrouping_is_a_stable_sort_by_new_chunk():
-    P, m, v, step = _scene()
+    P, m, v, step, ids0 = _scene()
     kf = [(_cam((4, 4, 1.5), 0.3), Rotation.from_euler("z", 20, degrees=True).as_matrix(),
            np.array([0.7, 0.9, 0.0]))]
-    out = olc.loop_closure(P, m, v, step, 2.0, kf, [])
+    out = olc.loop_closure(P, m, v, step, ids0, 2.0, kf, [])
     ids = out["ids"]
-    assert (np.diff(ids.astype(np.float64)) >= 0).all()
+    assert (ids[1:] >= ids[:-1]).all()
     # within each chunk the m rows (unique per Gaussian) keep the old order
     pos_old = {tuple(m[:, i]): i for i in range(0, P.shape[1])}
     old_pos = np.array([pos_old[tuple(out["m"][:, j])] for j in range(P.shape[1])])
-    old_ids = olc.store_ids(P, 2.0)
+    old_ids = ids0
     for c in np.unique(ids):
         sel = np.nonzero(ids == c)[0]
         keys = list(zip(old_ids[old_pos[sel]], old_pos[sel]))
@@ -106,17 +110,17 @@ def test_regrouping_is_a_stable_sort_by_new_chunk():
 
 
 def test_reset_touches_exactly_the_junction_chunks():
-    P, m, v, step = _scene()
+    P, m, v, step, ids = _scene()
     P[10, ::3] = -9.0                       # below the cap: kept
     # the correction moves part of the map into chunks that were empty before,
     # and the junction camera looks at them
     kf = [(_cam((4, 4, 1.5), 0.3), np.eye(3), np.array([20.0, 0.0, 0.0]))]
     jc = _cam((18, 6, 1.5), 0.3)
-    out = olc.loop_closure(P, m, v, step, 2.0, kf, [jc])
+    out = olc.loop_closure(P, m, v, step, ids, 2.0, kf, [jc])
     vis = oc.select_chunks([jc], np.unique(out["ids"]), 2.0)["union_ids"]
     want = np.isin(out["ids"], vis)
     assert (out["reset"] == want).all() and want.any() and (~want).any()
-    assert not np.isin(vis, olc.store_ids(P, 2.0)).all()
+    assert not np.isin(vis, ids).all()
     assert (out["m"][:, want] == 0).all() and (out["v"][:, want] == 0).all()
     assert (out["step"][want] == 0).all()
     lg = out["params"][10]
@@ -136,3 +140,20 @@ def _old_of(P, out, sel):
     for j in np.nonzero(sel)[0]:
         mask[key[tuple(out["params"][11:, j])]] = True
     return mask
+
+
+def test_only_the_correction_reassigns_chunks():
+    P, m, v, step, ids = _scene()
+    kf = [(_cam((4, 4, 1.5), 0.3), Rotation.from_euler("z", 5, degrees=True).as_matrix(),
+           np.array([0.4, 0.0, 0.0]))]
+    out = olc.loop_closure(P, m, v, step, ids, 2.0, kf, [])
+    pos_old = {tuple(m[:, i]): i for i in range(P.shape[1])}
+    src = np.array([pos_old[tuple(out["m"][:, j])] for j in range(P.shape[1])])
+    untouched = out["owner"] < 0
+    # untransformed Gaussians keep their stored chunk, drifted or not
+    assert (out["ids"][untouched] == ids[src[untouched]]).all()
+    drifted = ids != olc.store_ids(P, 2.0)
+    assert (drifted[src[untouched]]).any()
+    # transformed ones are in the chunk of their corrected mean
+    moved = ~untouched
+    assert (out["ids"][moved] == olc.store_ids(out["params"][:, moved], 2.0)).all()
