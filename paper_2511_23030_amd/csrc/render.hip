@@ -469,32 +469,42 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
-    for (int k = 0; k < nb && n_live > 0; ++k) {
+    for (int k = 0; k < nb; ++k) {
+      // a wavefront whose pixels are all saturated leaves the batch
+      if ((k & 7) == 0) {
+        bool live = false;
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) live = live || !done[j];
+        if (__ballot(live) == 0) break;
+      }
       const float4 C = sC[k];
       if (!box_meets_rows(C, wy0, wy1)) continue;  // no pixel of this wave is in the box
       const float4 A = sA[k], B = sB[k];
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        if (done[j]) continue;
+        // predicated rather than branched: a lane that does not composite
+        // adds exact zeros, and the wavefront issues no mask bookkeeping.
+        // Contraction is off in this kernel: every raster shape composites
+        // with the same roundings.
         const Sample s = sample(px, py0 + j, A, B, C);
-        if (!s.ok) continue;
-        // contraction is off in this kernel: every raster shape composites
-        // with the same roundings
-        const float Tn = T[j] * (1.0f - s.alpha);
-        if (Tn < kTMin) {
-          done[j] = true;
-          --n_live;
-          continue;
-        }
-        const float w = s.alpha * T[j];
+        const bool act = s.ok && !done[j];
+        const float a = act ? s.alpha : 0.0f;
+        const float Tn = T[j] * (1.0f - a);
+        const bool stop = act && Tn < kTMin;
+        const bool comp = act && !stop;
+        const float w = comp ? a * T[j] : 0.0f;
         c0[j] = __builtin_fmaf(B.z, w, c0[j]);
         c1[j] = __builtin_fmaf(B.w, w, c1[j]);
         c2[j] = __builtin_fmaf(C.x, w, c2[j]);
         D[j] = __builtin_fmaf(C.y, w, D[j]);
-        T[j] = Tn;
-        last[j] = base + k;
+        T[j] = comp ? Tn : T[j];
+        last[j] = comp ? base + k : last[j];
+        done[j] = done[j] || stop;
       }
     }
+    n_live = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) n_live += !done[j];
   }
   const int64_t HW = (int64_t)W * H;
 #pragma unroll
@@ -668,14 +678,16 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       bool contrib = false;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
-        if (pos > last[j]) continue;
+        // predicated rather than branched: a lane whose pixel does not use
+        // this Gaussian runs with alpha = 0 (1 / (1 - 0) is exact), which
+        // leaves T and S unchanged and adds exact zeros to every term
         const Sample s = sample(px, py0 + j, A, B, C);
-        if (!s.ok) continue;
-        contrib = true;
-        const float om = 1.0f - s.alpha;
-        const float iom = __builtin_amdgcn_rcpf(om);
+        const bool act = s.ok && pos <= last[j];
+        contrib = contrib || act;
+        const float a = act ? s.alpha : 0.0f;
+        const float iom = __builtin_amdgcn_rcpf(1.0f - a);
         const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
-        const float w = s.alpha * Tk;
+        const float w = a * Tk;
         v[6] += g0[j] * w;
         v[7] += g1[j] * w;
         v[8] += g2[j] * w;
@@ -687,15 +699,16 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         S2[j] += C.x * w;
         SD[j] += C.y * w;
         T[j] = Tk;
-        if (B.y * s.G <= kAlphaMax) {  // alpha not clamped
-          const float dp = s.alpha * da;
-          v[5] += s.G * da;
-          v[0] += dp * (A.z * s.dx + A.w * s.dy);
-          v[1] += dp * (A.w * s.dx + B.x * s.dy);
-          v[2] += -0.5f * s.dx * s.dx * dp;
-          v[3] += -s.dx * s.dy * dp;
-          v[4] += -0.5f * s.dy * s.dy * dp;
-        }
+        // alpha not clamped: the opacity and the exponent receive gradient
+        const bool free_alpha = act && B.y * s.G <= kAlphaMax;
+        const float gG = free_alpha ? s.G : 0.0f;
+        const float dp = free_alpha ? a * da : 0.0f;
+        v[5] += gG * da;
+        v[0] += dp * (A.z * s.dx + A.w * s.dy);
+        v[1] += dp * (A.w * s.dx + B.x * s.dy);
+        v[2] += -0.5f * s.dx * s.dx * dp;
+        v[3] += -s.dx * s.dy * dp;
+        v[4] += -0.5f * s.dy * s.dy * dp;
       }
       if (__ballot(contrib) != 0) {
         const float r = wave_reduce16(v);
