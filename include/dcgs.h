@@ -182,6 +182,42 @@ int dcgs_pool_read_chunk(dcgs_pool *pool, uint64_t id, float *params,
 int dcgs_pool_resident(dcgs_pool *pool, uint64_t *ids, int capacity,
                        int *n_out, int64_t *gaussians_out);
 
+/* ---- loop closure: Sec. III-G ----------------------------------------------- */
+
+/* SYNC.  Correct the store after a loop closure.
+ *  "Cross-Chunk Transformation": for the affected keyframes in order
+ *  (keyframes: host [n_keyframes] cameras, any count), the chunks each one
+ *  sees (the visibility test of dcgs_select_chunks) take that keyframe's
+ *  rigid correction, a chunk seen by several taking the first one's (the
+ *  global transformation mask).  corrections: host float64
+ *  [n_keyframes][12], a row-major rotation R (9) then a translation t (3),
+ *  mapping old world coordinates to corrected ones.  Each Gaussian of such a
+ *  chunk gets mean <- R mean + t (float64, each product and sum rounded, no
+ *  fused multiply-add, then rounded to float32) and quaternion <- q_R (x) q
+ *  (Hamilton product, q_R the unit quaternion of R with w >= 0); its other
+ *  parameters and its Adam state are kept.
+ *  "Chunk Redistribution": a corrected Gaussian moves to the chunk of its
+ *  new mean (Eqs. 5-6); every other Gaussian stays in its chunk.  Chunks
+ *  stay in ascending id order; inside a chunk, Gaussians keep the previous
+ *  order (old chunk id, then position).
+ *  "Post-Correction Refinement": every Gaussian of the chunks (after
+ *  redistribution) that a junction camera sees (junctions: host
+ *  [n_junctions]) gets its opacity logit set to min(logit, logit(0.01))
+ *  (float32 of log(0.01/0.99)), its moments m, v and its step set to 0.
+ * All affected chunks are processed in one batch on the device: it needs
+ * room for about two copies of them (parameters and Adam state) besides the
+ * pool.  The rebuilt chunks are written to a new pinned host block and are
+ * not resident afterwards; chunks that lost all their Gaussians disappear.
+ * stats (host, first n_stats of 7, nullable): affected chunks, corrected
+ * Gaussians, corrected Gaussians that changed chunk, chunks rebuilt (taken
+ * apart), chunks written, Gaussians reset, chunks in the store afterwards.
+ * DCGS_E_RANGE if a corrected mean leaves the Eq. (6) range or the batch
+ * holds 2^32 slots or more (the store is unchanged then). */
+int dcgs_pool_loop_closure(dcgs_pool *pool, const dcgs_camera *keyframes,
+                           const double *corrections, int n_keyframes,
+                           const dcgs_camera *junctions, int n_junctions, int64_t *stats,
+                           int n_stats, void *stream);
+
 /* ---- compaction: Sec. III-E ("index only the visible Gaussians") ---------- */
 
 /* Concatenate the Gaussians of the resident chunks `ids` (host, n_ids, any

@@ -18,7 +18,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libdcgs.so")
 ARCH = "gfx950"
 SOURCES = ["chunks.hip", "sort.hip", "render.hip", "stream_ops.hip", "loss.hip", "sampling.hip",
-           "prefetch.hip", "pool.cpp", "window.cpp", "api.cpp"]
+           "prefetch.hip", "loopclosure.hip", "pool.cpp", "window.cpp", "api.cpp"]
 
 
 def hipcc() -> str:

@@ -214,6 +214,17 @@ int dcgs_pool_resident(dcgs_pool *pool, uint64_t *ids, int capacity, int *n_out,
   });
 }
 
+int dcgs_pool_loop_closure(dcgs_pool *pool, const dcgs_camera *keyframes,
+                           const double *corrections, int n_keyframes,
+                           const dcgs_camera *junctions, int n_junctions, int64_t *stats,
+                           int n_stats, void *stream) {
+  if (!pool) return DCGS_E_INVALID;
+  return guarded(pool->ctx, [&] {
+    dcgs::pool_loop_closure(pool, keyframes, corrections, n_keyframes, junctions, n_junctions,
+                            stats, n_stats, S(stream));
+  });
+}
+
 int dcgs_compact(dcgs_pool *pool, const uint64_t *ids, const uint16_t *masks, int n_ids,
                  float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
                  int64_t capacity, int64_t *n_out, void *stream) {

@@ -100,18 +100,23 @@ void launch_chunk_ids(const float *mean, int64_t n, int64_t stride, double s,
   DCGS_LAUNCH_CHECK();
 }
 
+void launch_select_mask(const dcgs_camera *cams, int n_views, const uint64_t *ids,
+                        int n_chunks, double s, uint16_t *mask, hipStream_t st) {
+  if (n_chunks <= 0) return;
+  DCGS_CHECK(n_views >= 1 && n_views <= kMaxViews, DCGS_E_INVALID, "select: 1..16 views");
+  CamSet args{};
+  for (int v = 0; v < n_views; ++v) args.c[v] = to_cam(cams[v]);
+  const int blocks = (n_chunks + 255) / 256;
+  hipLaunchKernelGGL(k_select_mask, dim3(blocks), dim3(256), 0, st, args, n_views, ids,
+                     n_chunks, s, mask);
+  DCGS_LAUNCH_CHECK();
+}
+
 void launch_select(const dcgs_camera *cams, int n_views, const uint64_t *ids,
                    int n_chunks, double s, uint16_t *mask_tmp,
                    uint64_t *out_ids, uint16_t *out_mask, int32_t *out_count,
                    hipStream_t st) {
-  CamSet args{};
-  for (int v = 0; v < n_views; ++v) args.c[v] = to_cam(cams[v]);
-  if (n_chunks > 0) {
-    int blocks = (n_chunks + 255) / 256;
-    hipLaunchKernelGGL(k_select_mask, dim3(blocks), dim3(256), 0, st, args,
-                       n_views, ids, n_chunks, s, mask_tmp);
-    DCGS_LAUNCH_CHECK();
-  }
+  launch_select_mask(cams, n_views, ids, n_chunks, s, mask_tmp, st);
   hipLaunchKernelGGL(k_select_compact, dim3(1), dim3(1024), 0, st, ids,
                      mask_tmp, n_chunks, out_ids, out_mask, out_count);
   DCGS_LAUNCH_CHECK();

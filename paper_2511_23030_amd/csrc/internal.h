@@ -154,7 +154,8 @@ struct HostChunk {
   uint64_t id = 0;
   int64_t n = 0;
   int64_t pages = 0;
-  float *params = nullptr;  // [pages][R][PG] inside the pinned arena
+  int block = -1;           // host block holding the chunk's pages
+  float *params = nullptr;  // [pages][R][PG] inside the block
   float *m = nullptr;
   float *v = nullptr;
   int32_t *step = nullptr;  // [pages][PG]
@@ -170,6 +171,7 @@ struct dcgs_pool {
   dcgs_ctx *ctx = nullptr;
   int deg = 0, R = 0;
   int64_t budget = 0;        // Gaussians
+  double s = 0;              // chunk side (metres), fixed at ingest
   int64_t page_cap = 0;      // device pages
   int64_t resident_g = 0;    // Gaussians resident
   static constexpr int PG_LOG2 = 12;
@@ -178,9 +180,13 @@ struct dcgs_pool {
   float *d_params = nullptr, *d_m = nullptr, *d_v = nullptr;
   int32_t *d_step = nullptr;
   std::vector<int32_t> free_pages;  // kept sorted descending (pop_back = lowest)
-  // host store
-  char *arena = nullptr;
-  size_t arena_bytes = 0;
+  // host store: pinned blocks, each holding whole chunks (params, m, v and
+  // step pages back to back); a block is freed when no chunk lives in it
+  struct HostBlock {
+    char *base = nullptr;
+    int64_t live = 0;  // chunks stored in the block
+  };
+  std::vector<HostBlock> blocks;
   std::vector<HostChunk> chunks;               // ascending id
   std::unordered_map<uint64_t, int> index;     // id -> position in chunks
   dcgs::DevBuf<uint64_t> d_ids;                // ascending ids on device
@@ -232,6 +238,9 @@ void launch_select(const dcgs_camera *cams, int n_views, const uint64_t *ids,
                    int n_chunks, double s, uint16_t *mask_tmp,
                    uint64_t *out_ids, uint16_t *out_mask, int32_t *out_count,
                    hipStream_t st);
+// Per-chunk view mask only (bit v: view v sees the chunk), 1..16 views.
+void launch_select_mask(const dcgs_camera *cams, int n_views, const uint64_t *ids,
+                        int n_chunks, double s, uint16_t *mask, hipStream_t st);
 void launch_compact(const float *pool, int R, const int4 *seg, int n_seg,
                     const uint16_t *seg_mask, float *out, int64_t out_stride,
                     int32_t *out_src, uint16_t *out_gmask, hipStream_t st);
@@ -326,6 +335,11 @@ void window_launch(dcgs_window *w, const uint64_t *ids, const uint16_t *masks, i
 void window_sync(dcgs_window *w, int64_t *pairs_required, int *skipped);
 void window_pairs(dcgs_window *w, int64_t *n_pairs);
 dcgs_ctx *window_ctx(dcgs_window *w);
+void pool_loop_closure(dcgs_pool *p, const dcgs_camera *keyframes, const double *corr, int n_kf,
+                       const dcgs_camera *junctions, int n_junctions, int64_t *stats,
+                       int n_stats, hipStream_t st);
+void pool_release_chunk(dcgs_pool *p, HostChunk &h);
+void pool_index(dcgs_pool *p, hipStream_t st);
 void pool_compact(dcgs_pool *p, const uint64_t *ids, const uint16_t *masks, int n_ids,
                   float *out, int64_t out_stride, int32_t *out_src, uint16_t *out_gmask,
                   int64_t capacity, int64_t *n_out, hipStream_t st);

@@ -2,8 +2,9 @@
 // Eviction Strategy").
 //
 // Host store: every chunk's Gaussians (parameters, Adam moments, step
-// counts) in one pinned arena, page-major [page][row][4096], so a page moves
-// between host and device with one DMA copy.  Device pool: the same page
+// counts) in pinned blocks, page-major [page][row][4096], so a page moves
+// between host and device with one DMA copy.  Ingest writes one block; each
+// loop closure writes the chunks it rebuilds into a new one.  Device pool: the same page
 // layout, sized for the budget; a resident chunk owns a list of pages,
 // allocated lowest-first so a chunk's pages are usually one contiguous run
 // (one copy per run).
@@ -153,7 +154,8 @@ void pool_destroy(dcgs_pool *p) {
   if (p->d_m) (void)hipFree(p->d_m);
   if (p->d_v) (void)hipFree(p->d_v);
   if (p->d_step) (void)hipFree(p->d_step);
-  if (p->arena) (void)hipHostFree(p->arena);
+  for (auto &b : p->blocks)
+    if (b.base) (void)hipHostFree(b.base);
   if (p->h_seg) (void)hipHostFree(p->h_seg);
   if (p->seg_done) (void)hipEventDestroy(p->seg_done);
   if (p->cut) (void)hipEventDestroy(p->cut);
@@ -168,6 +170,7 @@ void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStre
   DCGS_CHECK(params && n > 0 && s > 0, DCGS_E_INVALID, "pool_ingest: bad args");
   DCGS_CHECK(p->chunks.empty(), DCGS_E_INVALID, "pool_ingest: pool already holds a scene");
   const int R = p->R;
+  p->s = s;
   // 1. chunk id of every Gaussian, computed on the device in batches
   std::vector<uint64_t> ids(n);
   const int64_t B = std::min<int64_t>(n, int64_t(1) << 22);
@@ -209,17 +212,20 @@ void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStre
     runs.push_back({k, e});
     k = e;
   }
-  // 3. pinned arena: params, m, v pages + step pages per chunk
+  // 3. one pinned block: params, m, v pages + step pages per chunk
   const size_t fpage = (size_t)R * PG * sizeof(float), spage = (size_t)PG * sizeof(int32_t);
   int64_t total_pages = 0;
   for (auto &r : runs) total_pages += pages_of(r.second - r.first);
-  p->arena_bytes = (size_t)total_pages * (3 * fpage + spage);
-  DCGS_HIP(hipHostMalloc((void **)&p->arena, p->arena_bytes, hipHostMallocDefault));
-  std::memset(p->arena, 0, p->arena_bytes);
-  char *cur = p->arena;
+  const size_t block_bytes = (size_t)total_pages * (3 * fpage + spage);
+  char *base = nullptr;
+  DCGS_HIP(hipHostMalloc((void **)&base, block_bytes, hipHostMallocDefault));
+  p->blocks.push_back({base, (int64_t)runs.size()});
+  std::memset(base, 0, block_bytes);
+  char *cur = base;
   p->chunks.resize(runs.size());
   for (size_t c = 0; c < runs.size(); ++c) {
     HostChunk &h = p->chunks[c];
+    h.block = (int)p->blocks.size() - 1;
     h.id = ids[idx[runs[c].first]];
     h.n = runs[c].second - runs[c].first;
     h.pages = pages_of(h.n);
@@ -232,7 +238,6 @@ void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStre
     h.step = (int32_t *)cur;
     cur += h.pages * spage;
     DCGS_HIP(hipEventCreateWithFlags(&h.ready, hipEventDisableTiming));
-    p->index[h.id] = (int)c;
   }
   // 4. scatter the input rows into the page-major store (threads over rows)
   auto fill_rows = [&](int r0, int r1) {
@@ -259,12 +264,43 @@ void pool_ingest(dcgs_pool *p, const float *params, int64_t n, double s, hipStre
   DCGS_HIP(hipMalloc(&p->d_step, p->page_cap * spage));
   p->free_pages.resize(p->page_cap);
   for (int64_t k = 0; k < p->page_cap; ++k) p->free_pages[k] = (int32_t)(p->page_cap - 1 - k);
-  std::vector<uint64_t> h_ids(runs.size());
-  for (size_t c = 0; c < runs.size(); ++c) h_ids[c] = p->chunks[c].id;
+  pool_index(p, st);
+}
+
+void pool_index(dcgs_pool *p, hipStream_t st) {
+  p->index.clear();
+  std::vector<uint64_t> h_ids(p->chunks.size());
+  for (size_t c = 0; c < p->chunks.size(); ++c) {
+    h_ids[c] = p->chunks[c].id;
+    p->index[h_ids[c]] = (int)c;
+  }
+  if (h_ids.empty()) return;
   uint64_t *d = p->d_ids.need(h_ids.size());
   DCGS_HIP(hipMemcpyAsync(d, h_ids.data(), h_ids.size() * sizeof(uint64_t),
                           hipMemcpyHostToDevice, st));
   DCGS_HIP(hipStreamSynchronize(st));
+}
+
+// Drop a chunk from the store (the caller has synchronised the device and
+// keeps what it needs of the chunk's data): its device pages go back to the
+// pool, and its block is freed once it holds no chunk.
+void pool_release_chunk(dcgs_pool *p, HostChunk &h) {
+  if (h.resident) {
+    release_pages(p, h.dev_pages);
+    h.dev_pages.clear();
+    h.resident = false;
+    p->resident_g -= h.n;
+  }
+  if (h.ready) (void)hipEventDestroy(h.ready);
+  h.ready = nullptr;
+  if (h.block >= 0) {
+    auto &b = p->blocks[h.block];
+    if (--b.live == 0 && b.base) {
+      (void)hipHostFree(b.base);
+      b.base = nullptr;
+    }
+  }
+  h.block = -1;
 }
 
 void pool_require(dcgs_pool *p, const uint64_t *ids, int n, int64_t now, int *loaded,

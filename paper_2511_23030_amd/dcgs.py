@@ -94,6 +94,7 @@ SIGNATURES = {
     "dcgs_pool_stats": (INT, [P, P, INT]),
     "dcgs_pool_resident": (INT, [P, P, INT, C.POINTER(INT), C.POINTER(I64)]),
     "dcgs_compact": (INT, [P, P, P, INT, P, I64, P, P, I64, C.POINTER(I64), P]),
+    "dcgs_pool_loop_closure": (INT, [P, P, P, INT, P, INT, P, INT, P]),
     "dcgs_state_create": (INT, [P, C.POINTER(P)]),
     "dcgs_state_destroy": (None, [P]),
     "dcgs_render_fwd": (INT, [P, P, P, I64, I64, INT, P, INT, P, INT, P, INT, INT, INT, P, P, P,
@@ -351,6 +352,29 @@ class Pool:
         self.ctx.check(lib().dcgs_pool_read_chunk(self.h, int(cid), p.ctypes.data, m.ctypes.data,
                                                   v.ctypes.data, s.ctypes.data))
         return p, m, v, s
+
+    LOOP_STAT_NAMES = ("affected_chunks", "corrected", "moved", "chunks_rebuilt",
+                       "chunks_written", "reset", "chunks_after")
+
+    def loop_closure(self, keyframes: list, corrections, junctions: list = (), stream=None) -> dict:
+        """Sec. III-G correction of the store.  corrections: [K][3][4] or
+        [K][12] float64, rotation rows then translation (R | t)."""
+        K = len(keyframes)
+        corr = np.zeros((max(K, 1), 12), np.float64)
+        if K:
+            c = np.asarray(corrections, np.float64).reshape(K, -1)
+            if c.shape[1] == 12 and np.asarray(corrections).ndim == 3:   # [K][3][4]
+                c3 = np.asarray(corrections, np.float64)
+                c = np.concatenate([c3[:, :, :3].reshape(K, 9), c3[:, :, 3]], 1)
+            corr[:K] = c
+        kf = (Camera * max(K, 1))(*[Camera.of(x) for x in keyframes])
+        J = len(junctions)
+        jc = (Camera * max(J, 1))(*[Camera.of(x) for x in junctions])
+        out = np.zeros(7, np.int64)
+        self.ctx.check(lib().dcgs_pool_loop_closure(self.h, C.cast(kf, P), corr.ctypes.data, K,
+                                                    C.cast(jc, P), J, out.ctypes.data, 7,
+                                                    stream_handle(stream)))
+        return dict(zip(self.LOOP_STAT_NAMES, out.tolist()))
 
     def resident(self):
         n, g = INT(), I64()

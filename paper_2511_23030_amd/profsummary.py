@@ -1,7 +1,9 @@
 """Summarise a rocprofv3 run: per-kernel calls and durations from the
 ``top_kernels`` view of its rocpd database, as a Markdown table.
 
-python -m paper_2511_23030_amd.profsummary <run_results.db> [title]
+python -m paper_2511_23030_amd.profsummary <run_results.db>
+python -m paper_2511_23030_amd.profsummary traffic <fetch.csv> <write.csv> <kernel regex>
+    <copy regex> <copy bytes> <source file> <out.json> <command>
 """
 from __future__ import annotations
 
@@ -69,6 +71,9 @@ def source_digest(path: str) -> str:
 
 
 def _main(argv):
+    if len(argv) < 2 or argv[1] in ("-h", "--help"):
+        print(__doc__)
+        return
     if argv[1] == "traffic":
         # traffic <fetch.csv> <write.csv> <kernel regex> <copy regex> <copy bytes> <source> <out.json> <command>
         import json
@@ -83,9 +88,6 @@ def _main(argv):
     else:
         print(summary(argv[1]))
 
-
-if __name__ == "__main__":
-    _main(sys.argv)
 
 
 def trace_summary(trace_csv: str, focus_regex: str, limit: int = 16) -> str:
@@ -114,3 +116,7 @@ def trace_summary(trace_csv: str, focus_regex: str, limit: int = 16) -> str:
         out.append(f"Largest launch of `{n}` (grid {g} threads): {len(v)} calls, average "
                    f"{sum(v) / len(v) / 1e3:.3f} ms.")
     return "\n".join(out)
+
+
+if __name__ == "__main__":
+    _main(sys.argv)
