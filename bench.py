@@ -158,13 +158,14 @@ def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray, budget_s: float = 2
                        f"({t_full_pre:.1f} s) is not counted twice")}
 
 
-def prefetch_study(ctx, w, make_loop, run, cursor, n_plain, log) -> dict:
+def prefetch_study(ctx, w, make_loop, run, cursor, n_walk, log) -> dict:
     """Learned prefetch on the driving corridor: train the network on the
     exact labels of 20 corridor layouts (seeds 100-119), measure chunk misses
     against the exact test on 5 held-out layouts (120-124), then time the
     plain per-keyframe path on this workload three ways, each from a fresh
-    pool: no staging ahead (misses load on demand), staging the network's
-    predictions, staging the next keyframe's exact selection."""
+    pool over the same stretch of the walk: no staging ahead (misses load on
+    demand), staging the network's predictions, staging the next keyframe's
+    exact selection."""
     import scenegen
 
     from paper_2511_23030_amd import prefetch as PF
@@ -188,21 +189,24 @@ def prefetch_study(ctx, w, make_loop, run, cursor, n_plain, log) -> dict:
                                                              for h in held])), 1)}
     log(f"prefetch network: trained in {t_train:.1f} s, held-out miss rate "
         f"{rep['held_out_miss_rate']:.4f} vs {rep['held_out_miss_rate_without']:.4f} without")
+    # a walk long enough for chunks to enter at the far plane and leave
+    # behind (2 m per keyframe: ~800 m), timed after the first view's set
+    # is loaded; pool counters are those of the timed stretch
+    keys = ("loads", "misses", "hits", "prefetched", "evictions", "bytes_h2d")
     for mode in ("none", "mlp", "exact"):
         pool, loop = make_loop()
         cursor["plain_" + mode] = (0, None)
-        run(loop, "plain_" + mode, 4, prefetch=mode, net=net)          # warm
-        cursor["plain_" + mode] = (0, None)
-        pool.close()
-        pool, loop = make_loop()
-        t = run(loop, "plain_" + mode, n_plain, prefetch=mode, net=net)
-        st = pool.stats()
-        rep[f"plain_{mode}_iters_per_s"] = round(n_plain / t, 3)
-        rep[f"plain_{mode}_pool"] = {k: st[k] for k in ("loads", "misses", "hits", "prefetched",
-                                                       "evictions", "bytes_h2d")}
-        log(f"plain, prefetch {mode}: {n_plain / t:.2f} iters/s, pool {st}")
+        run(loop, "plain_" + mode, 8, prefetch=mode, net=net)          # warm
+        s0 = pool.stats()
+        t = run(loop, "plain_" + mode, n_walk, prefetch=mode, net=net)
+        s1 = pool.stats()
+        st = {k: s1[k] - s0[k] for k in keys}
+        rep[f"plain_{mode}_iters_per_s"] = round(n_walk / t, 3)
+        rep[f"plain_{mode}_pool"] = st
+        log(f"plain, prefetch {mode}: {n_walk / t:.2f} iters/s over {n_walk} keyframes, pool {st}")
         pool.close()
         del loop
+    rep["plain_keyframes"] = n_walk
     return rep
 
 
@@ -402,7 +406,7 @@ def main():
     l1, psnr = loop_b.loss_psnr(3 * w["W"] * w["H"])
     prefetch_report = None
     if walk and not args.no_prefetch_mlp:
-        prefetch_report = prefetch_study(ctx, w, make_loop, run, cursor, n_plain, log)
+        prefetch_report = prefetch_study(ctx, w, make_loop, run, cursor, max(n_plain, 400), log)
 
     # stage profile of the batched path, outside the timed region
     ctx.profile(True)

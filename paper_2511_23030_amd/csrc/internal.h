@@ -130,6 +130,7 @@ struct dcgs_state {
   dcgs::DevBuf<uint32_t> key_tmp, val_tmp;
   dcgs::DevBuf<uint32_t> scan;      // [n + 1] pair offsets in depth order
   dcgs::DevBuf<uint32_t> pair_off;  // [n] pair offset by Gaussian
+  dcgs::DevBuf<uint64_t> tmask;     // [n] kept tiles of the record's tile rectangle
   // per pair
   dcgs::DevBuf<uint64_t> pairs, pairs_tmp;
   dcgs::DevBuf<float4> partial;  // [3 * P] per-pair gradient partials

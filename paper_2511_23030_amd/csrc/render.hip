@@ -247,6 +247,71 @@ __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, in
   }
 }
 
+// Tiles of a record's tile rectangle that can hold a pixel it composites.
+// Bit k (row-major in the rectangle) is set when the rectangle of pixel
+// centres that tile k shares with the pixel box meets the ellipse
+// f(d) = d^T Q d <= tau' (Q the conic, d relative to (u, v)): alpha >= 1/255
+// exactly where f <= tau = 2 ln(255 o), and tau' = (tau + 1e-3 (1 + tau)) /
+// (1 - 16 u kappa), u = 2^-24, kappa = 2 (Q00 + Q11) / lambda_min(Q), covers
+// the float32 evaluation of a sample, so a tile that is dropped holds no
+// pixel the float32 compositing would take.  The minimum of the convex f
+// over a rectangle not holding the centre lies on an edge, at the clamped
+// minimiser of f along it.  Every tile is kept when the rectangle has more
+// than 64 tiles or 16 u kappa >= 1/2.  n_keep gets the number kept.
+__device__ inline uint64_t tile_mask(const Geo &g, int TW, int TH, uint32_t &n_keep) {
+  const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
+  const int w = tx1 - tx0 + 1, n_rect = w * (ty1 - ty0 + 1);
+  const double half = 0.5 * (g.a - g.c);
+  const double lmax = 0.5 * (g.a + g.c) + sqrt(half * half + g.b * g.b);  // of Sigma2
+  const double kappa = 2.0 * (g.a + g.c) / g.det * lmax;
+  const double shrink = 1.0 - 16.0 * 0x1p-24 * kappa;
+  if (n_rect > 64 || !(shrink > 0.5)) {
+    n_keep = (uint32_t)n_rect;
+    return n_rect >= 64 ? ~uint64_t(0) : ((uint64_t(1) << n_rect) - 1);
+  }
+  const double tau = 2.0 * log(255.0 * g.o);
+  const double lim = (tau + 1e-3 * (1.0 + tau)) / shrink;
+  const double idet = 1.0 / g.det;
+  const double q00 = g.c * idet, q01x2 = -2.0 * g.b * idet, q11 = g.a * idet;
+  // minimiser of f along x = const is y = (b / a) x, along y = const x = (b / c) y
+  const double sy = g.b / g.a, sx = g.b / g.c;
+  const double uh = g.u - 0.5, vh = g.v - 0.5;
+  uint32_t lo = 0, hi = 0;
+  int k = 0;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const double y0 = max(ty * TH, g.j0) - vh, y1 = min(ty * TH + TH - 1, g.j1) - vh;
+    for (int tx = tx0; tx <= tx1; ++tx, ++k) {
+      const double x0 = max(tx * TW, g.i0) - uh, x1 = min(tx * TW + TW - 1, g.i1) - uh;
+      bool keep = x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0;
+      if (!keep) {
+        double best = INFINITY;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double xe = e ? x1 : x0, ye = e ? y1 : y0;
+          const double yc = fmin(fmax(sy * xe, y0), y1), xc = fmin(fmax(sx * ye, x0), x1);
+          best = fmin(best, xe * (q00 * xe + q01x2 * yc) + q11 * yc * yc);
+          best = fmin(best, xc * (q00 * xc + q01x2 * ye) + q11 * ye * ye);
+        }
+        keep = best <= lim;
+      }
+      if (keep) {
+        if (k < 32) lo |= 1u << k; else hi |= 1u << (k - 32);
+      }
+    }
+  }
+  n_keep = (uint32_t)(__popc(lo) + __popc(hi));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Slot of tile k of a record's rectangle among its kept tiles.
+__device__ __forceinline__ uint32_t kept_rank(uint64_t m, int n_rect, int k) {
+  return n_rect > 64 ? (uint32_t)k : (uint32_t)__popcll(m & ((uint64_t(1) << k) - 1));
+}
+
+__device__ __forceinline__ bool tile_kept(uint64_t m, int n_rect, int k) {
+  return n_rect > 64 || ((m >> k) & 1);
+}
+
 // One thread per Gaussian; it projects the Gaussian into every view whose
 // bit is set in its chunk's view mask.  Record r = v * n + g; the three
 // record planes are RS apart.  cnt[0] = n (device counter; the grid may be
@@ -257,7 +322,7 @@ __global__ void __launch_bounds__(256)
                  const uint16_t *__restrict__ gmask, int mask_shift, int TW, int TH,
                  float4 *__restrict__ rec, int64_t RS, uint32_t *__restrict__ zkey,
                  uint32_t *__restrict__ sortkey, uint32_t *__restrict__ order,
-                 uint32_t *__restrict__ count) {
+                 uint32_t *__restrict__ count, uint64_t *__restrict__ tmask) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0];
   if (i >= n) return;
@@ -278,6 +343,7 @@ __global__ void __launch_bounds__(256)
     zkey[r] = __float_as_uint(zf);
     if (culled) {
       count[r] = 0;
+      tmask[r] = 0;
       sortkey[r] = kCulledKey;
       rec[r] = make_float4(0, 0, 0, 0);
       rec[RS + r] = make_float4(0, 0, 0, 0);
@@ -286,8 +352,9 @@ __global__ void __launch_bounds__(256)
     }
     double dir[3], dn, Y[16], raw[3];
     color_raw(P, stride, i, deg, g, cam, dir, dn, Y, raw);
-    const int tx0 = g.i0 / TW, tx1 = g.i1 / TW, ty0 = g.j0 / TH, ty1 = g.j1 / TH;
-    count[r] = (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    uint32_t n_keep;
+    tmask[r] = tile_mask(g, TW, TH, n_keep);
+    count[r] = n_keep;
     sortkey[r] = __float_as_uint(zf);
     const double id = 1.0 / g.det;
     rec[r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(g.c * id),
@@ -324,9 +391,9 @@ __global__ void k_pairs_total(const uint32_t *__restrict__ scan, int64_t *__rest
 // depth order, tiles of a record row-major.
 __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
                        const uint32_t *__restrict__ scan, const float4 *__restrict__ recC,
-                       const int64_t *__restrict__ cnt, int TW, int TH, int tiles_x,
-                       int tiles_per_view, uint64_t *__restrict__ pairs,
-                       uint32_t *__restrict__ pair_off) {
+                       const uint64_t *__restrict__ tmask, const int64_t *__restrict__ cnt,
+                       int TW, int TH, int tiles_x, int tiles_per_view,
+                       uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
   if (j >= nr || cnt[3] != 0) return;
@@ -340,10 +407,14 @@ __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__res
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
   const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
+  const int n_rect = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+  const uint64_t m = tmask[g];
   uint32_t k = base;
+  int idx = 0;
   for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx)
-      pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | g;
+    for (int tx = tx0; tx <= tx1; ++tx, ++idx)
+      if (tile_kept(m, n_rect, idx))
+        pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | g;
 }
 
 __global__ void k_ranges(const uint64_t *__restrict__ pairs, const int64_t *__restrict__ cnt,
@@ -376,10 +447,14 @@ struct Sample {
   float power, G, alpha, dx, dy;
 };
 
+
 // The one definition of a (pixel, Gaussian) sample, shared by forward and
 // backward so that both take identical threshold decisions.
-__device__ __forceinline__ Sample sample(int px, int py, const float4 &A, const float4 &B,
-                                         const float4 &C) {
+// pxh, pyh: the pixel centre px + 0.5, py + 0.5 as floats.  The offset from
+// the box corner, (px + 0.5) - i0, is exact in float32 (both are exact and
+// so is their difference), so dx is the rounding of (px - i0 + 0.5) - A.x.
+__device__ __forceinline__ Sample sample(int px, int py, float pxh, float pyh, const float4 &A,
+                                         const float4 &B, const float4 &C) {
   // No implicit FMA contraction here: every kernel that inlines this takes
   // the same roundings (HIP's __f*_rn helpers are plain operators).
 #pragma clang fp contract(off)
@@ -387,8 +462,8 @@ __device__ __forceinline__ Sample sample(int px, int py, const float4 &A, const 
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int i0 = bx & 0xFFFF, i1 = bx >> 16, j0 = by & 0xFFFF, j1 = by >> 16;
   s.ok = px >= i0 && px <= i1 && py >= j0 && py <= j1;
-  s.dx = ((float)(px - i0) + 0.5f) - A.x;
-  s.dy = ((float)(py - j0) + 0.5f) - A.y;
+  s.dx = (pxh - (float)i0) - A.x;
+  s.dy = (pyh - (float)j0) - A.y;
   const float qxx = A.z * (s.dx * s.dx);
   const float qyy = B.x * (s.dy * s.dy);
   const float qxy = A.w * (s.dx * s.dy);
@@ -443,6 +518,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   // lane t owns PPT vertically adjacent pixels of the tile
   const int px = tx * TW + (threadIdx.x % TW);
   const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
+  const float pxh = (float)px + 0.5f;
+  float pyh[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) pyh[j] = (float)(py0 + j) + 0.5f;
   int wy0, wy1;
   wave_rows<TW, PPT>(ty * TH, wy0, wy1);
   const int2 rg = ranges[gt];
@@ -486,7 +565,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         // adds exact zeros, and the wavefront issues no mask bookkeeping.
         // Contraction is off in this kernel: every raster shape composites
         // with the same roundings.
-        const Sample s = sample(px, py0 + j, A, B, C);
+        const Sample s = sample(px, py0 + j, pxh, pyh[j], A, B, C);
         const bool act = s.ok && !done[j];
         const float a = act ? s.alpha : 0.0f;
         const float Tn = T[j] * (1.0f - a);
@@ -592,7 +671,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                  const float *__restrict__ Tstate, const int *__restrict__ last_in,
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
                  const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
-                 float4 *__restrict__ partial, int *__restrict__ frontier) {
+                 const uint64_t *__restrict__ tmask, float4 *__restrict__ partial,
+                 int *__restrict__ frontier) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
   constexpr int BS = NT < 128 ? NT : 128;  // records per batch
@@ -614,6 +694,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   }
   const int px = tx * TW + (threadIdx.x % TW);
   const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
+  const float pxh = (float)px + 0.5f;
+  float pyh[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) pyh[j] = (float)(py0 + j) + 0.5f;
   int wy0, wy1;
   wave_rows<TW, PPT>(ty * TH, wy0, wy1);
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
@@ -681,7 +765,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         // predicated rather than branched: a lane whose pixel does not use
         // this Gaussian runs with alpha = 0 (1 / (1 - 0) is exact), which
         // leaves T and S unchanged and adds exact zeros to every term
-        const Sample s = sample(px, py0 + j, A, B, C);
+        const Sample s = sample(px, py0 + j, pxh, pyh[j], A, B, C);
         const bool act = s.ok && pos <= last[j];
         contrib = contrib || act;
         const float a = act ? s.alpha : 0.0f;
@@ -732,8 +816,11 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const uint32_t g = sG[k];
       const float4 C = sC[k];
       const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
-      const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW, ty0 = (by & 0xFFFF) / TH;
-      const uint32_t slot = pair_off[g] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+      const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
+      const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
+      const int wc = tx1 - tx0 + 1;
+      const uint32_t slot = pair_off[g] + kept_rank(tmask[g], wc * (ty1 - ty0 + 1),
+                                                    (ty - ty0) * wc + (tx - tx0));
       partial[3 * (int64_t)slot] = make_float4(s[0], s[1], s[2], s[3]);
       partial[3 * (int64_t)slot + 1] = make_float4(s[4], s[5], s[6], s[7]);
       partial[3 * (int64_t)slot + 2] = make_float4(s[8], s[9], 0.0f, 0.0f);
@@ -849,28 +936,31 @@ __global__ void __launch_bounds__(256)
     k_sum_partials(const int64_t *__restrict__ cnt, int64_t RS, int TW, int TH, int tiles_x,
                    int tiles_per_view, const float4 *__restrict__ recC,
                    const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
-                   const uint32_t *__restrict__ rank_of, const int *__restrict__ frontier,
-                   const float4 *__restrict__ partial, float *__restrict__ s2d) {
+                   const uint32_t *__restrict__ rank_of, const uint64_t *__restrict__ tmask,
+                   const int *__restrict__ frontier, const float4 *__restrict__ partial,
+                   float *__restrict__ s2d) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
   if (r >= nr || cnt[3] != 0) return;
-  const uint32_t tiles = count[r];
   float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (tiles > 0) {
+  if (count[r] > 0) {
     const float4 C = recC[r];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
     const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
-    const int ty0 = (int)(by & 0xFFFF) / TH;
-    const int wc = tx1 - tx0 + 1;
+    const int ty0 = (int)(by & 0xFFFF) / TH, ty1 = (int)(by >> 16) / TH;
+    const int wc = tx1 - tx0 + 1, n_rect = wc * (ty1 - ty0 + 1);
+    const uint64_t m = tmask[r];
     const int tile_base = (int)(r / n) * tiles_per_view;
-    const uint32_t base = pair_off[r];
+    uint32_t slot = pair_off[r];
     const int rank = (int)rank_of[r];
-    for (uint32_t k = 0; k < tiles; ++k) {
-      const int t = tile_base + (ty0 + (int)k / wc) * tiles_x + tx0 + (int)k % wc;
+    for (int k = 0; k < n_rect; ++k) {
+      if (!tile_kept(m, n_rect, k)) continue;
+      const int t = tile_base + (ty0 + k / wc) * tiles_x + tx0 + k % wc;
+      const uint32_t sl = slot++;
       if (frontier[t] < rank) continue;
-      const float4 p0 = partial[3 * (int64_t)(base + k)];
-      const float4 p1 = partial[3 * (int64_t)(base + k) + 1];
-      const float4 p2 = partial[3 * (int64_t)(base + k) + 2];
+      const float4 p0 = partial[3 * (int64_t)sl];
+      const float4 p1 = partial[3 * (int64_t)sl + 1];
+      const float4 p2 = partial[3 * (int64_t)sl + 2];
       s[0] += p0.x; s[1] += p0.y; s[2] += p0.z; s[3] += p0.w;
       s[4] += p1.x; s[5] += p1.y; s[6] += p1.z; s[7] += p1.w;
       s[8] += p2.x; s[9] += p2.y;
@@ -884,7 +974,9 @@ __global__ void __launch_bounds__(256)
 // r = v n + g of every view that drew it contributes, in view order, with
 // float32 accumulation (the same additions as one single-view backward per
 // view accumulating into the gradient buffer).  The eleven geometry rows
-// accumulate in registers; the SH rows are added in place view by view.
+// accumulate in registers, the 3 (DEG+1)^2 SH rows in this thread's LDS
+// column (one global write per row instead of a read-modify-write per
+// view).
 template <int DEG>
 __global__ void __launch_bounds__(256)
     k_preprocess_bwd(const float *__restrict__ P, const int64_t *__restrict__ cnt,
@@ -892,13 +984,17 @@ __global__ void __launch_bounds__(256)
                      const uint32_t *__restrict__ count, const float *__restrict__ s2d,
                      int64_t RS, float *__restrict__ grad, int64_t gstride, int accumulate) {
   constexpr int K = (DEG + 1) * (DEG + 1), R = 11 + 3 * K;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float sh[3 * K][256];
+  const int t = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + t;
   const int64_t n = cnt[0];
   if (i >= n || cnt[3] != 0) return;
   float acc[11];
 #pragma unroll
   for (int r = 0; r < 11; ++r) acc[r] = accumulate ? grad[r * gstride + i] : 0.0f;
   bool sh_written = accumulate != 0;
+  if (accumulate)
+    for (int r = 0; r < 3 * K; ++r) sh[r][t] = grad[(int64_t)(11 + r) * gstride + i];
   GeoT<float> g;
   load_gauss(P, stride, i, g);  // camera-independent: once for all views
   for (int v = 0; v < V; ++v) {
@@ -916,16 +1012,15 @@ __global__ void __launch_bounds__(256)
 #pragma unroll 1
     for (int k = 0; k < K; ++k)
       for (int ch = 0; ch < 3; ++ch) {
-        const int64_t idx = (int64_t)(11 + 3 * k + ch) * gstride + i;
         const float val = Yb[k] * graw[ch];
-        grad[idx] = sh_written ? grad[idx] + val : 0.0f + val;
+        float &a = sh[3 * k + ch][t];
+        a = sh_written ? a + val : 0.0f + val;
       }
     sh_written = true;
   }
 #pragma unroll
   for (int r = 0; r < 11; ++r) grad[r * gstride + i] = acc[r];
-  if (!sh_written)
-    for (int r = 11; r < R; ++r) grad[r * gstride + i] = 0.0f;
+  for (int r = 11; r < R; ++r) grad[r * gstride + i] = sh_written ? sh[r - 11][t] : 0.0f;
 }
 
 // ---- work measurement (outside the hot path) ----
@@ -1036,8 +1131,8 @@ void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const flo
   hipLaunchKernelGGL((k_raster_bwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
                      s->pairs.p, s->ranges.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
                      s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], s->T_final.p,
-                     s->last.p, dl_drgb, dl_ddepth, s->pair_off.p, s->rank_of.p, s->partial.p,
-                     s->frontier.p);
+                     s->last.p, dl_drgb, dl_ddepth, s->pair_off.p, s->rank_of.p, s->tmask.p,
+                     s->partial.p, s->frontier.p);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1112,6 +1207,7 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   s->val_tmp.need(nr + 1);
   s->rank_of.need(nr + 1);
   s->pair_off.need(nr + 1);
+  s->tmask.need(nr + 1);
   s->scan.need(nr + 2);
   s->ranges.need(nt + 1);
   s->frontier.need(nt + 1);
@@ -1134,7 +1230,7 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
     StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
     hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st, params,
                        cnt, stride, s->sh_degree, dc, V, gmask, mask_shift, s->TW, s->TH,
-                       s->rec.p, RS, s->zkey.p, sortkey, order, s->count.p);
+                       s->rec.p, RS, s->zkey.p, sortkey, order, s->count.p, s->tmask.p);
     DCGS_LAUNCH_CHECK();
   }
   if (nr > 0) {
@@ -1165,8 +1261,8 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
   if (nr > 0) {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->order.p,
-                       s->count.p, s->scan.p, s->rec.p + 2 * s->rs, cnt, s->TW, s->TH,
-                       s->tiles_x, tpv, s->pairs.p, s->pair_off.p);
+                       s->count.p, s->scan.p, s->rec.p + 2 * s->rs, s->tmask.p, cnt, s->TW,
+                       s->TH, s->tiles_x, tpv, s->pairs.p, s->pair_off.p);
     DCGS_LAUNCH_CHECK();
   }
   int tile_bits = 0;
@@ -1262,7 +1358,8 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
     int64_t *cnt = counters(s, st);
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, cnt,
                        s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p + 2 * s->rs, s->count.p,
-                       s->pair_off.p, s->rank_of.p, s->frontier.p, s->partial.p, s2d);
+                       s->pair_off.p, s->rank_of.p, s->tmask.p, s->frontier.p, s->partial.p,
+                       s2d);
     DCGS_LAUNCH_CHECK();
 #define DCGS_PBWD(D)                                                                        \
   hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st,   \

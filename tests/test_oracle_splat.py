@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+from scipy.spatial.transform import Rotation
 import pytest
 import torch
 
@@ -176,21 +177,102 @@ def test_box_holds_every_visible_sample():
         assert len(ii) > 0
 
 
+def _kept_tiles(rec):
+    """{(g, tx, ty)} of the tiles the binning keeps, from rec.tile_keep."""
+    out, k = set(), 0
+    for g in range(rec.culled.size):
+        if rec.culled[g]:
+            continue
+        tx0, tx1, ty0, ty1 = rec.tile_rect[g]
+        for ty in range(ty0, ty1 + 1):
+            for tx in range(tx0, tx1 + 1):
+                if rec.tile_keep[k]:
+                    out.add((g, tx, ty))
+                k += 1
+    assert k == rec.tile_keep.size
+    return out
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
 def test_keys_and_ranges_linear_scan(tile):
     sc = scenegen.tiny_scene(n=400, seed=6, width=70, height=50, focal=60.0)
     rec = osp.preprocess(sc["params"], 0, sc["camera"], tile=tile)
     kr = osp.tile_keys(rec)
+    kept = _kept_tiles(rec)
     nt = kr["tiles_x"] * kr["tiles_y"]
     for t in range(nt):
         tx, ty = t % kr["tiles_x"], t // kr["tiles_x"]
-        lst = [g for g in range(400) if not rec.culled[g]
-               and rec.tile_rect[g, 0] <= tx <= rec.tile_rect[g, 1]
-               and rec.tile_rect[g, 2] <= ty <= rec.tile_rect[g, 3]]
+        lst = [g for g in range(400) if (g, tx, ty) in kept]
         lst.sort(key=lambda g: (rec.zbits[g], g))
         lo, hi = kr["ranges"][t]
         assert list(kr["values"][lo:hi]) == lst
         assert all(int(k) >> 32 == t for k in kr["keys"][lo:hi])
+    assert kr["counts"].sum() == len(kept) == kr["keys"].size
+
+
+def test_rect_min_against_a_bounded_minimiser():
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        L = rng.normal(size=(2, 2))
+        Q = L @ L.T + 0.05 * np.eye(2)
+        x0, y0 = rng.uniform(-6, 6, 2)
+        x1, y1 = x0 + rng.uniform(0, 8), y0 + rng.uniform(0, 8)
+        got = osp.rect_min(Q[0, 0], Q[0, 1], Q[1, 1], x0, x1, y0, y1)
+        res = minimize(lambda d: d @ Q @ d, [0.5 * (x0 + x1), 0.5 * (y0 + y1)],
+                       jac=lambda d: 2 * Q @ d, bounds=[(x0, x1), (y0, y1)], method="L-BFGS-B",
+                       options=dict(ftol=1e-15, gtol=1e-12))
+        assert abs(got - res.fun) <= 1e-7 * max(1.0, res.fun)
+        # and no sampled point of the rectangle lies below it
+        xs, ys = np.meshgrid(np.linspace(x0, x1, 41), np.linspace(y0, y1, 41))
+        f = Q[0, 0] * xs * xs + 2 * Q[0, 1] * xs * ys + Q[1, 1] * ys * ys
+        assert f.min() >= got - 1e-12 * max(1.0, f.min())
+
+
+def test_binning_keeps_every_tile_holding_a_sample_and_drops_some():
+    sc = scenegen.tiny_scene(n=3000, seed=4)
+    cam = sc["camera"]
+    rec = osp.preprocess(sc["params"], 0, cam, (16, 16))
+    kept = _kept_tiles(rec)
+    W, H = cam["width"], cam["height"]
+    px, py = pixel_grid(W, H)
+    u, v = rec.u.detach().numpy(), rec.v.detach().numpy()
+    Q, o = rec.conic.detach().numpy(), rec.opacity.detach().numpy()
+    dropped = 0
+    for g in np.nonzero(~rec.culled)[0][:400]:
+        dx, dy = px - u[g], py - v[g]
+        a = o[g] * np.exp(-0.5 * (Q[g, 0] * dx * dx + Q[g, 2] * dy * dy) - Q[g, 1] * dx * dy)
+        jj, ii = np.nonzero(a >= 1 / 255)
+        for tx, ty in set(zip(ii // 16, jj // 16)):
+            assert (g, tx, ty) in kept
+        tx0, tx1, ty0, ty1 = rec.tile_rect[g]
+        dropped += (tx1 - tx0 + 1) * (ty1 - ty0 + 1) - sum(1 for t in kept if t[0] == g)
+    assert dropped > 0
+
+
+def test_binning_drops_the_far_corner_of_a_thin_diagonal_gaussian():
+    # a long thin Gaussian along the image diagonal: its box spans 3 x 3
+    # tiles, the two off-diagonal corner tiles miss the ellipse
+    cam = scenegen.look_camera([0.0, 0.0, 0.0], 0.0, 0.0, 100.0, 100.0, 96, 96, 0.2, 50.0)
+    P = np.zeros((14, 1))
+    P[0:3, 0] = (-np.asarray(cam["R"]).T @ np.asarray(cam["t"])) + np.asarray(cam["R"]).T @ [0, 0, 3.0]
+    P[3:6, 0] = np.log([0.6, 0.01, 0.01])
+    ang = np.pi / 4
+    Rc = np.asarray(cam["R"], np.float64)
+    Rz = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
+    xyzw = Rotation.from_matrix(Rc.T @ Rz).as_quat()   # long axis along the screen diagonal
+    P[6:10, 0] = [xyzw[3], xyzw[0], xyzw[1], xyzw[2]]
+    P[10, 0] = 4.0
+    rec = osp.preprocess(P, 0, cam, (16, 16))
+    assert not rec.culled[0]
+    tx0, tx1, ty0, ty1 = rec.tile_rect[0]
+    assert tx1 - tx0 >= 2 and ty1 - ty0 >= 2
+    kept = _kept_tiles(rec)
+    # the long axis runs along one screen diagonal: that pair of opposite
+    # corner tiles is kept, the other pair dropped
+    corners = [(tx0, ty0), (tx1, ty1), (tx1, ty0), (tx0, ty1)]
+    k = [(0, tx, ty) in kept for tx, ty in corners]
+    assert k[0] == k[1] and k[2] == k[3] and k[0] != k[2], k
 
 
 def _fd_scene(seed, deg=3, n=40):
