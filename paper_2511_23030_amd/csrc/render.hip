@@ -39,6 +39,10 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTMin = 1e-4f;
 constexpr double kDilation = 0.3;
+// Records store the conic Q (Q00, Q01, Q11) as log2(e) (-Q00/2, -Q01,
+// -Q11/2); kQ converts a stored diagonal entry back (x -2/log2(e)).
+constexpr double kLog2e = 1.4426950408889634;
+constexpr float kQ = (float)(-2.0 / kLog2e);
 constexpr uint32_t kCulledKey = 0xFFFFFFFFu;
 
 struct CamD {
@@ -271,31 +275,30 @@ __device__ inline uint64_t tile_mask(const Geo &g, int TW, int TH, uint32_t &n_k
   }
   const double tau = 2.0 * log(255.0 * g.o);
   const double lim = (tau + 1e-3 * (1.0 + tau)) / shrink;
+  // Per row of tiles: the row's band of pixel-centre rows meets the ellipse
+  // {f <= lim} in an x-interval [xl, xr], and a tile is kept when its
+  // pixel-centre columns meet that interval.  The right end of the ellipse
+  // across y is concave, the left end convex, so over the band they are
+  // reached at the ellipse's rightmost / leftmost point clamped into it.
   const double idet = 1.0 / g.det;
-  const double q00 = g.c * idet, q01x2 = -2.0 * g.b * idet, q11 = g.a * idet;
-  // minimiser of f along x = const is y = (b / a) x, along y = const x = (b / c) y
-  const double sy = g.b / g.a, sx = g.b / g.c;
+  const double q00 = g.c * idet, q01 = -g.b * idet, q11 = g.a * idet;
+  const double dq = idet;                        // det Q = 1 / det Sigma2
+  const double ymax = sqrt(q00 * lim / dq);      // half height of the ellipse
+  const double yr = -q01 * sqrt(lim / (q11 * dq));  // y of its rightmost point
   const double uh = g.u - 0.5, vh = g.v - 0.5;
   uint32_t lo = 0, hi = 0;
   int k = 0;
-  for (int ty = ty0; ty <= ty1; ++ty) {
+  for (int ty = ty0; ty <= ty1; ++ty, k += w) {
     const double y0 = max(ty * TH, g.j0) - vh, y1 = min(ty * TH + TH - 1, g.j1) - vh;
-    for (int tx = tx0; tx <= tx1; ++tx, ++k) {
+    if (y1 < -ymax || y0 > ymax) continue;
+    const double ya = fmax(y0, -ymax), yb = fmin(y1, ymax);
+    const double y_r = fmin(fmax(yr, ya), yb), y_l = fmin(fmax(-yr, ya), yb);
+    const double xr = (-q01 * y_r + sqrt(fmax(q00 * lim - dq * y_r * y_r, 0.0))) / q00;
+    const double xl = (-q01 * y_l - sqrt(fmax(q00 * lim - dq * y_l * y_l, 0.0))) / q00;
+    for (int tx = tx0, kk = k; tx <= tx1; ++tx, ++kk) {
       const double x0 = max(tx * TW, g.i0) - uh, x1 = min(tx * TW + TW - 1, g.i1) - uh;
-      bool keep = x0 <= 0.0 && x1 >= 0.0 && y0 <= 0.0 && y1 >= 0.0;
-      if (!keep) {
-        double best = INFINITY;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const double xe = e ? x1 : x0, ye = e ? y1 : y0;
-          const double yc = fmin(fmax(sy * xe, y0), y1), xc = fmin(fmax(sx * ye, x0), x1);
-          best = fmin(best, xe * (q00 * xe + q01x2 * yc) + q11 * yc * yc);
-          best = fmin(best, xc * (q00 * xc + q01x2 * ye) + q11 * ye * ye);
-        }
-        keep = best <= lim;
-      }
-      if (keep) {
-        if (k < 32) lo |= 1u << k; else hi |= 1u << (k - 32);
+      if (x1 >= xl && x0 <= xr) {
+        if (kk < 32) lo |= 1u << kk; else hi |= 1u << (kk - 32);
       }
     }
   }
@@ -357,10 +360,10 @@ __global__ void __launch_bounds__(256)
     count[r] = n_keep;
     sortkey[r] = __float_as_uint(zf);
     const double id = 1.0 / g.det;
-    rec[r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(g.c * id),
-                         (float)(-g.b * id));
-    rec[RS + r] = make_float4((float)(g.a * id), (float)g.o, (float)fmax(raw[0], 0.0),
-                              (float)fmax(raw[1], 0.0));
+    rec[r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(-0.5 * kLog2e * g.c * id),
+                         (float)(kLog2e * g.b * id));
+    rec[RS + r] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
+                              (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
     rec[2 * RS + r] = make_float4((float)fmax(raw[2], 0.0), zf,
                                   __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
                                   __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
@@ -444,7 +447,7 @@ __device__ inline int tile_of_block(int n_tiles) {
 
 struct Sample {
   bool ok;
-  float power, G, alpha, dx, dy;
+  float power, G, alpha, dx, dy;  // power: the exponent in base 2
 };
 
 
@@ -464,11 +467,11 @@ __device__ __forceinline__ Sample sample(int px, int py, float pxh, float pyh, c
   s.ok = px >= i0 && px <= i1 && py >= j0 && py <= j1;
   s.dx = (pxh - (float)i0) - A.x;
   s.dy = (pyh - (float)j0) - A.y;
-  const float qxx = A.z * (s.dx * s.dx);
-  const float qyy = B.x * (s.dy * s.dy);
-  const float qxy = A.w * (s.dx * s.dy);
-  s.power = -0.5f * (qxx + qyy) - qxy;
-  s.G = __builtin_amdgcn_exp2f(1.44269502f * s.power);  // e^power
+  // the record holds the conic scaled by -log2(e) / 2 (off-diagonal by
+  // -log2(e)), so the exponent comes out in base 2: power = log2(e) (-d^T Q d / 2)
+  const float t = __builtin_fmaf(B.x, s.dy * s.dy, A.w * (s.dx * s.dy));
+  s.power = __builtin_fmaf(A.z, s.dx * s.dx, t);
+  s.G = __builtin_amdgcn_exp2f(s.power);  // e^(-d^T Q d / 2)
   const float oG = B.y * s.G;
   s.alpha = fminf(kAlphaMax, oG);
   s.ok = s.ok && !(s.power > 0.0f) && !(s.alpha < kAlphaMin);
@@ -756,6 +759,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         continue;
       }
       const float4 A = sA[k], B = sB[k];
+      const float a2 = 2.0f * A.z, b2 = 2.0f * B.x;
       float v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = 0.0f;
@@ -788,8 +792,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         const float gG = free_alpha ? s.G : 0.0f;
         const float dp = free_alpha ? a * da : 0.0f;
         v[5] += gG * da;
-        v[0] += dp * (A.z * s.dx + A.w * s.dy);
-        v[1] += dp * (A.w * s.dx + B.x * s.dy);
+        // scaled conic: (Q00 dx + Q01 dy) = kQ/2 (2 A.z dx + A.w dy); the
+        // factor kQ/2 is applied once per record after the reduction
+        v[0] += dp * (a2 * s.dx + A.w * s.dy);
+        v[1] += dp * (A.w * s.dx + b2 * s.dy);
         v[2] += -0.5f * s.dx * s.dx * dp;
         v[3] += -s.dx * s.dy * dp;
         v[4] += -0.5f * s.dy * s.dy * dp;
@@ -813,6 +819,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         for (int w = 0; w < NW; ++w) a += red[w][k][c];
         s[c] = a;
       }
+      s[0] *= 0.5f * kQ;
+      s[1] *= 0.5f * kQ;
       const uint32_t g = sG[k];
       const float4 C = sC[k];
       const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
@@ -1085,9 +1093,9 @@ __global__ void k_export_rec(const float4 *__restrict__ rec, int64_t RS,
     const bool cul = count[i] == 0;
     out[0 * n + i] = cul ? 0.0f : A.x + (float)i0;
     out[1 * n + i] = cul ? 0.0f : A.y + (float)j0;
-    out[2 * n + i] = A.z;
-    out[3 * n + i] = A.w;
-    out[4 * n + i] = B.x;
+    out[2 * n + i] = A.z * kQ;         // the conic Q00, Q01, Q11
+    out[3 * n + i] = A.w * (0.5f * kQ);
+    out[4 * n + i] = B.x * kQ;
     out[5 * n + i] = B.y;
     out[6 * n + i] = B.z;
     out[7 * n + i] = B.w;
