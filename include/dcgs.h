@@ -339,9 +339,10 @@ int dcgs_sample_pixels(dcgs_ctx *ctx, const float *image, const float *render, c
 
 /* ---- autotuner ----------------------------------------------------------- */
 
-/* SYNC.  Time one forward and one backward pass of every supported raster
- * shape (tile_w, tile_h, pixels_per_lane) on the given window (same
- * arguments as dcgs_render_fwd), keep the fastest, and remember it in ctx
+/* SYNC.  Time a forward and backward pass of every supported raster shape
+ * (tile_w, tile_h, pixels_per_lane) on the given window (same arguments as
+ * dcgs_render_fwd; one warm pass, then the fastest of three timed passes
+ * per shape), keep the fastest shape, and remember it in ctx
  * for windows of the same width, height, view count and size class
  * (ceil(log2(n))).  A cached answer returns at once unless force != 0.
  * Images do not depend on the shape.  Scratch images and gradients are

@@ -706,7 +706,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int2 rg = ranges[gt];
   const int64_t HW = (int64_t)W * H;
-  float T[PPT], g0[PPT], g1[PPT], g2[PPT], gd[PPT], S0[PPT], S1[PPT], S2[PPT], SD[PPT];
+  // GS = dL/dC . (colour and depth composited behind the current Gaussian,
+  // background included): dalpha needs only this dot product
+  float T[PPT], g0[PPT], g1[PPT], g2[PPT], gd[PPT], GS[PPT];
   int last[PPT];
   int my_last = -1;
 #pragma unroll
@@ -724,10 +726,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       g2[j] = dl_drgb[2 * HW + pix];
       if (dl_ddepth) gd[j] = dl_ddepth[pix];
     }
-    S0[j] = T[j] * bg0;
-    S1[j] = T[j] * bg1;
-    S2[j] = T[j] * bg2;
-    SD[j] = 0.0f;
+    GS[j] = T[j] * (g0[j] * bg0 + g1[j] * bg1 + g2[j] * bg2);
     my_last = max(my_last, last[j]);
   }
   if (threadIdx.x == 0) max_last = -1;
@@ -780,12 +779,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         v[7] += g1[j] * w;
         v[8] += g2[j] * w;
         v[9] += gd[j] * w;
-        const float da = g0[j] * (B.z * Tk - S0[j] * iom) + g1[j] * (B.w * Tk - S1[j] * iom) +
-                         g2[j] * (C.x * Tk - S2[j] * iom) + gd[j] * (C.y * Tk - SD[j] * iom);
-        S0[j] += B.z * w;
-        S1[j] += B.w * w;
-        S2[j] += C.x * w;
-        SD[j] += C.y * w;
+        // dL/dalpha = dL/dC . (c Tk - S / (1 - alpha)), S what lies behind
+        const float gc = g0[j] * B.z + g1[j] * B.w + g2[j] * C.x + gd[j] * C.y;
+        const float da = gc * Tk - GS[j] * iom;
+        GS[j] += gc * w;
         T[j] = Tk;
         // alpha not clamped: the opacity and the exponent receive gradient
         const bool free_alpha = act && B.y * s.G <= kAlphaMax;
@@ -796,9 +793,11 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         // factor kQ/2 is applied once per record after the reduction
         v[0] += dp * (a2 * s.dx + A.w * s.dy);
         v[1] += dp * (A.w * s.dx + b2 * s.dy);
-        v[2] += -0.5f * s.dx * s.dx * dp;
-        v[3] += -s.dx * s.dy * dp;
-        v[4] += -0.5f * s.dy * s.dy * dp;
+        // d power / d(Q00, Q01, Q11) = -(dx^2 / 2, dx dy, dy^2 / 2): the
+        // constant factors are applied after the reduction
+        v[2] += s.dx * s.dx * dp;
+        v[3] += s.dx * s.dy * dp;
+        v[4] += s.dy * s.dy * dp;
       }
       if (__ballot(contrib) != 0) {
         const float r = wave_reduce16(v);
@@ -821,6 +820,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       }
       s[0] *= 0.5f * kQ;
       s[1] *= 0.5f * kQ;
+      s[2] *= -0.5f;
+      s[3] = -s[3];
+      s[4] *= -0.5f;
       const uint32_t g = sG[k];
       const float4 C = sC[k];
       const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
