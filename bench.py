@@ -80,10 +80,11 @@ def make_workload(name: str) -> dict:
 COPY_BYTES = 1 << 30   # the plain copy that calibrates the HBM byte counters
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, instance: str | None = None):
     """HBM bytes per launch of `kernel` from the committed counter summary
-    of this workload, or None when there is none or the kernel's source
-    changed since the counters were taken."""
+    of this workload, or None when there is none, when it was taken for
+    another instance of the kernel (template arguments: the raster shape),
+    or when the kernel's source changed since the counters were taken."""
     import json
 
     from paper_2511_23030_amd import profsummary
@@ -92,6 +93,8 @@ def measured_traffic(workload: str, kernel: str):
         return None
     with open(path) as f:
         t = json.load(f)
+    if instance is not None and t.get("kernel_regex") != instance:
+        return None
     src = os.path.join(ROOT, t["source"])
     if not os.path.exists(src) or profsummary.source_digest(src) != t["source_sha256"]:
         return None
@@ -158,7 +161,7 @@ def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray, budget_s: float = 2
                        f"({t_full_pre:.1f} s) is not counted twice")}
 
 
-def prefetch_study(ctx, w, make_loop, run, cursor, n_walk, log) -> dict:
+def prefetch_study(ctx, w, make_loop, targets, n_walk, log) -> dict:
     """Learned prefetch on the driving corridor: train the network on the
     exact labels of 20 corridor layouts (seeds 100-119), measure chunk misses
     against the exact test on 5 held-out layouts (120-124), then time the
@@ -166,8 +169,9 @@ def prefetch_study(ctx, w, make_loop, run, cursor, n_walk, log) -> dict:
     pool over the same stretch of the walk: no staging ahead (misses load on
     demand), staging the network's predictions, staging the next keyframe's
     exact selection."""
-    import scenegen
+    import torch
 
+    import scenegen
     from paper_2511_23030_amd import prefetch as PF
     t0 = time.perf_counter()
     kw = dict(width=w["W"], height=w["H"], focal=w["f"], z_far=w["z_far"])
@@ -190,15 +194,35 @@ def prefetch_study(ctx, w, make_loop, run, cursor, n_walk, log) -> dict:
     log(f"prefetch network: trained in {t_train:.1f} s, held-out miss rate "
         f"{rep['held_out_miss_rate']:.4f} vs {rep['held_out_miss_rate_without']:.4f} without")
     # a walk long enough for chunks to enter at the far plane and leave
-    # behind (2 m per keyframe: ~800 m), timed after the first view's set
-    # is loaded; pool counters are those of the timed stretch
+    # behind (2 m per keyframe), timed after the first view's set is loaded;
+    # pool counters are those of the timed stretch.  The targets are the
+    # rendered ones reused in turn: their content changes neither the work
+    # nor the chunk traffic.
+    cams_all, every = w["cams_all"], w["every"]
+    n_walk = min(n_walk, len(cams_all) - 10)
+    K = len(targets)
+
+    def walk_plain(loop, mode, k0, n):
+        sel = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(k0, k0 + n):
+            loop.step(cams_all[k], targets[k % K], None if sel is None else sel[0])
+            sel = None
+            if mode == "exact":
+                sel = loop.prefetch_window([cams_all[k + 1]])
+            elif mode == "mlp":
+                loop.prefetch_predicted(net, [w["all_cams"][max(k * every - j, 0)]
+                                              for j in range(8)])
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
     keys = ("loads", "misses", "hits", "prefetched", "evictions", "bytes_h2d")
     for mode in ("none", "mlp", "exact"):
         pool, loop = make_loop()
-        cursor["plain_" + mode] = (0, None)
-        run(loop, "plain_" + mode, 8, prefetch=mode, net=net)          # warm
+        walk_plain(loop, mode, 0, 8)          # warm: the first view's chunks
         s0 = pool.stats()
-        t = run(loop, "plain_" + mode, n_walk, prefetch=mode, net=net)
+        t = walk_plain(loop, mode, 8, n_walk)
         s1 = pool.stats()
         st = {k: s1[k] - s0[k] for k in keys}
         rep[f"plain_{mode}_iters_per_s"] = round(n_walk / t, 3)
@@ -261,6 +285,7 @@ def main():
     if walk:
         # the camera only moves forward: warmup windows, then the timed ones
         n_win = args.warmup + -(-max(args.steps, V) // V)
+        w["cams_all"] = w["cams"]
         w["cams"] = w["cams"][:n_win * V]
     K = len(w["cams"])
 
@@ -353,14 +378,17 @@ def main():
     pool_s, loop_s = make_loop()
     pool_g, loop_g = make_loop()
     log(f"pools ingested ({time.perf_counter() - t_setup:.1f} s since start)")
-    tuned, tune_ms = None, []
+    tuned, tune_ms, tuned1 = None, [], None
     if args.tile == "auto":
         tuned, tune_ms = loop_b.autotune([w["cams"][i] for i in windows[0]])
-        for lp in (loop_s, loop_g):
-            lp.tile, lp.ppt = tuned[:2], tuned[2]
+        loop_g.tile, loop_g.ppt = tuned[:2], tuned[2]
+        # the one-view paths (sequential comparator, plain) get the shape
+        # tuned for one view
+        tuned1, _ = loop_s.autotune([w["cams"][windows[0][0]]])
         tw, th = tuned[0], tuned[1]
         args.ppt = tuned[2]
-        log(f"autotuned raster shape {tuned}; fwd+bwd ms per shape {[round(t, 2) for t in tune_ms]}")
+        log(f"autotuned raster shape {tuned} ({tuned1} for one view); fwd+bwd ms per shape "
+            f"{[round(t, 2) for t in tune_ms]}")
     n_views = max(args.steps, V)
     run(loop_b, "batched", args.warmup * V)
     run(loop_s, "sequential", args.warmup * V)
@@ -401,14 +429,18 @@ def main():
     del loop_s, loop_g
     # the paper's schedule: one Adam step per keyframe
     n_plain = max(args.steps // 2, 8)
+    if tuned1 is not None:
+        loop_b.tile, loop_b.ppt = tuned1[:2], tuned1[2]
     t_p = run(loop_b, "plain", n_plain)
     plain_rate = n_plain / t_p
     l1, psnr = loop_b.loss_psnr(3 * w["W"] * w["H"])
     prefetch_report = None
     if walk and not args.no_prefetch_mlp:
-        prefetch_report = prefetch_study(ctx, w, make_loop, run, cursor, max(n_plain, 400), log)
+        prefetch_report = prefetch_study(ctx, w, make_loop, targets, max(n_plain, 400), log)
 
     # stage profile of the batched path, outside the timed region
+    if tuned is not None:
+        loop_b.tile, loop_b.ppt = tuned[:2], tuned[2]
     ctx.profile(True)
     Ns, Ps, Es, Ews = [], [], [], []
     for k in range(args.profile_steps):
@@ -442,7 +474,9 @@ def main():
         achieved = RASTER_FLOPS[dominant] * E / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant}
+                "traffic": measured_traffic(args.workload, dominant,
+                                            f"k_{dominant}<{tw}, {th}, {args.ppt}>"),
+                "kernel": f"k_{dominant}<{tw}, {th}, {args.ppt}>"}
     else:
         achieved = stage_bytes(dominant, N, Pp, Npx, R) / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -484,7 +518,9 @@ def main():
                    "psnr_graph_db": round(psnr_g, 4),
                    "psnr_delta_db": round(max(abs(psnr_b - psnr_s), abs(psnr_g - psnr_s)), 6),
                    "prefetch": prefetch_report,
-                   "raster_shape": [tw, th, args.ppt], "autotune_ms": [round(t, 3) for t in tune_ms]},
+                   "raster_shape": [tw, th, args.ppt],
+                   "raster_shape_one_view": None if tuned1 is None else list(tuned1),
+                   "autotune_ms": [round(t, 3) for t in tune_ms]},
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
