@@ -161,30 +161,48 @@ __global__ void __launch_bounds__(kSortThreads)
     hist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
+// Scatter of one pass.  The workgroup first ranks its 4096 keys stably by
+// digit into LDS (so its keys sit there grouped by digit, in input order
+// within a digit), then writes each digit's run to its global offset:
+// consecutive threads write consecutive addresses of one run.
 template <typename K, bool kVals>
 __global__ void __launch_bounds__(kSortThreads)
     k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                  K *__restrict__ kout, uint32_t *__restrict__ vout,
                  const int64_t *__restrict__ n_dev, int64_t n, int shift, int width,
-                 const uint32_t *__restrict__ offs, int64_t nb) {
-  __shared__ uint32_t run[256];
-  n = count_of(n_dev, n);
+                 const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs,
+                 int64_t nb) {
+  __shared__ K sk[kSortTile];
+  __shared__ uint32_t sv[kVals ? kSortTile : 1];
+  __shared__ uint32_t gofs[256];  // global offset of the block's run of digit d
+  __shared__ uint32_t lofs[256];  // start of digit d's run in sk, then its fill
   __shared__ uint32_t wcnt[kSortWaves][256];
+  n = count_of(n_dev, n);
   const uint32_t bins = 1u << width, mask = bins - 1;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  for (uint32_t d = threadIdx.x; d < bins; d += kSortThreads)
-    run[d] = offs[(int64_t)d * nb + blockIdx.x];
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  if (base >= n) return;  // uniform across the block
+  const int cnt = (int)min<int64_t>(kSortTile, n - base);
+  {  // local run starts: exclusive scan of this block's digit counts
+    const uint32_t d = threadIdx.x;
+    const uint32_t c = d < bins ? hist[(int64_t)d * nb + blockIdx.x] : 0u;
+    uint32_t excl;
+    block_exclusive_scan(c, &excl);
+    if (d < bins) {
+      lofs[d] = excl;
+      gofs[d] = offs[(int64_t)d * nb + blockIdx.x];
+    }
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   for (int r = 0; r < kSortRounds; ++r) {
-    if (base + (int64_t)r * kSortThreads >= n) break;  // uniform across block
+    if (r * kSortThreads >= cnt) break;  // uniform across block
     for (int t = threadIdx.x; t < kSortWaves * 256; t += kSortThreads)
       (&wcnt[0][0])[t] = 0;
     __syncthreads();
-    const int64_t i = base + r * kSortThreads + threadIdx.x;
-    const bool valid = i < n;
-    K key = valid ? kin[i] : K(0);
-    uint32_t val = (kVals && valid) ? vin[i] : 0u;
+    const int li = r * kSortThreads + threadIdx.x;
+    const bool valid = li < cnt;
+    const K key = valid ? kin[base + li] : K(0);
+    const uint32_t val = (kVals && valid) ? vin[base + li] : 0u;
     const uint32_t d = digit_of(key, shift, mask);
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < width; ++b) {
@@ -196,18 +214,27 @@ __global__ void __launch_bounds__(kSortThreads)
     if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = run[d] + rank;
+      uint32_t pos = lofs[d] + rank;
       for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      kout[pos] = key;
-      if (kVals) vout[pos] = val;
+      sk[pos] = key;
+      if (kVals) sv[pos] = val;
     }
     __syncthreads();
     for (uint32_t dd = threadIdx.x; dd < bins; dd += kSortThreads) {
       uint32_t s = 0;
       for (int k = 0; k < kSortWaves; ++k) s += wcnt[k][dd];
-      run[dd] += s;
+      lofs[dd] += s;  // now the end of what is filled
     }
     __syncthreads();
+  }
+  // lofs[d] is now the end of digit d's run; its start is end - count
+  for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
+    const K key = sk[p];
+    const uint32_t d = digit_of(key, shift, mask);
+    const uint32_t start = lofs[d] - hist[(int64_t)d * nb + blockIdx.x];
+    const uint32_t pos = gofs[d] + (uint32_t)p - start;
+    kout[pos] = key;
+    if (kVals) vout[pos] = sv[p];
   }
 }
 
@@ -249,7 +276,7 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
   scan_u32(h, nullptr, scanned, tab, part, st);
   hipLaunchKernelGGL((k_rs_scatter<K, kVals>), dim3((unsigned)nb),
                      dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, n, shift,
-                     width, scanned, nb);
+                     width, h, scanned, nb);
   DCGS_LAUNCH_CHECK();
 }
 
