@@ -470,13 +470,15 @@ def main():
     stages = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
     dominant = max(stages, key=stages.get)
     avg_ms = stages[dominant]
+    # pixels per lane of the forward (bits 0-3) and backward (bits 4-7) rasters
+    ppt_f = (args.ppt & 15) or {8: 1, 16: 2}.get(tw, 4)
+    ppt_b = (args.ppt >> 4) or ppt_f
+    inst = f"k_{dominant}<{tw}, {th}, {ppt_b if dominant == 'raster_bwd' else ppt_f}>"
     if dominant in RASTER_FLOPS:
         achieved = RASTER_FLOPS[dominant] * E / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(args.workload, dominant,
-                                            f"k_{dominant}<{tw}, {th}, {args.ppt}>"),
-                "kernel": f"k_{dominant}<{tw}, {th}, {args.ppt}>"}
+                "traffic": measured_traffic(args.workload, dominant, inst), "kernel": inst}
     else:
         achieved = stage_bytes(dominant, N, Pp, Npx, R) / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -504,7 +506,7 @@ def main():
         "config": {"workload": f"{args.workload}: {scene} {w['n']} Gaussians SH{w['deg']}, "
                                f"{w['W']}x{w['H']}, {w['chunk']:g} m chunks, device budget "
                                f"{min(w['budget'], w['n'])} Gaussians, tile {tw}x{th}, "
-                               f"{args.ppt or 'default'} px/lane; value = graph-replayed batched "
+                               f"{ppt_f} px/lane forward, {ppt_b} backward; value = graph-replayed batched "
                                f"windows of {V} keyframes (one iteration = one keyframe view)",
                    "pool_batched": pool_stats,
                    "active_gaussians_per_window_mean": round(N), "pairs_per_window_mean": round(Pp),
@@ -518,7 +520,7 @@ def main():
                    "psnr_graph_db": round(psnr_g, 4),
                    "psnr_delta_db": round(max(abs(psnr_b - psnr_s), abs(psnr_g - psnr_s)), 6),
                    "prefetch": prefetch_report,
-                   "raster_shape": [tw, th, args.ppt],
+                   "raster_shape": [tw, th, ppt_f, ppt_b],
                    "raster_shape_one_view": None if tuned1 is None else list(tuned1),
                    "autotune_ms": [round(t, 3) for t in tune_ms]},
         "roofline": roof,

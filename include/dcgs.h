@@ -254,9 +254,12 @@ void dcgs_state_destroy(dcgs_state *st);
  *   bg: host float[3]
  *   raster shape: tile_w x tile_h pixels per workgroup, pixels_per_lane
  *   vertically adjacent pixels per lane; supported (16,16,{1,2,4}),
- *   (8,8,1), (32,16,{2,4,8}); pixels_per_lane 0 picks 2, 1 and 4.  The
- *   image does not depend on the shape (each pixel composites only the
- *   Gaussians whose pixel box holds it), nor on the other views.
+ *   (8,8,1), (32,16,{2,4,8}); pixels_per_lane 0 picks 2, 1 and 4.  Bits
+ *   0-3 of pixels_per_lane are the forward's, bits 4-7 the backward's
+ *   (0: the forward's), so the two rasters of one tile size may map pixels
+ *   to lanes differently.  The image does not depend on the shape (each
+ *   pixel composites only the Gaussians whose pixel box holds it), nor on
+ *   the other views.
  *   rgb: device [n_views][3][H][W]; depth: device [n_views][H][W];
  *   T: device [n_views][H][W] or null.
  * Outputs are overwritten.  The state keeps what render_bwd needs. */
@@ -339,10 +342,12 @@ int dcgs_sample_pixels(dcgs_ctx *ctx, const float *image, const float *render, c
 
 /* ---- autotuner ----------------------------------------------------------- */
 
-/* SYNC.  Time a forward and backward pass of every supported raster shape
- * (tile_w, tile_h, pixels_per_lane) on the given window (same arguments as
- * dcgs_render_fwd; one warm pass, then the fastest of three timed passes
- * per shape), keep the fastest shape, and remember it in ctx
+/* SYNC.  Time the forward and the backward pass of every supported raster
+ * shape (tile_w, tile_h, pixels_per_lane) on the given window (same
+ * arguments as dcgs_render_fwd; one warm pass, then the fastest of three
+ * timed passes per shape), keep the tile size whose fastest forward plus
+ * fastest backward is smallest, with those two pixels-per-lane values
+ * packed as in dcgs_render_fwd (out_shape[2]), and remember it in ctx
  * for windows of the same width, height, view count and size class
  * (ceil(log2(n))).  A cached answer returns at once unless force != 0.
  * Images do not depend on the shape.  Scratch images and gradients are
@@ -382,7 +387,8 @@ typedef struct dcgs_window dcgs_window;
 typedef struct dcgs_window_config {
   int sh_degree;                 /* must equal the pool's */
   int width, height, n_views;    /* every camera of a launch has this size; 1..16 views */
-  int tile_w, tile_h, pixels_per_lane;  /* a supported raster shape (see dcgs_autotune) */
+  int tile_w, tile_h, pixels_per_lane;  /* a supported raster shape, backward's pixels per
+                                           lane in bits 4-7 (see dcgs_render_fwd) */
   int64_t capacity;              /* Gaussians: row stride of params and grad;
                                     capacity * n_views < 2^31 */
   int64_t pair_capacity;         /* (tile, Gaussian) pairs, < 2^31 */

@@ -264,12 +264,14 @@ int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t 
     DCGS_CHECK(sh_degree >= 0 && sh_degree <= 3, DCGS_E_INVALID, "render_fwd: sh_degree 0..3");
     DCGS_CHECK(mask_shift >= 0 && mask_shift + n_views <= 16, DCGS_E_INVALID,
                "render_fwd: mask_shift + n_views must be <= 16");
-    int ppt = pixels_per_lane;
+    DCGS_CHECK(pixels_per_lane >= 0 && pixels_per_lane < 256, DCGS_E_INVALID,
+               "render_fwd: pixels_per_lane out of range");
+    int ppt = pixels_per_lane & 15, ppt_bwd = pixels_per_lane >> 4;
     if (ppt == 0) ppt = tile_w == 8 ? 1 : tile_w == 16 ? 2 : 4;
-    const bool shape_ok = (tile_w == 16 && tile_h == 16 && (ppt == 1 || ppt == 2 || ppt == 4)) ||
-                          (tile_w == 8 && tile_h == 8 && ppt == 1) ||
-                          (tile_w == 32 && tile_h == 16 && (ppt == 2 || ppt == 4 || ppt == 8));
-    DCGS_CHECK(shape_ok, DCGS_E_INVALID,
+    if (ppt_bwd == 0) ppt_bwd = ppt;
+    DCGS_CHECK(dcgs::raster_shape_supported(tile_w, tile_h, ppt) &&
+                   dcgs::raster_shape_supported(tile_w, tile_h, ppt_bwd),
+               DCGS_E_INVALID,
                "render_fwd: raster shape must be 16x16x{1,2,4}, 8x8x1 or 32x16x{2,4,8}");
     for (int v = 0; v < n_views; ++v) {
       check_cam(&cams[v]);
@@ -280,6 +282,7 @@ int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t 
     DCGS_CHECK(bg && rgb && depth, DCGS_E_INVALID, "render_fwd: null output");
     st->V = n_views;
     st->ppt = ppt;
+    st->ppt_bwd = ppt_bwd;
     st->W = cams[0].width;
     st->H = cams[0].height;
     st->TW = tile_w;
@@ -385,40 +388,68 @@ int dcgs_autotune(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t n,
     float *grad = ctx->tune_grad.need((size_t)R * (n > 0 ? n : 1));
     DCGS_HIP(hipMemsetAsync(dl, 0, 3 * n_views * HW * sizeof(float), S(stream)));
     const float bg[3] = {0, 0, 0};
-    hipEvent_t e0, e1;
+    hipEvent_t e0, e1, e2;
     DCGS_HIP(hipEventCreate(&e0));
     DCGS_HIP(hipEventCreate(&e1));
-    double best = 1e300;
-    int bi = 1;
+    DCGS_HIP(hipEventCreate(&e2));
+    struct Free {
+      hipEvent_t a, b, c;
+      ~Free() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        (void)hipEventDestroy(c);
+      }
+    } fr{e0, e1, e2};
+    // forward and backward timed apart: the forward and the backward of one
+    // tile size may take different pixels per lane (the pairs, the images
+    // and the per-pixel state do not depend on it)
+    float tf[kN], tb[kN];
     for (int k = 0; k < kN; ++k) {
       const int *sh = kShapes[k];
-      auto pass = [&] {
-        int rc = dcgs_render_fwd(ctx, st, params, n, stride, sh_degree, gmask, 0, cams, n_views,
-                                 bg, sh[0], sh[1], sh[2], rgb, depth, nullptr, stream);
+      auto fwd = [&] {
+        const int rc = dcgs_render_fwd(ctx, st, params, n, stride, sh_degree, gmask, 0, cams,
+                                       n_views, bg, sh[0], sh[1], sh[2], rgb, depth, nullptr,
+                                       stream);
         DCGS_CHECK(rc == DCGS_OK, rc, "autotune: forward failed: " + ctx->err);
-        rc = dcgs_render_bwd(ctx, st, params, n, stride, dl, nullptr, grad, n, 0, nullptr, stream);
+      };
+      auto bwd = [&] {
+        const int rc = dcgs_render_bwd(ctx, st, params, n, stride, dl, nullptr, grad, n, 0,
+                                       nullptr, stream);
         DCGS_CHECK(rc == DCGS_OK, rc, "autotune: backward failed: " + ctx->err);
       };
-      pass();  // warm: buffers sized, code loaded
-      float ms = 1e30f;
+      fwd();  // warm: buffers sized, code loaded
+      bwd();
+      tf[k] = tb[k] = 1e30f;
       for (int rep = 0; rep < 3; ++rep) {  // the fastest of three passes
         DCGS_HIP(hipEventRecord(e0, S(stream)));
-        pass();
+        fwd();
         DCGS_HIP(hipEventRecord(e1, S(stream)));
-        DCGS_HIP(hipEventSynchronize(e1));
-        float t = 0.0f;
-        DCGS_HIP(hipEventElapsedTime(&t, e0, e1));
-        ms = std::min(ms, t);
+        bwd();
+        DCGS_HIP(hipEventRecord(e2, S(stream)));
+        DCGS_HIP(hipEventSynchronize(e2));
+        float a = 0.0f, b = 0.0f;
+        DCGS_HIP(hipEventElapsedTime(&a, e0, e1));
+        DCGS_HIP(hipEventElapsedTime(&b, e1, e2));
+        tf[k] = std::min(tf[k], a);
+        tb[k] = std::min(tb[k], b);
       }
-      if (times_ms) times_ms[k] = ms;
-      if (ms < best) {
-        best = ms;
-        bi = k;
+      if (times_ms) times_ms[k] = tf[k] + tb[k];
+    }
+    // per tile size the fastest forward and the fastest backward
+    double best = 1e300;
+    int bf = 1, bb = 1;
+    for (int k = 0; k < kN; ++k) {
+      for (int j = 0; j < kN; ++j) {
+        if (kShapes[j][0] != kShapes[k][0] || kShapes[j][1] != kShapes[k][1]) continue;
+        if (tf[k] + tb[j] < best) {
+          best = tf[k] + tb[j];
+          bf = k;
+          bb = j;
+        }
       }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    std::array<int, 3> a{kShapes[bi][0], kShapes[bi][1], kShapes[bi][2]};
+    const int packed = kShapes[bf][2] | (kShapes[bb][2] == kShapes[bf][2] ? 0 : kShapes[bb][2] << 4);
+    std::array<int, 3> a{kShapes[bf][0], kShapes[bf][1], packed};
     ctx->tune_cache[key] = a;
     for (int k = 0; k < 3; ++k) out_shape[k] = a[k];
   });

@@ -116,6 +116,7 @@ struct dcgs_state {
   // shape of the last forward
   int64_t n = 0, n_pairs = 0;
   int W = 0, H = 0, TW = 16, TH = 16, ppt = 2, tiles_x = 0, tiles_y = 0, sh_degree = 0;
+  int ppt_bwd = 2;  // pixels per lane of the backward raster
   float bg[3] = {0, 0, 0};
   int V = 1;                              // views rendered together
   dcgs_camera cams[dcgs::kMaxViews]{};

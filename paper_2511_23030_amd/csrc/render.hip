@@ -137,7 +137,7 @@ template <typename T>
 struct GeoT {
   T mu[3], s[3], qn[4], qnorm, o, Rg[9], M[9], Sig[6];
   T X, Y, Z, A0[3], A1[3], a, b, c, det;
-  T u, v;
+  T u, v, r2;  // r2 = 2 ln(255 o): alpha >= 1/255 where d^T Q d <= r2
   bool culled;
   int i0, i1, j0, j1;
 };
@@ -210,7 +210,8 @@ __device__ inline void project(const CamD &cam, GeoT<T> &g) {
   }
   g.u = fx * g.X / g.Z + (T)cam.cx;
   g.v = fy * g.Y / g.Z + (T)cam.cy;
-  const T r2 = T(2) * log(T(255) * g.o);
+  g.r2 = T(2) * log(T(255) * g.o);
+  const T r2 = g.r2;
   const T ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
   const T big = T(1e9);
   const T e0 = fmin(fmax(g.u - ex - T(0.5), -big), big), e1 = fmin(fmax(g.u + ex - T(0.5), -big), big);
@@ -273,7 +274,7 @@ __device__ inline uint64_t tile_mask(const Geo &g, int TW, int TH, uint32_t &n_k
     n_keep = (uint32_t)n_rect;
     return n_rect >= 64 ? ~uint64_t(0) : ((uint64_t(1) << n_rect) - 1);
   }
-  const double tau = 2.0 * log(255.0 * g.o);
+  const double tau = g.r2;
   const double lim = (tau + 1e-3 * (1.0 + tau)) / shrink;
   // Per row of tiles: the row's band of pixel-centre rows meets the ellipse
   // {f <= lim} in an x-interval [xl, xr], and a tile is kept when its
@@ -1163,7 +1164,7 @@ void launch_fwd(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *
 
 void launch_bwd(dcgs_state *s, hipStream_t st, const float *dl_drgb, const float *dl_ddepth) {
 #define X(a, b, c)                                                   \
-  if (s->TW == a && s->TH == b && s->ppt == c) {                     \
+  if (s->TW == a && s->TH == b && s->ppt_bwd == c) {                     \
     launch_bwd_t<a, b, c>(s, st, dl_drgb, dl_ddepth);                \
     return;                                                          \
   }

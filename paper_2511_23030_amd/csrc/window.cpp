@@ -121,14 +121,17 @@ void window_create(dcgs_ctx *ctx, dcgs_pool *pool, const dcgs_window_config *cfg
   s->H = c.height;
   s->TW = c.tile_w;
   s->TH = c.tile_h;
-  s->ppt = c.pixels_per_lane;
+  s->ppt = c.pixels_per_lane & 15;
+  s->ppt_bwd = (c.pixels_per_lane >> 4) ? (c.pixels_per_lane >> 4) : s->ppt;
   s->tiles_x = (c.width + c.tile_w - 1) / c.tile_w;
   s->tiles_y = (c.height + c.tile_h - 1) / c.tile_h;
   s->sh_degree = c.sh_degree;
   s->V = c.n_views;
   for (int k = 0; k < 3; ++k) s->bg[k] = c.bg[k];
-  DCGS_CHECK(raster_shape_supported(c.tile_w, c.tile_h, c.pixels_per_lane), DCGS_E_INVALID,
-             "window_create: unsupported raster shape");
+  DCGS_CHECK(c.pixels_per_lane >= 0 && c.pixels_per_lane < 256 &&
+                 raster_shape_supported(c.tile_w, c.tile_h, s->ppt) &&
+                 raster_shape_supported(c.tile_w, c.tile_h, s->ppt_bwd),
+             DCGS_E_INVALID, "window_create: unsupported raster shape");
   render_plan(s, c.capacity, c.pair_capacity);
   s->grad2d.need(10 * (size_t)s->rs + 1);
   w->loss_part.need(2 * 1024);
