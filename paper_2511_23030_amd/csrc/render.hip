@@ -143,6 +143,12 @@ struct GeoT {
 };
 using Geo = GeoT<double>;
 
+// a / b: IEEE division in float64 (the forward geometry, whose keys and
+// boxes must match a float64 reference bit for bit); in float32 (the
+// backward chain) the hardware reciprocal (about 1 ulp) times a.
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
 // Camera-independent part: activations, rotation, covariance.
 template <typename T>
 __device__ inline void load_gauss(const float *__restrict__ P, int64_t stride, int64_t i,
@@ -151,9 +157,9 @@ __device__ inline void load_gauss(const float *__restrict__ P, int64_t stride, i
   for (int k = 0; k < 3; ++k) g.s[k] = exp((T)P[(3 + k) * stride + i]);
   T q[4];
   for (int k = 0; k < 4; ++k) q[k] = (T)P[(6 + k) * stride + i];
-  g.o = T(1) / (T(1) + exp(-(T)P[10 * stride + i]));
+  g.o = qdiv(T(1), T(1) + exp(-(T)P[10 * stride + i]));
   g.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-  for (int k = 0; k < 4; ++k) g.qn[k] = q[k] / g.qnorm;
+  for (int k = 0; k < 4; ++k) g.qn[k] = qdiv(q[k], g.qnorm);
   const T w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
   T *R = g.Rg;
   R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
@@ -172,21 +178,27 @@ __device__ inline void load_gauss(const float *__restrict__ P, int64_t stride, i
 }
 
 // Camera-dependent part: camera coordinates, culling, EWA, conic, pixel box.
+// With cull false (the backward of a record the forward drew) the culling
+// tests and the box are skipped: the float32 chain must not take its own
+// decisions near the float64 forward's thresholds.
 template <typename T>
-__device__ inline void project(const CamD &cam, GeoT<T> &g) {
+__device__ inline void project(const CamD &cam, GeoT<T> &g, bool cull = true) {
   T Rc[9];
   for (int k = 0; k < 9; ++k) Rc[k] = (T)cam.R[k];
   g.X = Rc[0] * g.mu[0] + Rc[1] * g.mu[1] + Rc[2] * g.mu[2] + (T)cam.t[0];
   g.Y = Rc[3] * g.mu[0] + Rc[4] * g.mu[1] + Rc[5] * g.mu[2] + (T)cam.t[1];
   g.Z = Rc[6] * g.mu[0] + Rc[7] * g.mu[1] + Rc[8] * g.mu[2] + (T)cam.t[2];
-  g.culled = !(g.Z > (T)cam.zn);
-  if (!g.culled) {
-    const T rx = fabs(g.X / g.Z), ry = fabs(g.Y / g.Z);
-    g.culled = (rx > (T)cam.limx) || (ry > (T)cam.limy) || (g.o < T(1.0 / 255.0));
+  g.culled = false;
+  if (cull) {
+    g.culled = !(g.Z > (T)cam.zn);
+    if (!g.culled) {
+      const T rx = fabs(qdiv(g.X, g.Z)), ry = fabs(qdiv(g.Y, g.Z));
+      g.culled = (rx > (T)cam.limx) || (ry > (T)cam.limy) || (g.o < T(1.0 / 255.0));
+    }
+    if (g.culled) return;
   }
-  if (g.culled) return;
   const T fx = (T)cam.fx, fy = (T)cam.fy;
-  const T iz = T(1) / g.Z;
+  const T iz = qdiv(T(1), g.Z);
   const T j00 = fx * iz, j02 = -fx * g.X * iz * iz;
   const T j11 = fy * iz, j12 = -fy * g.Y * iz * iz;
   for (int c = 0; c < 3; ++c) {
@@ -204,12 +216,13 @@ __device__ inline void project(const CamD &cam, GeoT<T> &g) {
   g.b = quad(g.A0, g.A1);
   g.c = quad(g.A1, g.A1) + T(kDilation);
   g.det = g.a * g.c - g.b * g.b;
-  if (!(g.det > T(0))) {
+  if (cull && !(g.det > T(0))) {
     g.culled = true;
     return;
   }
-  g.u = fx * g.X / g.Z + (T)cam.cx;
-  g.v = fy * g.Y / g.Z + (T)cam.cy;
+  g.u = qdiv(fx * g.X, g.Z) + (T)cam.cx;
+  g.v = qdiv(fy * g.Y, g.Z) + (T)cam.cy;
+  if (!cull) return;
   g.r2 = T(2) * log(T(255) * g.o);
   const T r2 = g.r2;
   const T ex = sqrt(r2 * g.a), ey = sqrt(r2 * g.c);
@@ -237,9 +250,9 @@ __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, in
                                  T *Y, T raw[3]) {
   T d0 = g.mu[0] - (T)cam.C[0], d1 = g.mu[1] - (T)cam.C[1], d2 = g.mu[2] - (T)cam.C[2];
   dnorm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-  dir[0] = d0 / dnorm;
-  dir[1] = d1 / dnorm;
-  dir[2] = d2 / dnorm;
+  dir[0] = qdiv(d0, dnorm);
+  dir[1] = qdiv(d1, dnorm);
+  dir[2] = qdiv(d2, dnorm);
   sh_eval(deg, dir[0], dir[1], dir[2], Y);
   const int K = (deg + 1) * (deg + 1);
   for (int ch = 0; ch < 3; ++ch) {
@@ -852,10 +865,11 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
   const T go = s[5], gz_depth = s[9];
   // conic Q = Sigma2^-1 -> Sigma2 entries a, b, c
   const T det = g.det, a = g.a, b = g.b, c = g.c;
-  const T gdet = -(gQ00 * c - gQ01 * b + gQ11 * a) / (det * det);
-  const T ga = gQ11 / det + gdet * c;
-  const T gb = -gQ01 / det - T(2) * b * gdet;
-  const T gc = gQ00 / det + gdet * a;
+  const T idet = qdiv(T(1), det);
+  const T gdet = -(gQ00 * c - gQ01 * b + gQ11 * a) * (idet * idet);
+  const T ga = gQ11 * idet + gdet * c;
+  const T gb = -gQ01 * idet - T(2) * b * gdet;
+  const T gc = gQ00 * idet + gdet * a;
   // Sigma2 = A Sigma A^T: G_Sigma = A^T G2 A, G_A = 2 G2 A Sigma
   const T G2[2][2] = {{ga, T(0.5) * gb}, {T(0.5) * gb, gc}};
   const T A[2][3] = {{g.A0[0], g.A0[1], g.A0[2]}, {g.A1[0], g.A1[1], g.A1[2]}};
@@ -879,7 +893,7 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
   for (int r = 0; r < 2; ++r)
     for (int k = 0; k < 3; ++k)
       GJ[r][k] = GA[r][0] * Rc[3 * k] + GA[r][1] * Rc[3 * k + 1] + GA[r][2] * Rc[3 * k + 2];
-  const T iz = T(1) / g.Z, iz2 = iz * iz, iz3 = iz2 * iz;
+  const T iz = qdiv(T(1), g.Z), iz2 = iz * iz, iz3 = iz2 * iz;
   const T fx = (T)cam.fx, fy = (T)cam.fy, X = g.X, Y = g.Y;
   T gX = GJ[0][2] * (-fx * iz2) + gu * fx * iz;
   T gY = GJ[1][2] * (-fy * iz2) + gv * fy * iz;
@@ -913,7 +927,8 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
                   y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
   const T dq = g.qn[0] * gqn[0] + g.qn[1] * gqn[1] + g.qn[2] * gqn[2] + g.qn[3] * gqn[3];
   T gq[4];
-  for (int k = 0; k < 4; ++k) gq[k] = (gqn[k] - g.qn[k] * dq) / g.qnorm;
+  const T iqn = qdiv(T(1), g.qnorm);
+  for (int k = 0; k < 4; ++k) gq[k] = (gqn[k] - g.qn[k] * dq) * iqn;
   const T glogit = go * g.o * (T(1) - g.o);
   // colour
   T dir[3], dn, raw[3];
@@ -932,7 +947,8 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
     T gd[3];
     sh_grad_dot(deg, dir[0], dir[1], dir[2], f, gd);
     const T dd = dir[0] * gd[0] + dir[1] * gd[1] + dir[2] * gd[2];
-    for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) / dn;
+    const T idn = qdiv(T(1), dn);
+    for (int k = 0; k < 3; ++k) gmu[k] += (gd[k] - dir[k] * dd) * idn;
   }
   out[0] = gmu[0]; out[1] = gmu[1]; out[2] = gmu[2];
   out[3] = gls[0]; out[4] = gls[1]; out[5] = gls[2];
@@ -1008,11 +1024,13 @@ __global__ void __launch_bounds__(256)
     for (int r = 0; r < 3 * K; ++r) sh[r][t] = grad[(int64_t)(11 + r) * gstride + i];
   GeoT<float> g;
   load_gauss(P, stride, i, g);  // camera-independent: once for all views
+  unsigned drawn = 0;  // views that drew the Gaussian (independent loads, issued together)
+  for (int v = 0; v < V; ++v) drawn |= (count[v * n + i] != 0 ? 1u : 0u) << v;
   for (int v = 0; v < V; ++v) {
     const int64_t rr = v * n + i;
-    if (count[rr] == 0) continue;
+    if (!((drawn >> v) & 1u)) continue;
     const CamD &cam = cams[v];
-    project(cam, g);
+    project(cam, g, false);  // drawn by the forward: no culling decisions
     float s[10];
 #pragma unroll
     for (int c = 0; c < 10; ++c) s[c] = s2d[c * RS + rr];

@@ -8,6 +8,7 @@ import pytest
 import scenegen
 from gpu_helpers import (IMG_TOL, SHAPES, assert_grad_close, flagged_pixels, gpu_render)
 from oracle import splat as osp
+from paper_2511_23030_amd import dcgs as D
 
 pytestmark = pytest.mark.gpu
 
@@ -130,6 +131,24 @@ def test_backward_is_deterministic(ctx):
     a = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl)
     b = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl)
     assert (a["grad"] == b["grad"]).all() and (a["rgb"] == b["rgb"]).all()
+
+
+def test_backward_pixels_per_lane_apart_from_forward(ctx):
+    # bits 4-7 of pixels_per_lane give the backward raster its own lane
+    # layout: gradients then depend only on it, images on neither
+    sc = _scene((256, 192))
+    cam = sc["camera"]
+    dl = scenegen.upstream_grad(256, 192, seed=4, scale=1e-3)
+    ref = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl, ppt=4)
+    for packed in (1 | 4 << 4, 2 | 4 << 4):
+        g = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl, ppt=packed)
+        assert (g["rgb"] == ref["rgb"]).all()
+        assert (g["grad"] == ref["grad"]).all() and (g["grad2d"] == ref["grad2d"]).all()
+    other = gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl, ppt=4 | 2 << 4)
+    assert (other["rgb"] == ref["rgb"]).all()
+    assert np.abs(other["grad"] - ref["grad"]).max() <= 1e-5 * np.abs(ref["grad"]).max()
+    with pytest.raises(D.DcgsError):
+        gpu_render(ctx, sc["params"], 0, cam, [0, 0, 0], (16, 16), dl, ppt=2 | 3 << 4)
 
 
 def test_empty_and_all_culled(ctx):
