@@ -254,8 +254,8 @@ def main():
                     help="skip the learned-prefetch study of the driving workloads")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "sharding of this path is described in DESIGN.md and not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): sharding the map "
+              "by space over several GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
