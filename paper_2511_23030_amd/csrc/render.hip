@@ -333,7 +333,9 @@ __device__ __forceinline__ bool tile_kept(uint64_t m, int n_rect, int k) {
 // bit is set in its chunk's view mask.  Record r = v * n + g; the three
 // record planes are RS apart.  cnt[0] = n (device counter; the grid may be
 // sized for a capacity).
-__global__ void __launch_bounds__(256)
+// Four waves per SIMD: the float64 projection is latency-bound, and the
+// compiler fits it in 128 registers without spilling.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_preprocess(const float *__restrict__ P, const int64_t *__restrict__ cnt, int64_t stride,
                  int deg, const CamD *__restrict__ cams, int V,
                  const uint16_t *__restrict__ gmask, int mask_shift, int TW, int TH,
