@@ -134,7 +134,7 @@ struct dcgs_state {
   dcgs::DevBuf<uint64_t> tmask;     // [n] kept tiles of the record's tile rectangle
   // per pair
   dcgs::DevBuf<uint64_t> pairs, pairs_tmp;
-  dcgs::DevBuf<float4> partial;  // [3 * P] per-pair gradient partials
+  dcgs::DevBuf<float2> partial;  // [5 * P] per-pair gradient partials (ten floats)
   // launch plan: grids sized for n_grid Gaussians, record planes rs apart,
   // pcap pair slots (planned windows; eager forwards size them exactly).
   // The device counters [n, nr, pairs, overflow, sticky overflow] follow

@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                  const float *__restrict__ Tstate, const int *__restrict__ last_in,
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
                  const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
-                 const uint64_t *__restrict__ tmask, float4 *__restrict__ partial,
+                 const uint64_t *__restrict__ tmask, float2 *__restrict__ partial,
                  int *__restrict__ frontier) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
@@ -847,9 +847,12 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const int wc = tx1 - tx0 + 1;
       const uint32_t slot = pair_off[g] + kept_rank(tmask[g], wc * (ty1 - ty0 + 1),
                                                     (ty - ty0) * wc + (tx - tx0));
-      partial[3 * (int64_t)slot] = make_float4(s[0], s[1], s[2], s[3]);
-      partial[3 * (int64_t)slot + 1] = make_float4(s[4], s[5], s[6], s[7]);
-      partial[3 * (int64_t)slot + 2] = make_float4(s[8], s[9], 0.0f, 0.0f);
+      float2 *pp = partial + 5 * (int64_t)slot;  // ten floats, 40 B per slot
+      pp[0] = make_float2(s[0], s[1]);
+      pp[1] = make_float2(s[2], s[3]);
+      pp[2] = make_float2(s[4], s[5]);
+      pp[3] = make_float2(s[6], s[7]);
+      pp[4] = make_float2(s[8], s[9]);
     }
     __syncthreads();
   }
@@ -966,7 +969,7 @@ __global__ void __launch_bounds__(256)
                    int tiles_per_view, const float4 *__restrict__ recC,
                    const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
                    const uint32_t *__restrict__ rank_of, const uint64_t *__restrict__ tmask,
-                   const int *__restrict__ frontier, const float4 *__restrict__ partial,
+                   const int *__restrict__ frontier, const float2 *__restrict__ partial,
                    float *__restrict__ s2d) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
@@ -987,12 +990,11 @@ __global__ void __launch_bounds__(256)
       const int t = tile_base + (ty0 + k / wc) * tiles_x + tx0 + k % wc;
       const uint32_t sl = slot++;
       if (frontier[t] < rank) continue;
-      const float4 p0 = partial[3 * (int64_t)sl];
-      const float4 p1 = partial[3 * (int64_t)sl + 1];
-      const float4 p2 = partial[3 * (int64_t)sl + 2];
-      s[0] += p0.x; s[1] += p0.y; s[2] += p0.z; s[3] += p0.w;
-      s[4] += p1.x; s[5] += p1.y; s[6] += p1.z; s[7] += p1.w;
-      s[8] += p2.x; s[9] += p2.y;
+      const float2 *pp = partial + 5 * (int64_t)sl;
+      const float2 q0 = pp[0], q1 = pp[1], q2 = pp[2], q3 = pp[3], q4 = pp[4];
+      s[0] += q0.x; s[1] += q0.y; s[2] += q1.x; s[3] += q1.y;
+      s[4] += q2.x; s[5] += q2.y; s[6] += q3.x; s[7] += q3.y;
+      s[8] += q4.x; s[9] += q4.y;
     }
   }
 #pragma unroll
@@ -1315,7 +1317,7 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
 void size_pairs(dcgs_state *s, int64_t pcap) {
   s->pairs.need((size_t)pcap + 1);
   s->pairs_tmp.need((size_t)pcap + 1);
-  s->partial.need(3 * (size_t)pcap + 3);
+  s->partial.need(5 * (size_t)pcap + 5);
 }
 
 }  // namespace
