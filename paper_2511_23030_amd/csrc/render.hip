@@ -330,8 +330,8 @@ __device__ __forceinline__ bool tile_kept(uint64_t m, int n_rect, int k) {
 }
 
 // One thread per Gaussian; it projects the Gaussian into every view whose
-// bit is set in its chunk's view mask.  Record r = v * n + g; the three
-// record planes are RS apart.  cnt[0] = n (device counter; the grid may be
+// bit is set in its chunk's view mask.  Record r = v * n + g is three
+// float4 at rec[3 r .. 3 r + 2] (48 contiguous bytes, one gather per record).  cnt[0] = n (device counter; the grid may be
 // sized for a capacity).
 // Four waves per SIMD: the float64 projection is latency-bound, and the
 // compiler fits it in 128 registers without spilling.
@@ -364,9 +364,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
       count[r] = 0;
       tmask[r] = 0;
       sortkey[r] = kCulledKey;
-      rec[r] = make_float4(0, 0, 0, 0);
-      rec[RS + r] = make_float4(0, 0, 0, 0);
-      rec[2 * RS + r] = make_float4(0, 0, 0, 0);
+      rec[3 * r] = make_float4(0, 0, 0, 0);
+      rec[3 * r + 1] = make_float4(0, 0, 0, 0);
+      rec[3 * r + 2] = make_float4(0, 0, 0, 0);
       continue;
     }
     double dir[3], dn, Y[16], raw[3];
@@ -376,11 +376,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     count[r] = n_keep;
     sortkey[r] = __float_as_uint(zf);
     const double id = 1.0 / g.det;
-    rec[r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(-0.5 * kLog2e * g.c * id),
+    rec[3 * r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(-0.5 * kLog2e * g.c * id),
                          (float)(kLog2e * g.b * id));
-    rec[RS + r] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
+    rec[3 * r + 1] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
                               (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
-    rec[2 * RS + r] = make_float4((float)fmax(raw[2], 0.0), zf,
+    rec[3 * r + 2] = make_float4((float)fmax(raw[2], 0.0), zf,
                                   __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
                                   __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
   }
@@ -409,7 +409,7 @@ __global__ void k_pairs_total(const uint32_t *__restrict__ scan, int64_t *__rest
 // Pairs of record r = v n + g: (global tile v T + t) << 32 | r, emitted in
 // depth order, tiles of a record row-major.
 __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
-                       const uint32_t *__restrict__ scan, const float4 *__restrict__ recC,
+                       const uint32_t *__restrict__ scan, const float4 *__restrict__ rec,
                        const uint64_t *__restrict__ tmask, const int64_t *__restrict__ cnt,
                        int TW, int TH, int tiles_x, int tiles_per_view,
                        uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
@@ -422,7 +422,7 @@ __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__res
   const uint32_t base = scan[j];
   pair_off[g] = base;
   if (c == 0) return;
-  const float4 C = recC[g];
+  const float4 C = rec[3 * (int64_t)g + 2];
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
   const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
@@ -561,9 +561,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     const int p = base + threadIdx.x;
     if (p < rg.y) {
       const uint32_t g = (uint32_t)pairs[p];
-      sA[threadIdx.x] = rec[g];
-      sB[threadIdx.x] = rec[RS + g];
-      sC[threadIdx.x] = rec[2 * RS + g];
+      const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
+      sA[threadIdx.x] = q[0];
+      sB[threadIdx.x] = q[1];
+      sC[threadIdx.x] = q[2];
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
@@ -760,9 +761,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     if (threadIdx.x < nb) {  // slot k holds position end - 1 - k
       const uint32_t g = (uint32_t)pairs[end - 1 - threadIdx.x];
       sG[threadIdx.x] = g;
-      sA[threadIdx.x] = rec[g];
-      sB[threadIdx.x] = rec[RS + g];
-      sC[threadIdx.x] = rec[2 * RS + g];
+      const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
+      sA[threadIdx.x] = q[0];
+      sB[threadIdx.x] = q[1];
+      sC[threadIdx.x] = q[2];
     }
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
@@ -966,7 +968,7 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
 // written as ten planes s2d[c][r].  Integer box from the packed record.
 __global__ void __launch_bounds__(256)
     k_sum_partials(const int64_t *__restrict__ cnt, int64_t RS, int TW, int TH, int tiles_x,
-                   int tiles_per_view, const float4 *__restrict__ recC,
+                   int tiles_per_view, const float4 *__restrict__ rec,
                    const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
                    const uint32_t *__restrict__ rank_of, const uint64_t *__restrict__ tmask,
                    const int *__restrict__ frontier, const float2 *__restrict__ partial,
@@ -976,7 +978,7 @@ __global__ void __launch_bounds__(256)
   if (r >= nr || cnt[3] != 0) return;
   float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (count[r] > 0) {
-    const float4 C = recC[r];
+    const float4 C = rec[3 * r + 2];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
     const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
     const int ty0 = (int)(by & 0xFFFF) / TH, ty1 = (int)(by >> 16) / TH;
@@ -1062,7 +1064,7 @@ __global__ void __launch_bounds__(256)
 // box.  out[2 * tile] / out[2 * tile + 1].
 __global__ void __launch_bounds__(256)
     k_work(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
-           const float4 *__restrict__ recC, int W, int H, int TW, int TH, int tiles_x,
+           const float4 *__restrict__ rec, int W, int H, int TW, int TH, int tiles_x,
            int tiles_per_view, const int *__restrict__ last, long long *__restrict__ out) {
   __shared__ unsigned long long s_walk, s_in;
   const int gt = blockIdx.x;
@@ -1079,7 +1081,7 @@ __global__ void __launch_bounds__(256)
     if (l < rg.x) continue;
     walk += (unsigned long long)(l - rg.x + 1);
     for (int p = rg.x; p <= l; ++p) {
-      const float4 C = recC[(uint32_t)pairs[p]];
+      const float4 C = rec[3 * (int64_t)(uint32_t)pairs[p] + 2];
       const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
       inbox += (px >= (int)(bx & 0xFFFF) && px <= (int)(bx >> 16) && py >= (int)(by & 0xFFFF) &&
                 py <= (int)(by >> 16));
@@ -1111,7 +1113,7 @@ __global__ void k_export_rec(const float4 *__restrict__ rec, int64_t RS,
                              float *__restrict__ out, int32_t *__restrict__ box) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float4 A = rec[i], B = rec[RS + i], C = rec[2 * RS + i];
+  const float4 A = rec[3 * i], B = rec[3 * i + 1], C = rec[3 * i + 2];
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int i0 = bx & 0xFFFF, j0 = by & 0xFFFF;
   if (out) {
@@ -1294,7 +1296,7 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
   if (nr > 0) {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
     hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->order.p,
-                       s->count.p, s->scan.p, s->rec.p + 2 * s->rs, s->tmask.p, cnt, s->TW,
+                       s->count.p, s->scan.p, s->rec.p, s->tmask.p, cnt, s->TW,
                        s->TH, s->tiles_x, tpv, s->pairs.p, s->pair_off.p);
     DCGS_LAUNCH_CHECK();
   }
@@ -1390,7 +1392,7 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
     float *s2d = grad2d ? grad2d : s->grad2d.need(10 * (size_t)s->rs + 1);
     int64_t *cnt = counters(s, st);
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, cnt,
-                       s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p + 2 * s->rs, s->count.p,
+                       s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p, s->count.p,
                        s->pair_off.p, s->rank_of.p, s->tmask.p, s->frontier.p, s->partial.p,
                        s2d);
     DCGS_LAUNCH_CHECK();
@@ -1419,7 +1421,7 @@ void state_work(const dcgs_state *s, int64_t *walk, int64_t *inbox, hipStream_t 
     ~Free() { (void)hipFree(p); }
   } fr{d};
   hipLaunchKernelGGL(k_work, dim3(nt), dim3(256), 0, st, s->pairs.p, s->ranges.p,
-                     s->rec.p + 2 * s->rs, s->W, s->H, s->TW, s->TH, s->tiles_x, tpv, s->last.p,
+                     s->rec.p, s->W, s->H, s->TW, s->TH, s->tiles_x, tpv, s->last.p,
                      d);
   DCGS_LAUNCH_CHECK();
   std::vector<long long> h(2 * (size_t)nt);
