@@ -130,3 +130,33 @@ def test_two_closures_in_a_row_and_identity(ctx, corridor):
 
 def _as_input(ref):
     return ref["params"], ref["m"], ref["v"], ref["step"], ref["ids"]
+
+
+def test_junction_only_many_keyframes_and_out_of_range(ctx, corridor):
+    params, cams = corridor
+    pool = _mapped_pool(ctx, params, cams, range(0, 120, 8))
+    s0 = _store(pool)
+    # no correction, only a junction reset
+    st = pool.loop_closure([], np.zeros((0, 3, 4)), [cams[30]])
+    assert st["affected_chunks"] == 0 and st["reset"] > 0
+    ref = olc.loop_closure(*s0, S, [], [cams[30]])
+    _check(_store(pool), ref)
+    # more keyframes than one visibility pass takes (16): the owner of a
+    # chunk is still the first keyframe that sees it
+    frames = list(range(40, 240, 10))
+    assert len(frames) > 16
+    kf = _corrections(cams, frames, 0.05, (0.02, 0.01, 0.0))
+    pool.loop_closure([k[0] for k in kf], np.stack([np.c_[k[1], k[2]] for k in kf]), [])
+    ref2 = olc.loop_closure(*_as_input(ref), S, kf, [])
+    assert (ref2["owner"] >= 16).any()
+    _check(_store(pool), ref2)
+    # a correction that throws means out of the Eq. (6) range fails and
+    # leaves the store as it was
+    before = _store(pool)
+    far = [(cams[60], np.eye(3), np.array([1e8, 0.0, 0.0]))]
+    with pytest.raises(D.DcgsError):
+        pool.loop_closure([far[0][0]], np.c_[far[0][1], far[0][2]][None], [])
+    after = _store(pool)
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    pool.close()
