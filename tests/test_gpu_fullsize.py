@@ -93,3 +93,55 @@ def test_headline_keyframe(ctx):
     G = grad[:, :n].cpu().numpy()
     assert_grad_close(G[:, inside], g_ref.params[:, inside], "full-size gradients")
     pool.close()
+
+
+def test_headline_window_in_the_bench_launch_configuration(ctx):
+    """The bench's timed unit at full size: a 16-keyframe window rendered
+    and differentiated in one launch sequence at the raster shape the
+    autotuner picks for it (16x16 tiles, 2 pixels per lane forward, 4
+    backward).  Every view's image and the summed gradient equal the
+    per-view path bit for bit; one view's central crop against the oracle."""
+    import bench
+    w = bench.make_workload("indoor-2m")
+    V = 16
+    cams = w["cams"][:V]
+    W, H, deg, s = w["W"], w["H"], w["deg"], w["chunk"]
+    pool = D.Pool(ctx, deg, budget=w["n"] + 1)
+    pool.ingest(w["start"], s)
+    loop = mapping.MappingLoop(ctx, pool, deg, s, 3_400_000, W, H, (16, 16))
+    loop._window_buffers(V)
+    ids, masks = loop.select_window(cams)
+    pool.require(ids, now=0)
+    n = pool.compact(ids, loop.params, loop.src, masks=masks, out_gmask=loop.gmask)
+    assert 2.0e6 < n < 3.4e6
+    tile, ppt = (16, 16), 2 | 4 << 4
+    print(f"case fullsize window: V={V} n={n}", flush=True)
+    bg = (0.0, 0.0, 0.0)
+    st_b = D.RenderState(ctx)
+    rgb_b, depth_b = st_b.forward(loop.params, n, deg, cams, bg, tile, ppt=ppt, gmask=loop.gmask)
+    rng = np.random.default_rng(8)
+    dl = torch.from_numpy((rng.normal(size=(V, 3, H, W)) * 1e-7).astype(np.float32)).cuda()
+    grad_b = st_b.backward(loop.params, n, dl, None)
+    st_s = D.RenderState(ctx)
+    grad_s = torch.empty_like(grad_b)
+    for v in range(V):
+        rgb, depth = st_s.forward(loop.params, n, deg, cams[v], bg, tile, ppt=ppt,
+                                  gmask=loop.gmask, mask_shift=v)
+        assert torch.equal(rgb, rgb_b[v]) and torch.equal(depth, depth_b[v]), v
+        st_s.backward(loop.params, n, dl[v].contiguous(), None, grad_s, accumulate=v > 0)
+    torch.cuda.synchronize()
+    assert torch.equal(grad_b[:, :n], grad_s[:, :n])
+    print("case fullsize window: batched equals per-view", flush=True)
+    # view 5 of the window against the oracle on the central crop
+    v = 5
+    gm = loop.gmask[:n].cpu().numpy().astype(np.int64)
+    Pv = loop.params[:, :n].cpu().numpy()[:, ((gm >> v) & 1) == 1]
+    rec = osp.preprocess(Pv, deg, cams[v], (16, 16))
+    x0, x1, y0, y1 = W // 2 - 32, W // 2 + 32, H // 2 - 32, H // 2 + 32
+    img = osp.composite(rec, np.zeros(3), (x0, x1, y0, y1))
+    flag = flagged_pixels(img)
+    assert flag.sum() <= 0.05 * flag.size
+    ok = ~flag
+    got = rgb_b[v].cpu().numpy()[:, y0:y1, x0:x1]
+    assert np.abs(got - img.rgb.detach().numpy())[:, ok].max() <= IMG_TOL
+    pool.close()
