@@ -466,23 +466,28 @@ struct Sample {
   float power, G, alpha, dx, dy;  // power: the exponent in base 2
 };
 
+struct Box {
+  int i0, i1, j0, j1;  // inclusive pixel columns i0..i1, rows j0..j1
+};
+
 
 // The one definition of a (pixel, Gaussian) sample, shared by forward and
 // backward so that both take identical threshold decisions.
-// pxh, pyh: the pixel centre px + 0.5, py + 0.5 as floats.  The offset from
-// the box corner, (px + 0.5) - i0, is exact in float32 (both are exact and
-// so is their difference), so dx is the rounding of (px - i0 + 0.5) - A.x.
-__device__ __forceinline__ Sample sample(int px, int py, float pxh, float pyh, const float4 &A,
-                                         const float4 &B, const float4 &C) {
+// The pixel is (X0 + lx, Y0 + ly): (X0, Y0) the origin of its 8x8 cell and
+// (i0..i1, j0..j1) the record's pixel box, all wavefront-uniform; lxh, lyh
+// = lx + 0.5, ly + 0.5.  The offset from the box corner, (X0 + lx + 0.5) -
+// i0 = lxh + (X0 - i0), is exact in float32 (small half-integers), so dx is
+// the rounding of (px - i0 + 0.5) - A.x.
+__device__ __forceinline__ Sample sample(int lx, int ly, float lxh, float lyh, int X0, int Y0,
+                                         const Box &b, const float4 &A, const float4 &B) {
   // No implicit FMA contraction here: every kernel that inlines this takes
   // the same roundings (HIP's __f*_rn helpers are plain operators).
 #pragma clang fp contract(off)
   Sample s;
-  const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
-  const int i0 = bx & 0xFFFF, i1 = bx >> 16, j0 = by & 0xFFFF, j1 = by >> 16;
-  s.ok = px >= i0 && px <= i1 && py >= j0 && py <= j1;
-  s.dx = (pxh - (float)i0) - A.x;
-  s.dy = (pyh - (float)j0) - A.y;
+  // bitwise, not short-circuit: no lane-mask branch for a partial cell
+  s.ok = (lx >= b.i0 - X0) & (lx <= b.i1 - X0) & (ly >= b.j0 - Y0) & (ly <= b.j1 - Y0);
+  s.dx = (lxh + (float)(X0 - b.i0)) - A.x;
+  s.dy = (lyh + (float)(Y0 - b.j0)) - A.y;
   // the record holds the conic scaled by -log2(e) / 2 (off-diagonal by
   // -log2(e)), so the exponent comes out in base 2: power = log2(e) (-d^T Q d / 2)
   const float t = __builtin_fmaf(B.x, s.dy * s.dy, A.w * (s.dx * s.dy));
@@ -490,25 +495,61 @@ __device__ __forceinline__ Sample sample(int px, int py, float pxh, float pyh, c
   s.G = __builtin_amdgcn_exp2f(s.power);  // e^(-d^T Q d / 2)
   const float oG = B.y * s.G;
   s.alpha = fminf(kAlphaMax, oG);
-  s.ok = s.ok && !(s.power > 0.0f) && !(s.alpha < kAlphaMin);
+  s.ok = s.ok & !(s.power > 0.0f) & !(s.alpha < kAlphaMin);
   return s;
 }
 
-// Pixel rows [wy0, wy1] covered by this thread's wavefront: lane t of the
-// workgroup owns column t % TW and rows (t / TW) * PPT .. + PPT - 1, and a
-// wavefront spans whole tile rows (TW divides 64).
-template <int TW, int PPT>
-__device__ __forceinline__ void wave_rows(int tile_y0, int &wy0, int &wy1) {
-  static_assert(kWave % TW == 0, "a wavefront must span whole tile rows");
-  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  wy0 = tile_y0 + (w * kWave / TW) * PPT;
-  wy1 = tile_y0 + ((w * kWave + kWave - 1) / TW) * PPT + PPT - 1;
-}
+// Lane layout of the rasterizers.  A tile is a grid of 8x8-pixel cells,
+// numbered row-major; cell j (0 <= j < PPT) of wavefront w is cell
+// w * PPT + j, and lane l holds its pixel (l % 8, l / 8).  A cell is one
+// wavefront-wide pixel set, so whether a record's box meets it, and whether
+// any of its pixels still composites, are uniform branches that skip the
+// cell's arithmetic for the whole wavefront.
+template <int TW, int TH, int PPT>
+struct CellLayout {
+  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are whole 8x8 cells");
+  static_assert((TW * TH / PPT) % kWave == 0, "whole wavefronts per tile");
+  static constexpr int kCells = TW * TH / 64;  // at most 32
+  int w;                 // this wavefront (uniform)
+  int X0[PPT], Y0[PPT];  // its cells' origins in pixels (uniform)
+  __device__ __forceinline__ CellLayout(int tx, int ty) {
+    w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int c = w * PPT + j;
+      X0[j] = tx * TW + (c % (TW / 8)) * 8;
+      Y0[j] = ty * TH + (c / (TW / 8)) * 8;
+    }
+  }
+  // Bit c set: the record's box meets cell c of tile (tx, ty).  Computed
+  // once per record and tile by the thread that stages the record.
+  static __device__ __forceinline__ uint32_t cell_mask(const float4 &C, int tx, int ty) {
+    const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+    const int i0 = bx & 0xFFFF, i1 = bx >> 16, j0 = by & 0xFFFF, j1 = by >> 16;
+    uint32_t m = 0;
+#pragma unroll
+    for (int c = 0; c < kCells; ++c) {
+      const int x0 = tx * TW + (c % (TW / 8)) * 8, y0 = ty * TH + (c / (TW / 8)) * 8;
+      m |= (uint32_t)((i1 >= x0) & (i0 <= x0 + 7) & (j1 >= y0) & (j0 <= y0 + 7)) << c;
+    }
+    return m;
+  }
+  // this wavefront's PPT bits of a tile cell mask (uniform)
+  __device__ __forceinline__ uint32_t mine(uint32_t m) const {
+    return (m >> (w * PPT)) & ((1u << PPT) - 1u);
+  }
+};
 
-// The record's pixel box (packed rows in C.w) meets rows [wy0, wy1].
-__device__ __forceinline__ bool box_meets_rows(const float4 &C, int wy0, int wy1) {
-  const uint32_t by = __float_as_uint(C.w);
-  return (int)(by >> 16) >= wy0 && (int)(by & 0xFFFF) <= wy1;
+// A record's packed pixel box, read once per wavefront into scalar registers.
+__device__ __forceinline__ Box uniform_box(const float4 &C) {
+  const uint32_t bx = __builtin_amdgcn_readfirstlane(__float_as_uint(C.z));
+  const uint32_t by = __builtin_amdgcn_readfirstlane(__float_as_uint(C.w));
+  Box b;
+  b.i0 = bx & 0xFFFF;
+  b.i1 = bx >> 16;
+  b.j0 = by & 0xFFFF;
+  b.j1 = by >> 16;
+  return b;
 }
 
 template <int TW, int TH, int PPT>
@@ -522,6 +563,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   constexpr int NT = TW * TH / PPT;
   constexpr int BS = NT;
   __shared__ float4 sA[BS], sB[BS], sC[BS];
+  __shared__ uint32_t sM[BS];
+  // a one-cell tile needs no cell masks: every record of its list meets it
+  // or is rejected pixel by pixel
+  constexpr bool kOneCell = CellLayout<TW, TH, PPT>::kCells == 1;
   const int gt = tile_of_block(n_tiles);
   if (gt >= n_tiles) return;
   const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
@@ -534,15 +579,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     Tstate += view * HWv;
     last_out += view * HWv;
   }
-  // lane t owns PPT vertically adjacent pixels of the tile
-  const int px = tx * TW + (threadIdx.x % TW);
-  const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
-  const float pxh = (float)px + 0.5f;
-  float pyh[PPT];
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) pyh[j] = (float)(py0 + j) + 0.5f;
-  int wy0, wy1;
-  wave_rows<TW, PPT>(ty * TH, wy0, wy1);
+  const CellLayout<TW, TH, PPT> cell(tx, ty);
+  const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7;
+  const float lxh = (float)lx + 0.5f, lyh = (float)ly + 0.5f;
   const int2 rg = ranges[gt];
   float T[PPT], c0[PPT], c1[PPT], c2[PPT], D[PPT];
   int last[PPT];
@@ -553,7 +592,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     T[j] = 1.0f;
     c0[j] = c1[j] = c2[j] = D[j] = 0.0f;
     last[j] = -1;
-    done[j] = !(px < W && py0 + j < H);
+    done[j] = !(cell.X0[j] + lx < W && cell.Y0[j] + ly < H);
     n_live += !done[j];
   }
   for (int base = rg.x; base < rg.y; base += BS) {
@@ -564,33 +603,43 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
       sA[threadIdx.x] = q[0];
       sB[threadIdx.x] = q[1];
-      sC[threadIdx.x] = q[2];
+      const float4 C = q[2];
+      sC[threadIdx.x] = C;
+      if constexpr (!kOneCell) sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(C, tx, ty);
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
+    uint32_t live = 0;
+    uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
     for (int k = 0; k < nb; ++k) {
-      // a wavefront whose pixels are all saturated leaves the batch
-      if ((k & 7) == 0) {
-        bool live = false;
-#pragma unroll
-        for (int j = 0; j < PPT; ++j) live = live || !done[j];
-        if (__ballot(live) == 0) break;
+      uint32_t mk = 1u;
+      if constexpr (!kOneCell) {
+        mk = __builtin_amdgcn_readfirstlane(m_next);
+        m_next = sM[min(k + 1, BS - 1)];
       }
-      const float4 C = sC[k];
-      if (!box_meets_rows(C, wy0, wy1)) continue;  // no pixel of this wave is in the box
-      const float4 A = sA[k], B = sB[k];
+      // cells whose pixels are all saturated leave the batch; a wavefront
+      // with none left leaves it altogether
+      if ((k & 7) == 0) {
+        live = 0;
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        // predicated rather than branched: a lane that does not composite
-        // adds exact zeros, and the wavefront issues no mask bookkeeping.
-        // Contraction is off in this kernel: every raster shape composites
-        // with the same roundings.
-        const Sample s = sample(px, py0 + j, pxh, pyh[j], A, B, C);
-        const bool act = s.ok && !done[j];
+        for (int j = 0; j < PPT; ++j) live |= (uint32_t)(__ballot(!done[j]) != 0) << j;
+        if (live == 0) break;
+      }
+      const uint32_t hit = cell.mine(mk) & live;
+      if (hit == 0) continue;  // no live cell of this wavefront meets the box
+      const float4 A = sA[k], B = sB[k], C = sC[k];
+      const Box bx = uniform_box(C);
+      // predicated rather than branched inside a cell: a lane that does not
+      // composite adds exact zeros, and the wavefront issues no mask
+      // bookkeeping.  Contraction is off in this kernel: every raster shape
+      // composites with the same roundings.
+      auto composite = [&](const int j) {
+        const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
+        const bool act = s.ok & !done[j];
         const float a = act ? s.alpha : 0.0f;
         const float Tn = T[j] * (1.0f - a);
-        const bool stop = act && Tn < kTMin;
-        const bool comp = act && !stop;
+        const bool stop = act & (Tn < kTMin);
+        const bool comp = act & !stop;
         const float w = comp ? a * T[j] : 0.0f;
         c0[j] = __builtin_fmaf(B.z, w, c0[j]);
         c1[j] = __builtin_fmaf(B.w, w, c1[j]);
@@ -598,8 +647,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         D[j] = __builtin_fmaf(C.y, w, D[j]);
         T[j] = comp ? Tn : T[j];
         last[j] = comp ? base + k : last[j];
-        done[j] = done[j] || stop;
-      }
+        done[j] = done[j] | stop;
+      };
+      // one cell at a time (straight-line code over all cells holds more
+      // registers and runs slower here)
+#pragma unroll
+      for (int j = 0; j < PPT; ++j)
+        if (hit & (1u << j)) composite(j);
     }
     n_live = 0;
 #pragma unroll
@@ -608,7 +662,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   const int64_t HW = (int64_t)W * H;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
-    const int py = py0 + j;
+    const int px = cell.X0[j] + lx, py = cell.Y0[j] + ly;
     if (!(px < W && py < H)) continue;
     const int64_t pix = (int64_t)py * W + px;
     rgb[pix] = __builtin_fmaf(T[j], bg0, c0[j]);
@@ -632,21 +686,27 @@ constexpr int kDppShl4 = 0x104;   // row_shl:4 (lane i reads lane i + 4)
 constexpr int kDppShr4 = 0x114;   // row_shr:4 (lane i reads lane i - 4)
 constexpr int kDppRor8 = 0x128;   // row_ror:8 (lane i reads lane i ^ 8 in a row)
 
-// Sum of 16 values over a wavefront by a halving butterfly: at each level a
-// lane keeps half of its values and adds its partner's copy of that half.
-// Levels 1, 2, 4, 8 stay inside 16-lane rows (DPP); the two cross-row
-// levels move one value each (LDS-crossbar shuffles).  Afterwards the lane
-// whose low 4 bits are l holds the wave total of value bitrev4(l).
-__device__ __forceinline__ float wave_reduce16(float (&v)[16]) {
+// Sum of 10 values over a wavefront by a halving butterfly: at each level a
+// lane keeps half of its value slots and adds its partner's copy of that
+// half, so a slot always stands for one value index.  Levels 1, 2, 4, 8
+// stay inside 16-lane rows (DPP); the two cross-row levels move one value
+// each (LDS-crossbar shuffles).  Afterwards the lane whose low 4 bits are l
+// holds the wave total of value bitrev4(l) (for bitrev4(l) < 10).  Value
+// indices 10..15 do not exist: at the first level the slots that would
+// carry them are left to hold anything, which saves their selects.
+__device__ __forceinline__ float wave_reduce10(float (&v)[16]) {
   const int lane = threadIdx.x & (kWave - 1);
   {
     const bool hi = lane & 1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 2; ++i) {
       const float send = hi ? v[i] : v[i + 8];
       const float keep = hi ? v[i + 8] : v[i];
       v[i] = keep + dpp<kDppXor1>(send);
     }
+    // slots 2..7: values 2..7 on even lanes, nothing (10..15) on odd ones
+#pragma unroll
+    for (int i = 2; i < 8; ++i) v[i] = v[i] + dpp<kDppXor1>(v[i]);
   }
   {
     const bool hi = lane & 2;
@@ -698,8 +758,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   constexpr int BS = NT < 128 ? NT : 128;  // records per batch
   constexpr int NC = 10;
   __shared__ float4 sA[BS], sB[BS], sC[BS];
-  __shared__ uint32_t sG[BS];
+  __shared__ uint32_t sG[BS], sM[BS];
   __shared__ float red[NW][BS][NC];
+  constexpr bool kOneCell = CellLayout<TW, TH, PPT>::kCells == 1;  // no cell masks needed
   __shared__ int max_last;
   const int gt = tile_of_block(n_tiles);
   if (gt >= n_tiles) return;
@@ -712,28 +773,23 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     dl_drgb += view * 3 * HWv;
     if (dl_ddepth) dl_ddepth += view * HWv;
   }
-  const int px = tx * TW + (threadIdx.x % TW);
-  const int py0 = ty * TH + (threadIdx.x / TW) * PPT;
-  const float pxh = (float)px + 0.5f;
-  float pyh[PPT];
-#pragma unroll
-  for (int j = 0; j < PPT; ++j) pyh[j] = (float)(py0 + j) + 0.5f;
-  int wy0, wy1;
-  wave_rows<TW, PPT>(ty * TH, wy0, wy1);
+  const CellLayout<TW, TH, PPT> cell(tx, ty);
+  const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7;
+  const float lxh = (float)lx + 0.5f, lyh = (float)ly + 0.5f;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int2 rg = ranges[gt];
   const int64_t HW = (int64_t)W * H;
   // GS = dL/dC . (colour and depth composited behind the current Gaussian,
   // background included): dalpha needs only this dot product
   float T[PPT], g0[PPT], g1[PPT], g2[PPT], gd[PPT], GS[PPT];
-  int last[PPT];
+  int last[PPT], cell_last[PPT];
   int my_last = -1;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
     T[j] = 1.0f;
     g0[j] = g1[j] = g2[j] = gd[j] = 0.0f;
     last[j] = -1;
-    const int py = py0 + j;
+    const int px = cell.X0[j] + lx, py = cell.Y0[j] + ly;
     if (px < W && py < H) {
       const int64_t pix = (int64_t)py * W + px;
       T[j] = Tstate[pix];
@@ -744,11 +800,16 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       if (dl_ddepth) gd[j] = dl_ddepth[pix];
     }
     GS[j] = T[j] * (g0[j] * bg0 + g1[j] * bg1 + g2[j] * bg2);
-    my_last = max(my_last, last[j]);
+    // the last list position any pixel of cell j composited (uniform)
+    int m = last[j];
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) m = max(m, __shfl_xor(m, off));
+    cell_last[j] = __builtin_amdgcn_readfirstlane(m);
+    my_last = max(my_last, cell_last[j]);
   }
   if (threadIdx.x == 0) max_last = -1;
   __syncthreads();
-  if (my_last >= 0) atomicMax(&max_last, my_last);
+  if (lane == 0 && my_last >= 0) atomicMax(&max_last, my_last);
   __syncthreads();
   const int top = max_last;
   if (top < rg.x) {
@@ -764,31 +825,44 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
       sA[threadIdx.x] = q[0];
       sB[threadIdx.x] = q[1];
-      sC[threadIdx.x] = q[2];
+      const float4 C = q[2];
+      sC[threadIdx.x] = C;
+      if constexpr (!kOneCell) sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(C, tx, ty);
     }
     __syncthreads();
+    uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
     for (int k = 0; k < nb; ++k) {
+      uint32_t mk = 1u;
+      if constexpr (!kOneCell) {
+        mk = __builtin_amdgcn_readfirstlane(m_next);
+        m_next = sM[min(k + 1, BS - 1)];
+      }
       const int pos = end - 1 - k;
-      const float4 C = sC[k];
-      // no pixel of this wave reaches pos, or none is in the record's box
-      if (__ballot(pos <= my_last) == 0 || !box_meets_rows(C, wy0, wy1)) {
+      // cell j takes part if one of its pixels composited this position
+      // and the record's box meets it
+      uint32_t alive = 0;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) alive |= (uint32_t)(pos <= cell_last[j]) << j;
+      const uint32_t hit = cell.mine(mk) & alive;
+      if (hit == 0) {
         if (lane < NC) red[wv][k][lane] = 0.0f;
         continue;
       }
-      const float4 A = sA[k], B = sB[k];
+      const float4 A = sA[k], B = sB[k], C = sC[k];
+      const Box bx = uniform_box(C);
       const float a2 = 2.0f * A.z, b2 = 2.0f * B.x;
       float v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = 0.0f;
       bool contrib = false;
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        // predicated rather than branched: a lane whose pixel does not use
-        // this Gaussian runs with alpha = 0 (1 / (1 - 0) is exact), which
-        // leaves T and S unchanged and adds exact zeros to every term
-        const Sample s = sample(px, py0 + j, pxh, pyh[j], A, B, C);
-        const bool act = s.ok && pos <= last[j];
-        contrib = contrib || act;
+      // predicated rather than branched inside a cell: a lane whose pixel
+      // does not use this Gaussian runs with alpha = 0 (1 / (1 - 0) is
+      // exact), which leaves T and S unchanged and adds exact zeros to every
+      // term
+      auto adjoint = [&](const int j) {
+        const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
+        const bool act = s.ok & (pos <= last[j]);
+        contrib = contrib | act;
         const float a = act ? s.alpha : 0.0f;
         const float iom = __builtin_amdgcn_rcpf(1.0f - a);
         const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
@@ -803,7 +877,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         GS[j] += gc * w;
         T[j] = Tk;
         // alpha not clamped: the opacity and the exponent receive gradient
-        const bool free_alpha = act && B.y * s.G <= kAlphaMax;
+        const bool free_alpha = act & (B.y * s.G <= kAlphaMax);
         const float gG = free_alpha ? s.G : 0.0f;
         const float dp = free_alpha ? a * da : 0.0f;
         v[5] += gG * da;
@@ -816,9 +890,18 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         v[2] += s.dx * s.dx * dp;
         v[3] += s.dx * s.dy * dp;
         v[4] += s.dy * s.dy * dp;
+      };
+      // every cell hit: one straight-line block the compiler can interleave
+      if (hit == (1u << PPT) - 1u) {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) adjoint(j);
+      } else {
+#pragma unroll
+        for (int j = 0; j < PPT; ++j)
+          if (hit & (1u << j)) adjoint(j);
       }
       if (__ballot(contrib) != 0) {
-        const float r = wave_reduce16(v);
+        const float r = wave_reduce10(v);
         const int c = bitrev4(lane & 15);
         if (lane < 16 && c < NC) red[wv][k][c] = r;
       } else if (lane < NC) {
