@@ -521,16 +521,62 @@ struct CellLayout {
       Y0[j] = ty * TH + (c / (TW / 8)) * 8;
     }
   }
-  // Bit c set: the record's box meets cell c of tile (tx, ty).  Computed
-  // once per record and tile by the thread that stages the record.
-  static __device__ __forceinline__ uint32_t cell_mask(const float4 &C, int tx, int ty) {
+  // Bit c set: some pixel of cell c of tile (tx, ty) may take the record
+  // (A, B, C): the cell meets the record's pixel box and, unless that cannot
+  // be decided safely, the record's alpha >= 1/255 ellipse.  Computed once
+  // per record and tile by the thread that stages the record; a cleared bit
+  // only lets a wavefront skip a cell whose every pixel the sample test
+  // would reject.
+  static __device__ __forceinline__ uint32_t cell_mask(const float4 &A, const float4 &B,
+                                                       const float4 &C, int tx, int ty) {
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
     const int i0 = bx & 0xFFFF, i1 = bx >> 16, j0 = by & 0xFFFF, j1 = by >> 16;
+    // -power = P(d) = p00 dx^2 + 2 p01 dx dy + p11 dy^2 for d = pixel centre
+    // - mean; a pixel passes only if P(d) <= log2(255 o) (alpha >= 1/255).
+    // Float32 throughout (float64 here would cost the rasterizer registers).
+    const float p00 = -A.z, p01 = -0.5f * A.w, p11 = -B.x;
+    const bool exact = p00 > 0.0f && p11 > 0.0f && p00 * p11 > p01 * p01 && B.y > 0.0f;
+    // threshold with room for the float32 exponent, opacity product and
+    // constant roundings of the sample test (a few 1e-7 in log2 units)
+    const float thr = exact ? __log2f(255.0f * B.y) + 1e-3f : 0.0f;
     uint32_t m = 0;
 #pragma unroll
     for (int c = 0; c < kCells; ++c) {
       const int x0 = tx * TW + (c % (TW / 8)) * 8, y0 = ty * TH + (c / (TW / 8)) * 8;
-      m |= (uint32_t)((i1 >= x0) & (i0 <= x0 + 7) & (j1 >= y0) & (j0 <= y0 + 7)) << c;
+      // the cell's pixels inside the box
+      const int xa = max(x0, i0), xb = min(x0 + 7, i1), ya = max(y0, j0), yb = min(y0 + 7, j1);
+      if (xa > xb || ya > yb) continue;
+      if (!exact) {
+        m |= 1u << c;
+        continue;
+      }
+      // their centres relative to the mean, rounded as the sample test's
+      // dx, dy are (the first operands are exact half-integers)
+      const float ax = ((float)(xa - i0) + 0.5f) - A.x, bx = ((float)(xb - i0) + 0.5f) - A.x;
+      const float ay = ((float)(ya - j0) + 0.5f) - A.y, by = ((float)(yb - j0) + 0.5f) - A.y;
+      // minimum of P over that rectangle: 0 inside, else on an edge (any
+      // point of an edge gives an upper bound; the clamped one is the minimum)
+      float pmin = 0.0f;
+      if (!(ax <= 0.0f && bx >= 0.0f && ay <= 0.0f && by >= 0.0f)) {
+        const float ex[2] = {ax, bx}, ey[2] = {ay, by};
+        // an approximate reciprocal moves the edge point by a few ulp,
+        // which raises P by a second-order amount far below err
+        const float r00 = __builtin_amdgcn_rcpf(p00), r11 = __builtin_amdgcn_rcpf(p11);
+        pmin = 3.0e38f;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float x = ex[e], yy = fminf(fmaxf(-p01 * x * r11, ay), by);
+          pmin = fminf(pmin, p00 * x * x + 2.0f * p01 * x * yy + p11 * yy * yy);
+          const float y = ey[e], xx = fminf(fmaxf(-p01 * y * r00, ax), bx);
+          pmin = fminf(pmin, p00 * xx * xx + 2.0f * p01 * xx * y + p11 * y * y);
+        }
+      }
+      // bound on the float32 rounding of P here and in the sample test at
+      // any of the pixels: a handful of roundings each of terms no larger
+      // than these
+      const float X = fmaxf(fabsf(ax), fabsf(bx)), Y = fmaxf(fabsf(ay), fabsf(by));
+      const float err = 32.0f * 0x1p-24f * (p00 * X * X + 2.0f * fabsf(p01) * X * Y + p11 * Y * Y);
+      if (pmin - err <= thr) m |= 1u << c;
     }
     return m;
   }
@@ -601,11 +647,12 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     if (p < rg.y) {
       const uint32_t g = (uint32_t)pairs[p];
       const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
-      sA[threadIdx.x] = q[0];
-      sB[threadIdx.x] = q[1];
-      const float4 C = q[2];
+      const float4 A = q[0], B = q[1], C = q[2];
+      sA[threadIdx.x] = A;
+      sB[threadIdx.x] = B;
       sC[threadIdx.x] = C;
-      if constexpr (!kOneCell) sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(C, tx, ty);
+      if constexpr (!kOneCell)
+        sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(A, B, C, tx, ty);
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
@@ -823,11 +870,12 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const uint32_t g = (uint32_t)pairs[end - 1 - threadIdx.x];
       sG[threadIdx.x] = g;
       const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
-      sA[threadIdx.x] = q[0];
-      sB[threadIdx.x] = q[1];
-      const float4 C = q[2];
+      const float4 A = q[0], B = q[1], C = q[2];
+      sA[threadIdx.x] = A;
+      sB[threadIdx.x] = B;
       sC[threadIdx.x] = C;
-      if constexpr (!kOneCell) sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(C, tx, ty);
+      if constexpr (!kOneCell)
+        sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(A, B, C, tx, ty);
     }
     __syncthreads();
     uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
