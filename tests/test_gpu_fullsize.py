@@ -98,7 +98,7 @@ def test_headline_keyframe(ctx):
 def test_headline_window_in_the_bench_launch_configuration(ctx):
     """The bench's timed unit at full size: a 16-keyframe window rendered
     and differentiated in one launch sequence at the raster shape the
-    autotuner picks for it (16x16 tiles, 2 pixels per lane forward, 4
+    autotuner picks for it (16x16 tiles, 4 pixels per lane forward and
     backward).  Every view's image and the summed gradient equal the
     per-view path bit for bit; one view's central crop against the oracle."""
     import bench
@@ -114,7 +114,7 @@ def test_headline_window_in_the_bench_launch_configuration(ctx):
     pool.require(ids, now=0)
     n = pool.compact(ids, loop.params, loop.src, masks=masks, out_gmask=loop.gmask)
     assert 2.0e6 < n < 3.4e6
-    tile, ppt = (16, 16), 2 | 4 << 4
+    tile, ppt = (16, 16), 4 | 4 << 4
     print(f"case fullsize window: V={V} n={n}", flush=True)
     bg = (0.0, 0.0, 0.0)
     st_b = D.RenderState(ctx)
@@ -144,4 +144,37 @@ def test_headline_window_in_the_bench_launch_configuration(ctx):
     ok = ~flag
     got = rgb_b[v].cpu().numpy()[:, y0:y1, x0:x1]
     assert np.abs(got - img.rgb.detach().numpy())[:, ok].max() <= IMG_TOL
+    pool.close()
+
+
+def test_cell_skipping_changes_no_pixel_at_full_size(ctx):
+    """The rasterizers skip 8x8 cells that a record's box or alpha >= 1/255
+    ellipse misses.  Every raster shape composites each pixel with the same
+    roundings, so a 16-keyframe window rendered with multi-cell tiles must
+    equal, bit for bit, the same window with 8x8 tiles (one cell per tile,
+    no cell masks): a cell skipped wrongly would change some pixel."""
+    import bench
+    w = bench.make_workload("indoor-2m")
+    V = 16
+    cams = w["cams"][8:8 + V]
+    W, H, deg, s = w["W"], w["H"], w["deg"], w["chunk"]
+    pool = D.Pool(ctx, deg, budget=w["n"] + 1)
+    pool.ingest(w["start"], s)
+    loop = mapping.MappingLoop(ctx, pool, deg, s, 3_400_000, W, H, (16, 16))
+    loop._window_buffers(V)
+    ids, masks = loop.select_window(cams)
+    pool.require(ids, now=0)
+    n = pool.compact(ids, loop.params, loop.src, masks=masks, out_gmask=loop.gmask)
+    bg = (0.05, 0.1, 0.2)
+    st = D.RenderState(ctx)
+    T0 = torch.empty(V, H, W, device="cuda")
+    rgb0, depth0 = st.forward(loop.params, n, deg, cams, bg, (8, 8), ppt=1, gmask=loop.gmask, T=T0)
+    rgb0, depth0 = rgb0.clone(), depth0.clone()
+    for tile, ppt in (((16, 16), 4), ((16, 16), 2), ((32, 16), 8)):
+        print(f"case cell skipping: V={V} n={n} tile={tile} ppt={ppt}", flush=True)
+        T1 = torch.empty(V, H, W, device="cuda")
+        rgb1, depth1 = st.forward(loop.params, n, deg, cams, bg, tile, ppt=ppt, gmask=loop.gmask,
+                                  T=T1)
+        torch.cuda.synchronize()
+        assert torch.equal(rgb1, rgb0) and torch.equal(depth1, depth0) and torch.equal(T1, T0)
     pool.close()
