@@ -165,6 +165,13 @@ __global__ void __launch_bounds__(kSortThreads)
 // digit into LDS (so its keys sit there grouped by digit, in input order
 // within a digit), then writes each digit's run to its global offset:
 // consecutive threads write consecutive addresses of one run.
+// Ranking: wavefront w owns the contiguous keys [1024 w, 1024 w + 1024) and
+// walks them 64 at a time in order; a key's rank among equal digits of its
+// step comes from ballots (a match mask per digit), and a per-wavefront
+// running count per digit (LDS, touched by that wavefront only) places it
+// after the equal digits of the wavefront's earlier steps.  One scan of the
+// per-wavefront counts, digit-major, then gives every key its slot: the
+// workgroup synchronises a fixed number of times, not once per step.
 template <typename K, bool kVals>
 __global__ void __launch_bounds__(kSortThreads)
     k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
@@ -172,69 +179,91 @@ __global__ void __launch_bounds__(kSortThreads)
                  const int64_t *__restrict__ n_dev, int64_t n, int shift, int width,
                  const uint32_t *__restrict__ hist, const uint32_t *__restrict__ offs,
                  int64_t nb) {
+  constexpr int kPerWave = kSortTile / kSortWaves;  // 1024 keys
+  constexpr int kSteps = kPerWave / kWave;           // 16
   __shared__ K sk[kSortTile];
   __shared__ uint32_t sv[kVals ? kSortTile : 1];
   __shared__ uint32_t gofs[256];  // global offset of the block's run of digit d
-  __shared__ uint32_t lofs[256];  // start of digit d's run in sk, then its fill
-  __shared__ uint32_t wcnt[kSortWaves][256];
+  __shared__ uint32_t lofs[256];  // start of digit d's run in sk
+  __shared__ uint32_t wcnt[kSortWaves][256];  // per wavefront: count, then slot base
   n = count_of(n_dev, n);
   const uint32_t bins = 1u << width, mask = bins - 1;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= n) return;  // uniform across the block
   const int cnt = (int)min<int64_t>(kSortTile, n - base);
-  {  // local run starts: exclusive scan of this block's digit counts
-    const uint32_t d = threadIdx.x;
-    const uint32_t c = d < bins ? hist[(int64_t)d * nb + blockIdx.x] : 0u;
-    uint32_t excl;
-    block_exclusive_scan(c, &excl);
-    if (d < bins) {
-      lofs[d] = excl;
-      gofs[d] = offs[(int64_t)d * nb + blockIdx.x];
-    }
-  }
+  for (int t = threadIdx.x; t < kSortWaves * 256; t += kSortThreads) (&wcnt[0][0])[t] = 0;
+  if (threadIdx.x < 256) gofs[threadIdx.x] = threadIdx.x < bins ?
+      offs[(int64_t)threadIdx.x * nb + blockIdx.x] : 0u;
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  for (int r = 0; r < kSortRounds; ++r) {
-    if (r * kSortThreads >= cnt) break;  // uniform across block
-    for (int t = threadIdx.x; t < kSortWaves * 256; t += kSortThreads)
-      (&wcnt[0][0])[t] = 0;
-    __syncthreads();
-    const int li = r * kSortThreads + threadIdx.x;
+  K key[kSteps];
+  uint32_t val[kVals ? kSteps : 1];
+  uint32_t pos[kSteps];
+#pragma unroll
+  for (int r = 0; r < kSteps; ++r) {
+    const int li = w * kPerWave + r * kWave + lane;
     const bool valid = li < cnt;
-    const K key = valid ? kin[base + li] : K(0);
-    const uint32_t val = (kVals && valid) ? vin[base + li] : 0u;
-    const uint32_t d = digit_of(key, shift, mask);
+    key[r] = valid ? kin[base + li] : K(0);
+    if (kVals) val[r] = valid ? vin[base + li] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kSteps; ++r) {
+    const int li = w * kPerWave + r * kWave + lane;
+    const bool valid = li < cnt;
+    const uint32_t d = digit_of(key[r], shift, mask);
     uint64_t peers = __ballot(valid);
     for (int b = 0; b < width; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t rank = __popcll(peers & lt);
-    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = lofs[d] + rank;
-      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      sk[pos] = key;
-      if (kVals) sv[pos] = val;
-    }
-    __syncthreads();
-    for (uint32_t dd = threadIdx.x; dd < bins; dd += kSortThreads) {
-      uint32_t s = 0;
-      for (int k = 0; k < kSortWaves; ++k) s += wcnt[k][dd];
-      lofs[dd] += s;  // now the end of what is filled
-    }
-    __syncthreads();
+    // the running count is read by every lane before the step's leader
+    // adds to it (in-order LDS access within the wavefront)
+    const uint32_t before = valid ? wcnt[w][d] : 0u;
+    pos[r] = before + (uint32_t)__popcll(peers & lt);
+    __builtin_amdgcn_wave_barrier();
+    if (valid && (peers & lt) == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
-  // lofs[d] is now the end of digit d's run; its start is end - count
+  __syncthreads();
+  {  // slot bases: exclusive scan over (digit, wavefront), digit-major
+    const uint32_t d = threadIdx.x;
+    uint32_t c[kSortWaves], tot = 0;
+#pragma unroll
+    for (int k = 0; k < kSortWaves; ++k) {
+      c[k] = d < bins ? wcnt[k][d] : 0u;
+      tot += c[k];
+    }
+    uint32_t excl;
+    block_exclusive_scan(tot, &excl);
+    if (d < bins) {
+      lofs[d] = excl;
+      uint32_t run = excl;
+#pragma unroll
+      for (int k = 0; k < kSortWaves; ++k) {
+        wcnt[k][d] = run;
+        run += c[k];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSteps; ++r) {
+    const int li = w * kPerWave + r * kWave + lane;
+    if (li < cnt) {
+      const uint32_t q = wcnt[w][digit_of(key[r], shift, mask)] + pos[r];
+      sk[q] = key[r];
+      if (kVals) sv[q] = val[r];
+    }
+  }
+  __syncthreads();
   for (int p = threadIdx.x; p < cnt; p += kSortThreads) {
-    const K key = sk[p];
-    const uint32_t d = digit_of(key, shift, mask);
-    const uint32_t start = lofs[d] - hist[(int64_t)d * nb + blockIdx.x];
-    const uint32_t pos = gofs[d] + (uint32_t)p - start;
-    kout[pos] = key;
-    if (kVals) vout[pos] = sv[p];
+    const K k = sk[p];
+    const uint32_t d = digit_of(k, shift, mask);
+    const uint32_t o = gofs[d] + (uint32_t)p - lofs[d];
+    kout[o] = k;
+    if (kVals) vout[o] = sv[p];
   }
 }
 
