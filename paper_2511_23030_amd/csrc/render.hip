@@ -1103,11 +1103,14 @@ __global__ void __launch_bounds__(256)
                    const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
                    const uint32_t *__restrict__ rank_of, const uint64_t *__restrict__ tmask,
                    const int *__restrict__ frontier, const float2 *__restrict__ partial,
-                   float *__restrict__ s2d) {
+                   float *__restrict__ s2d, int zero_undrawn) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
   if (r >= nr || cnt[3] != 0) return;
   float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  // the projection backward reads only drawn records: an undrawn one's
+  // planes are written (as zeros) only for a caller's own output buffer
+  if (count[r] == 0 && !zero_undrawn) return;
   if (count[r] > 0) {
     const float4 C = rec[3 * r + 2];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
@@ -1118,16 +1121,21 @@ __global__ void __launch_bounds__(256)
     const int tile_base = (int)(r / n) * tiles_per_view;
     uint32_t slot = pair_off[r];
     const int rank = (int)rank_of[r];
-    for (int k = 0; k < n_rect; ++k) {
-      if (!tile_kept(m, n_rect, k)) continue;
+    auto add = [&](int k) {
       const int t = tile_base + (ty0 + k / wc) * tiles_x + tx0 + k % wc;
       const uint32_t sl = slot++;
-      if (frontier[t] < rank) continue;
+      if (frontier[t] < rank) return;
       const float2 *pp = partial + 5 * (int64_t)sl;
       const float2 q0 = pp[0], q1 = pp[1], q2 = pp[2], q3 = pp[3], q4 = pp[4];
       s[0] += q0.x; s[1] += q0.y; s[2] += q1.x; s[3] += q1.y;
       s[4] += q2.x; s[5] += q2.y; s[6] += q3.x; s[7] += q3.y;
       s[8] += q4.x; s[9] += q4.y;
+    };
+    if (n_rect > 64) {
+      for (int k = 0; k < n_rect; ++k) add(k);
+    } else {
+      // the kept tiles, lowest bit first (the order their slots were laid out)
+      for (uint64_t mm = m; mm != 0; mm &= mm - 1) add(__builtin_ctzll(mm));
     }
   }
 #pragma unroll
@@ -1525,7 +1533,7 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, cnt,
                        s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p, s->count.p,
                        s->pair_off.p, s->rank_of.p, s->tmask.p, s->frontier.p, s->partial.p,
-                       s2d);
+                       s2d, grad2d ? 1 : 0);
     DCGS_LAUNCH_CHECK();
 #define DCGS_PBWD(D)                                                                        \
   hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st,   \
