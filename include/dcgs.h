@@ -253,7 +253,8 @@ void dcgs_state_destroy(dcgs_state *st);
  *   cams: host [n_views], 1 <= n_views <= 16, all of one width and height
  *   bg: host float[3]
  *   raster shape: tile_w x tile_h pixels per workgroup, pixels_per_lane
- *   vertically adjacent pixels per lane; supported (16,16,{1,2,4}),
+ *   pixels per lane (one in each of that many 8x8 cells of the tile);
+ *   supported (16,16,{1,2,4}),
  *   (8,8,1), (32,16,{2,4,8}); pixels_per_lane 0 picks 2, 1 and 4.  Bits
  *   0-3 of pixels_per_lane are the forward's, bits 4-7 the backward's
  *   (0: the forward's), so the two rasters of one tile size may map pixels
