@@ -386,10 +386,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   }
 }
 
-__global__ void k_rank(const uint32_t *__restrict__ order, const int64_t *__restrict__ cnt,
-                       uint32_t *__restrict__ rank_of) {
+// Depth rank of every record, and the records' pair counts in depth order
+// (what the pair-offset scan sums, read once here instead of gathered by it).
+__global__ void k_rank(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
+                       const int64_t *__restrict__ cnt, uint32_t *__restrict__ rank_of,
+                       uint32_t *__restrict__ count_sorted) {
   int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < cnt[1]) rank_of[order[j]] = (uint32_t)j;
+  if (j >= cnt[1]) return;
+  const uint32_t r = order[j];
+  rank_of[r] = (uint32_t)j;
+  count_sorted[j] = count[r];
 }
 
 // Pair total = scan[nr].  cnt[2] = pairs to process; cnt[3] = the total
@@ -406,23 +412,25 @@ __global__ void k_pairs_total(const uint32_t *__restrict__ scan, int64_t *__rest
   if (over) cnt[4] = 1;
 }
 
-// Pairs of record r = v n + g: (global tile v T + t) << 32 | r, emitted in
-// depth order, tiles of a record row-major.
-__global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
+// Pairs of record r = v n + g: (global tile v T + t) << 32 | r, laid out in
+// depth order (the run of the record of depth rank j starts at scan[j]),
+// tiles of a record row-major.  One thread per record in record order: its
+// count, box and tile mask are read coalesced, and only its run's start is
+// gathered (by depth rank).
+__global__ void k_emit(const uint32_t *__restrict__ rank_of, const uint32_t *__restrict__ count,
                        const uint32_t *__restrict__ scan, const float4 *__restrict__ rec,
                        const uint64_t *__restrict__ tmask, const int64_t *__restrict__ cnt,
                        int TW, int TH, int tiles_x, int tiles_per_view,
                        uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
-  if (j >= nr || cnt[3] != 0) return;
-  const uint32_t g = order[j];
-  const uint32_t view_base = (uint32_t)(g / (uint64_t)n) * (uint32_t)tiles_per_view;
+  if (g >= nr || cnt[3] != 0) return;
   const uint32_t c = count[g];
-  const uint32_t base = scan[j];
+  if (c == 0) return;  // no pairs; its pair offset is never read
+  const uint32_t base = scan[rank_of[g]];
   pair_off[g] = base;
-  if (c == 0) return;
-  const float4 C = rec[3 * (int64_t)g + 2];
+  const uint32_t view_base = (uint32_t)(g / n) * (uint32_t)tiles_per_view;
+  const float4 C = rec[3 * g + 2];
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
   const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
@@ -433,7 +441,7 @@ __global__ void k_emit(const uint32_t *__restrict__ order, const uint32_t *__res
   for (int ty = ty0; ty <= ty1; ++ty)
     for (int tx = tx0; tx <= tx1; ++tx, ++idx)
       if (tile_kept(m, n_rect, idx))
-        pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | g;
+        pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | (uint32_t)g;
 }
 
 __global__ void k_ranges(const uint64_t *__restrict__ pairs, const int64_t *__restrict__ cnt,
@@ -1412,12 +1420,13 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
     // depth order of all records: stable sort of the float32 depth bits
     sort_u32_pairs(sortkey, order, sortkey + RS + 1, s->val_tmp.p, nr, 32, s->hist, st,
                    cnt + 1);
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, cnt,
-                       s->rank_of.p);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, s->count.p,
+                       cnt, s->rank_of.p, sortkey + RS + 1);
     DCGS_LAUNCH_CHECK();
   }
   StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-  scan_u32(s->count.p, order, s->scan.p, nr, s->scan_part.p, st, cnt + 1);
+  // the depth sort's second key buffer holds the counts in depth order now
+  scan_u32(sortkey + RS + 1, nullptr, s->scan.p, nr, s->scan_part.p, st, cnt + 1);
   hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, st, s->scan.p, cnt, pcap);
   DCGS_LAUNCH_CHECK();
 }
@@ -1434,7 +1443,7 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
   int64_t *cnt = counters(s, st);
   if (nr > 0) {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->order.p,
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->rank_of.p,
                        s->count.p, s->scan.p, s->rec.p, s->tmask.p, cnt, s->TW,
                        s->TH, s->tiles_x, tpv, s->pairs.p, s->pair_off.p);
     DCGS_LAUNCH_CHECK();
