@@ -906,7 +906,6 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       }
       const float4 A = sA[k], B = sB[k], C = sC[k];
       const Box bx = uniform_box(C);
-      const float a2 = 2.0f * A.z, b2 = 2.0f * B.x;
       float v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = 0.0f;
@@ -937,10 +936,11 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         const float gG = free_alpha ? s.G : 0.0f;
         const float dp = free_alpha ? a * da : 0.0f;
         v[5] += gG * da;
-        // scaled conic: (Q00 dx + Q01 dy) = kQ/2 (2 A.z dx + A.w dy); the
-        // factor kQ/2 is applied once per record after the reduction
-        v[0] += dp * (a2 * s.dx + A.w * s.dy);
-        v[1] += dp * (A.w * s.dx + b2 * s.dy);
+        // the mean's gradient is linear in (sum dp dx, sum dp dy): the
+        // conic (scaled: Q00 dx + Q01 dy = kQ/2 (2 A.z dx + A.w dy)) is
+        // applied once per record after the reduction
+        v[0] += dp * s.dx;
+        v[1] += dp * s.dy;
         // d power / d(Q00, Q01, Q11) = -(dx^2 / 2, dx dy, dy^2 / 2): the
         // constant factors are applied after the reduction
         v[2] += s.dx * s.dx * dp;
@@ -975,8 +975,12 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         for (int w = 0; w < NW; ++w) a += red[w][k][c];
         s[c] = a;
       }
-      s[0] *= 0.5f * kQ;
-      s[1] *= 0.5f * kQ;
+      {
+        const float4 A = sA[k], B = sB[k];
+        const float sx = s[0], sy = s[1];
+        s[0] = 0.5f * kQ * (2.0f * A.z * sx + A.w * sy);
+        s[1] = 0.5f * kQ * (A.w * sx + 2.0f * B.x * sy);
+      }
       s[2] *= -0.5f;
       s[3] = -s[3];
       s[4] *= -0.5f;
