@@ -909,7 +909,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       float v[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) v[c] = 0.0f;
-      bool contrib = false;
+      uint64_t contrib = 0;  // lanes that composited this record in some cell
       // predicated rather than branched inside a cell: a lane whose pixel
       // does not use this Gaussian runs with alpha = 0 (1 / (1 - 0) is
       // exact), which leaves T and S unchanged and adds exact zeros to every
@@ -917,7 +917,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       auto adjoint = [&](const int j) {
         const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
         const bool act = s.ok & (pos <= last[j]);
-        contrib = contrib | act;
+        contrib |= __ballot(act);
         const float a = act ? s.alpha : 0.0f;
         const float iom = __builtin_amdgcn_rcpf(1.0f - a);
         const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
@@ -956,7 +956,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         for (int j = 0; j < PPT; ++j)
           if (hit & (1u << j)) adjoint(j);
       }
-      if (__ballot(contrib) != 0) {
+      if (contrib != 0) {
         const float r = wave_reduce10(v);
         const int c = bitrev4(lane & 15);
         if (lane < 16 && c < NC) red[wv][k][c] = r;
