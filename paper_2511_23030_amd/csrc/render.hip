@@ -245,7 +245,7 @@ __device__ inline void load_geo(const float *__restrict__ P, int64_t stride, int
 
 // Colour before the clamp (raw) for each channel.
 template <typename T>
-__device__ inline void color_raw(const float *__restrict__ P, int64_t stride, int64_t i,
+__device__ inline void color_raw(const float *__restrict__ coef, int64_t cstride,
                                  int deg, const GeoT<T> &g, const CamD &cam, T *dir, T &dnorm,
                                  T *Y, T raw[3]) {
   T d0 = g.mu[0] - (T)cam.C[0], d1 = g.mu[1] - (T)cam.C[1], d2 = g.mu[2] - (T)cam.C[2];
@@ -257,10 +257,18 @@ __device__ inline void color_raw(const float *__restrict__ P, int64_t stride, in
   const int K = (deg + 1) * (deg + 1);
   for (int ch = 0; ch < 3; ++ch) {
     T acc = T(0);
-    // not unrolled: the 48 coefficient loads would otherwise be hoisted
-    // into registers and cap the occupancy of the backward kernel
+    if constexpr (sizeof(T) == 4) {
+      // float (the projection backward): unrolled by 4, not fully, so four
+      // coefficient loads are in flight per step without hoisting all 48
+      // into registers (which would cap the kernel's occupancy)
+#pragma unroll 4
+      for (int k = 0; k < K; ++k) acc += (T)coef[(3 * k + ch) * cstride] * Y[k];
+    } else {
+      // double (the forward projection, held to 128 registers): rolled;
+      // its coefficients come from LDS
 #pragma unroll 1
-    for (int k = 0; k < K; ++k) acc += (T)P[(11 + 3 * k + ch) * stride + i] * Y[k];
+      for (int k = 0; k < K; ++k) acc += (T)coef[(3 * k + ch) * cstride] * Y[k];
+    }
     raw[ch] = acc + T(0.5);
   }
 }
@@ -335,18 +343,24 @@ __device__ __forceinline__ bool tile_kept(uint64_t m, int n_rect, int k) {
 // sized for a capacity).
 // Four waves per SIMD: the float64 projection is latency-bound, and the
 // compiler fits it in 128 registers without spilling.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8)))
+constexpr int kPrepThreads = 64;
+__global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
     k_preprocess(const float *__restrict__ P, const int64_t *__restrict__ cnt, int64_t stride,
                  int deg, const CamD *__restrict__ cams, int V,
                  const uint16_t *__restrict__ gmask, int mask_shift, int TW, int TH,
                  float4 *__restrict__ rec, int64_t RS, uint32_t *__restrict__ zkey,
                  uint32_t *__restrict__ sortkey, uint32_t *__restrict__ order,
                  uint32_t *__restrict__ count, uint64_t *__restrict__ tmask) {
+  // the Gaussian's colour coefficients, read once for all views into this
+  // thread's LDS column (each thread reads back only its own column)
+  __shared__ float shc[48][kPrepThreads];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0];
   if (i >= n) return;
   Geo g;
   load_gauss(P, stride, i, g);
+  for (int r = 0; r < 3 * (deg + 1) * (deg + 1); ++r)
+    shc[r][threadIdx.x] = P[(11 + r) * stride + i];
   const unsigned m = gmask ? ((unsigned)gmask[i] >> mask_shift) : 0xFFFFu;
   for (int v = 0; v < V; ++v) {
     const int64_t r = v * n + i;
@@ -370,7 +384,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
       continue;
     }
     double dir[3], dn, Y[16], raw[3];
-    color_raw(P, stride, i, deg, g, cam, dir, dn, Y, raw);
+    color_raw(&shc[0][threadIdx.x], kPrepThreads, deg, g, cam, dir, dn, Y, raw);
     uint32_t n_keep;
     tmask[r] = tile_mask(g, TW, TH, n_keep);
     count[r] = n_keep;
@@ -1082,13 +1096,13 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
   const T glogit = go * g.o * (T(1) - g.o);
   // colour
   T dir[3], dn, raw[3];
-  color_raw(P, stride, i, deg, g, cam, dir, dn, Yb, raw);
+  color_raw(P + 11 * stride + i, stride, deg, g, cam, dir, dn, Yb, raw);
   for (int ch = 0; ch < 3; ++ch) graw[ch] = raw[ch] > T(0) ? (T)s[6 + ch] : T(0);
   const int K = (deg + 1) * (deg + 1);
   if (deg > 0) {
     T f[16];
     f[0] = T(0);
-#pragma unroll 1
+#pragma unroll 4
     for (int k = 1; k < K; ++k) {
       T a = T(0);
       for (int ch = 0; ch < 3; ++ch) a += (T)P[(11 + 3 * k + ch) * stride + i] * graw[ch];
@@ -1414,7 +1428,8 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
   uint32_t *sortkey = s->key_tmp.p, *order = s->order.p;
   if (n_grid > 0) {
     StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st, params,
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, kPrepThreads)), dim3(kPrepThreads),
+                       0, st, params,
                        cnt, stride, s->sh_degree, dc, V, gmask, mask_shift, s->TW, s->TH,
                        s->rec.p, RS, s->zkey.p, sortkey, order, s->count.p, s->tmask.p);
     DCGS_LAUNCH_CHECK();
