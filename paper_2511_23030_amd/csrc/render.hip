@@ -1145,23 +1145,52 @@ __global__ void __launch_bounds__(256)
     const int wc = tx1 - tx0 + 1, n_rect = wc * (ty1 - ty0 + 1);
     const uint64_t m = tmask[r];
     const int tile_base = (int)(r / n) * tiles_per_view;
-    uint32_t slot = pair_off[r];
+    const uint32_t slot = pair_off[r];
     const int rank = (int)rank_of[r];
-    auto add = [&](int k) {
-      const int t = tile_base + (ty0 + k / wc) * tiles_x + tx0 + k % wc;
-      const uint32_t sl = slot++;
-      if (frontier[t] < rank) return;
-      const float2 *pp = partial + 5 * (int64_t)sl;
-      const float2 q0 = pp[0], q1 = pp[1], q2 = pp[2], q3 = pp[3], q4 = pp[4];
-      s[0] += q0.x; s[1] += q0.y; s[2] += q1.x; s[3] += q1.y;
-      s[4] += q2.x; s[5] += q2.y; s[6] += q3.x; s[7] += q3.y;
-      s[8] += q4.x; s[9] += q4.y;
-    };
-    if (n_rect > 64) {
-      for (int k = 0; k < n_rect; ++k) add(k);
-    } else {
-      // the kept tiles, lowest bit first (the order their slots were laid out)
-      for (uint64_t mm = m; mm != 0; mm &= mm - 1) add(__builtin_ctzll(mm));
+    const uint32_t c = count[r];  // kept tiles: popcount(m), or n_rect beyond 64
+    uint64_t mm = m;
+    // the kept tiles in slot order (lowest mask bit first), four at a time:
+    // their frontier reads, then the partial reads of the reached ones, are
+    // issued together, and the sums are taken in slot order afterwards
+    for (uint32_t b = 0; b < c; b += 4) {
+      int t[4];
+      bool ok[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ok[i] = b + i < c;
+        int k = 0;
+        if (ok[i]) {
+          if (n_rect > 64) {
+            k = (int)(b + i);
+          } else {
+            k = __builtin_ctzll(mm);
+            mm &= mm - 1;
+          }
+        }
+        t[i] = tile_base + (ty0 + k / wc) * tiles_x + tx0 + k % wc;
+      }
+      int f[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) f[i] = ok[i] ? frontier[t[i]] : -1;
+      float2 q[4][5];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float2 *pp = partial + 5 * (int64_t)(slot + b + i);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) q[i][j] = make_float2(0.0f, 0.0f);
+        if (ok[i] && f[i] >= rank) {  // that tile's backward reached the record
+#pragma unroll
+          for (int j = 0; j < 5; ++j) q[i][j] = pp[j];
+        }
+      }
+      // an unreached tile adds exact zeros (s never holds -0)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          s[2 * j] += q[i][j].x;
+          s[2 * j + 1] += q[i][j].y;
+        }
     }
   }
 #pragma unroll
