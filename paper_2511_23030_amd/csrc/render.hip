@@ -759,7 +759,7 @@ constexpr int kDppRor8 = 0x128;   // row_ror:8 (lane i reads lane i ^ 8 in a row
 // lane keeps half of its value slots and adds its partner's copy of that
 // half, so a slot always stands for one value index.  Levels 1, 2, 4, 8
 // stay inside 16-lane rows (DPP); the two cross-row levels move one value
-// each (LDS-crossbar shuffles).  Afterwards the lane whose low 4 bits are l
+// each (row swaps).  Afterwards the lane whose low 4 bits are l
 // holds the wave total of value bitrev4(l) (for bitrev4(l) < 10).  Value
 // indices 10..15 do not exist: at the first level the slots that would
 // carry them are left to hold anything, which saves their selects.
@@ -802,9 +802,20 @@ __device__ __forceinline__ float wave_reduce10(float (&v)[16]) {
     const float keep = hi ? v[1] : v[0];
     v[0] = keep + dpp<kDppRor8>(send);
   }
+  // the two cross-row levels with gfx950's row swaps (VALU, no LDS
+  // crossbar): each yields a lane's value and its partner's, lower row
+  // first in both lanes
   float r = v[0];
-  r += __shfl_xor(r, 16);
-  r += __shfl_xor(r, 32);
+  {
+    const auto q = __builtin_amdgcn_permlane16_swap(__float_as_uint(r), __float_as_uint(r),
+                                                    false, false);
+    r = __uint_as_float(q[0]) + __uint_as_float(q[1]);  // lanes l and l ^ 16
+  }
+  {
+    const auto q = __builtin_amdgcn_permlane32_swap(__float_as_uint(r), __float_as_uint(r),
+                                                    false, false);
+    r = __uint_as_float(q[0]) + __uint_as_float(q[1]);  // lanes l and l ^ 32
+  }
   return r;
 }
 
