@@ -506,8 +506,10 @@ __device__ __forceinline__ Sample sample(int lx, int ly, float lxh, float lyh, i
   // the same roundings (HIP's __f*_rn helpers are plain operators).
 #pragma clang fp contract(off)
   Sample s;
-  // bitwise, not short-circuit: no lane-mask branch for a partial cell
-  s.ok = (lx >= b.i0 - X0) & (lx <= b.i1 - X0) & (ly >= b.j0 - Y0) & (ly <= b.j1 - Y0);
+  // bitwise, not short-circuit: no lane-mask branch for a partial cell; one
+  // unsigned range compare per axis (the box is never empty: i0 <= i1)
+  s.ok = ((uint32_t)(lx - (b.i0 - X0)) <= (uint32_t)(b.i1 - b.i0)) &
+         ((uint32_t)(ly - (b.j0 - Y0)) <= (uint32_t)(b.j1 - b.j0));
   s.dx = (lxh + (float)(X0 - b.i0)) - A.x;
   s.dy = (lyh + (float)(Y0 - b.j0)) - A.y;
   // the record holds the conic scaled by -log2(e) / 2 (off-diagonal by
