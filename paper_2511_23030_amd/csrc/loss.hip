@@ -5,9 +5,10 @@
 //
 // SSIM uses the 11-tap Gaussian window (sigma 1.5) applied separably with
 // zero padding, C1 = 0.01^2, C2 = 0.03^2.  Forward and backward are image
-// stencils: one 256-thread workgroup per 16 x 16 output tile of one colour
-// plane stages the tile plus a 5-pixel halo in LDS, blurs rows, then
-// columns.  The forward writes, per pixel, the derivatives of that pixel's
+// stencils: one 256-thread workgroup per 32 x 32 output tile of one colour
+// plane stages the tile plus a 5-pixel halo in LDS (1.7 reads per pixel),
+// blurs rows, then columns, each thread finishing four vertically adjacent
+// pixels from one sweep of 14 staged rows.  The forward writes, per pixel, the derivatives of that pixel's
 // SSIM with respect to the three local moments (mean, mean of squares, mean
 // of products); the backward blurs those maps again (the window is
 // symmetric, so the adjoint of the blur is the blur) and combines them with
@@ -18,7 +19,8 @@
 namespace dcgs {
 namespace {
 
-constexpr int kT = 16;           // output tile side
+constexpr int kT = 32;           // output tile side
+constexpr int kPP = kT * kT / 256;  // output pixels per thread (a column run)
 constexpr int kR = 5;            // window radius
 constexpr int kS = kT + 2 * kR;  // staged side
 constexpr float kC1 = 0.01f * 0.01f;
@@ -27,6 +29,18 @@ constexpr float kC2 = 0.03f * 0.03f;
 struct Window11 {
   float g[11];
 };
+
+// Sum of one float per thread over a 256-thread workgroup in a fixed order
+// (wavefront butterflies, then the four wavefront totals in order); every
+// thread gets the total.  red: kWave-strided scratch of 4 floats.
+__device__ inline float block_sum(float v, float *red) {
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) v += __shfl_xor(v, off);
+  __syncthreads();  // red may still be read by an earlier call's threads
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
 
 // Stage an (kS x kS) region of a plane (zero outside) for up to 3 inputs.
 template <int NIN>
@@ -50,7 +64,7 @@ __global__ void __launch_bounds__(256)
                float *__restrict__ cmap, float *__restrict__ part) {
   __shared__ float s[2][kS][kS + 1];
   __shared__ float h[5][kS][kT + 1];
-  __shared__ float red[256];
+  __shared__ float red[256 / kWave];
   const int64_t HW = (int64_t)W * H;
   const int64_t plane = blockIdx.z;
   x += plane * HW;
@@ -79,37 +93,49 @@ __global__ void __launch_bounds__(256)
     h[4][r][c] = mxy;
   }
   __syncthreads();
-  const int r = threadIdx.x / kT, c = threadIdx.x % kT;
-  float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  // columns: thread (c, r0) finishes rows r0 .. r0 + kPP - 1 of column c;
+  // every output sums its 11 taps in order
+  const int c = threadIdx.x % kT, r0 = (threadIdx.x / kT) * kPP;
+  float m[kPP][5];
 #pragma unroll
-  for (int k = 0; k < 11; ++k) {
-    const float g = win.g[k];
+  for (int p = 0; p < kPP; ++p)
 #pragma unroll
-    for (int q = 0; q < 5; ++q) m[q] = fmaf(g, h[q][r + k][c], m[q]);
+    for (int q = 0; q < 5; ++q) m[p][q] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 11 + kPP - 1; ++k) {
+    float hv[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) hv[q] = h[q][r0 + k][c];
+#pragma unroll
+    for (int p = 0; p < kPP; ++p)
+      if (k - p >= 0 && k - p < 11) {
+        const float g = win.g[k - p];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) m[p][q] = fmaf(g, hv[q], m[p][q]);
+      }
   }
-  const int px = blockIdx.x * kT + c, py = blockIdx.y * kT + r;
-  float S = 0.0f;
-  if (px < W && py < H) {
-    const float mx = m[0], my = m[1];
-    const float sx = m[2] - mx * mx, sy = m[3] - my * my, sxy = m[4] - mx * my;
-    const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
-    const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
-    const float iB = 1.0f / (B1 * B2);
-    S = A1 * A2 * iB;
-    const int64_t o = plane * HW + (int64_t)py * W + px;
-    // S(m_x, m_xx, m_xy) with sx = m_xx - m_x^2 and sxy = m_xy - m_x m_y
-    amap[o] = 2.0f * my * (A2 - A1) * iB - 2.0f * mx * S * (1.0f / B1 - 1.0f / B2);
-    bmap[o] = -S / B2;
-    cmap[o] = 2.0f * A1 * iB;
+  float S_sum = 0.0f;
+#pragma unroll
+  for (int p = 0; p < kPP; ++p) {
+    const int px = blockIdx.x * kT + c, py = blockIdx.y * kT + r0 + p;
+    if (px < W && py < H) {
+      const float mx = m[p][0], my = m[p][1];
+      const float sx = m[p][2] - mx * mx, sy = m[p][3] - my * my, sxy = m[p][4] - mx * my;
+      const float A1 = 2.0f * mx * my + kC1, A2 = 2.0f * sxy + kC2;
+      const float B1 = mx * mx + my * my + kC1, B2 = sx + sy + kC2;
+      const float iB = 1.0f / (B1 * B2);
+      const float S = A1 * A2 * iB;
+      const int64_t o = plane * HW + (int64_t)py * W + px;
+      // S(m_x, m_xx, m_xy) with sx = m_xx - m_x^2 and sxy = m_xy - m_x m_y
+      amap[o] = 2.0f * my * (A2 - A1) * iB - 2.0f * mx * S * (1.0f / B1 - 1.0f / B2);
+      bmap[o] = -S / B2;
+      cmap[o] = 2.0f * A1 * iB;
+      S_sum += S;
+    }
   }
-  red[threadIdx.x] = S;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
-    __syncthreads();
-  }
+  const float tot = block_sum(S_sum, red);
   if (threadIdx.x == 0)
-    part[(plane * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+    part[(plane * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
 }
 
 // Backward: dl/dx = w1 sign(x - y) - ws ((G*a) + 2 x (G*b) + y (G*c)) with
@@ -122,7 +148,7 @@ __global__ void __launch_bounds__(256)
                float *__restrict__ dl, float *__restrict__ part) {
   __shared__ float s[3][kS][kS + 1];
   __shared__ float h[3][kS][kT + 1];
-  __shared__ float red[2][256];
+  __shared__ float red[2][256 / kWave];
   const int64_t HW = (int64_t)W * H;
   const int64_t plane = blockIdx.z;
   const int x0 = blockIdx.x * kT - kR, y0 = blockIdx.y * kT - kR;
@@ -144,40 +170,42 @@ __global__ void __launch_bounds__(256)
     h[2][r][c] = v2;
   }
   __syncthreads();
-  const int r = threadIdx.x / kT, c = threadIdx.x % kT;
-  float ga = 0.f, gb = 0.f, gc = 0.f;
+  const int c = threadIdx.x % kT, r0 = (threadIdx.x / kT) * kPP;
+  float gsum[kPP][3];
 #pragma unroll
-  for (int k = 0; k < 11; ++k) {
-    const float g = win.g[k];
-    ga = fmaf(g, h[0][r + k][c], ga);
-    gb = fmaf(g, h[1][r + k][c], gb);
-    gc = fmaf(g, h[2][r + k][c], gc);
+  for (int p = 0; p < kPP; ++p) gsum[p][0] = gsum[p][1] = gsum[p][2] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 11 + kPP - 1; ++k) {
+    const float h0 = h[0][r0 + k][c], h1 = h[1][r0 + k][c], h2 = h[2][r0 + k][c];
+#pragma unroll
+    for (int p = 0; p < kPP; ++p)
+      if (k - p >= 0 && k - p < 11) {
+        const float g = win.g[k - p];
+        gsum[p][0] = fmaf(g, h0, gsum[p][0]);
+        gsum[p][1] = fmaf(g, h1, gsum[p][1]);
+        gsum[p][2] = fmaf(g, h2, gsum[p][2]);
+      }
   }
-  const int px = blockIdx.x * kT + c, py = blockIdx.y * kT + r;
   float a1 = 0.0f, a2 = 0.0f;
-  if (px < W && py < H) {
-    const int64_t o = plane * HW + (int64_t)py * W + px;
-    const float xv = x[o], yv = y[o], d = xv - yv;
-    const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
-    dl[o] = w1 * sg - ws * (ga + 2.0f * xv * gb + yv * gc);
-    a1 = fabsf(d);
-    const float e = fminf(fmaxf(xv, 0.0f), 1.0f) - yv;
-    a2 = e * e;
-  }
-  red[0][threadIdx.x] = a1;
-  red[1][threadIdx.x] = a2;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if (threadIdx.x < k) {
-      red[0][threadIdx.x] += red[0][threadIdx.x + k];
-      red[1][threadIdx.x] += red[1][threadIdx.x + k];
+#pragma unroll
+  for (int p = 0; p < kPP; ++p) {
+    const int px = blockIdx.x * kT + c, py = blockIdx.y * kT + r0 + p;
+    if (px < W && py < H) {
+      const int64_t o = plane * HW + (int64_t)py * W + px;
+      const float xv = x[o], yv = y[o], d = xv - yv;
+      const float sg = d > 0.0f ? 1.0f : (d < 0.0f ? -1.0f : 0.0f);
+      dl[o] = w1 * sg - ws * (gsum[p][0] + 2.0f * xv * gsum[p][1] + yv * gsum[p][2]);
+      a1 += fabsf(d);
+      const float e = fminf(fmaxf(xv, 0.0f), 1.0f) - yv;
+      a2 += e * e;
     }
-    __syncthreads();
   }
+  const float t1 = block_sum(a1, red[0]);
+  const float t2 = block_sum(a2, red[1]);
   if (threadIdx.x == 0) {
     const int64_t b = (plane * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    part[2 * b] = red[0][0];
-    part[2 * b + 1] = red[1][0];
+    part[2 * b] = t1;
+    part[2 * b + 1] = t2;
   }
 }
 
@@ -204,15 +232,25 @@ __global__ void __launch_bounds__(256)
 }
 
 // out = sum of n partials (stride `step`, offset `off`) in float64, one block.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     k_sum_parts(const float *__restrict__ part, int64_t n, int step, int off,
                 double *__restrict__ out) {
-  __shared__ double red[256];
+  // thread t sums elements t, t + 1024, ... (eight loads in flight per
+  // step), then a fixed tree over the 1024 threads
+  __shared__ double red[1024];
   double a = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) a += part[i * step + off];
+  int64_t i = threadIdx.x;
+  for (; i + 7 * 1024 < n; i += 8 * 1024) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(i + u * 1024) * step + off];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a += v[u];
+  }
+  for (; i < n; i += 1024) a += part[i * step + off];
   red[threadIdx.x] = a;
   __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
+  for (int k = 512; k > 0; k >>= 1) {
     if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
@@ -260,19 +298,19 @@ void mapping_loss(dcgs_ctx *ctx, const float *rgb, const float *target, const fl
   hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, st, rgb, target, amap, bmap, cmap, W, H,
                      win, (float)(1.0 - lambda_s) * norm, (float)lambda_s * norm, dl_drgb, pL);
   DCGS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, pL, nb, 2, 0, stats);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, pL, nb, 2, 1, stats + 1);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, pS, nb, 1, 0, stats + 2);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, pL, nb, 2, 0, stats);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, pL, nb, 2, 1, stats + 1);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, pS, nb, 1, 0, stats + 2);
   DCGS_LAUNCH_CHECK();
   if (depth && depth_target) {
     hipLaunchKernelGGL(k_depth_l1, dim3(kDepthBlocks), dim3(256), 0, st, depth, depth_target,
                        (int64_t)n_views * HW, (float)(lambda_depth / (double)HW), dl_ddepth, pD);
     DCGS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, pD, (int64_t)kDepthBlocks, 1, 0,
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, pD, (int64_t)kDepthBlocks, 1, 0,
                        stats + 3);
     DCGS_LAUNCH_CHECK();
   } else {
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, st, pD, (int64_t)0, 1, 0, stats + 3);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, st, pD, (int64_t)0, 1, 0, stats + 3);
     DCGS_LAUNCH_CHECK();
   }
 }
