@@ -680,51 +680,51 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
-    uint32_t live = 0;
     uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
-    for (int k = 0; k < nb; ++k) {
-      uint32_t mk = 1u;
-      if constexpr (!kOneCell) {
-        mk = __builtin_amdgcn_readfirstlane(m_next);
-        m_next = sM[min(k + 1, BS - 1)];
-      }
-      // cells whose pixels are all saturated leave the batch; a wavefront
-      // with none left leaves it altogether
-      if ((k & 7) == 0) {
-        live = 0;
+    for (int k0 = 0; k0 < nb; k0 += 8) {
+      // every 8 records: cells whose pixels are all saturated leave the
+      // batch; a wavefront with none left leaves it altogether
+      uint32_t live = 0;
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) live |= (uint32_t)(__ballot(!done[j]) != 0) << j;
-        if (live == 0) break;
-      }
-      const uint32_t hit = cell.mine(mk) & live;
-      if (hit == 0) continue;  // no live cell of this wavefront meets the box
-      const float4 A = sA[k], B = sB[k], C = sC[k];
-      const Box bx = uniform_box(C);
-      // predicated rather than branched inside a cell: a lane that does not
-      // composite adds exact zeros, and the wavefront issues no mask
-      // bookkeeping.  Contraction is off in this kernel: every raster shape
-      // composites with the same roundings.
-      auto composite = [&](const int j) {
-        const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
-        const bool act = s.ok & !done[j];
-        const float a = act ? s.alpha : 0.0f;
-        const float Tn = T[j] * (1.0f - a);
-        const bool stop = act & (Tn < kTMin);
-        const bool comp = act & !stop;
-        const float w = comp ? a * T[j] : 0.0f;
-        c0[j] = __builtin_fmaf(B.z, w, c0[j]);
-        c1[j] = __builtin_fmaf(B.w, w, c1[j]);
-        c2[j] = __builtin_fmaf(C.x, w, c2[j]);
-        D[j] = __builtin_fmaf(C.y, w, D[j]);
-        T[j] = comp ? Tn : T[j];
-        last[j] = comp ? base + k : last[j];
-        done[j] = done[j] | stop;
-      };
-      // one cell at a time (straight-line code over all cells holds more
-      // registers and runs slower here)
+      for (int j = 0; j < PPT; ++j) live |= (uint32_t)(__ballot(!done[j]) != 0) << j;
+      if (live == 0) break;
+      const int k1 = min(k0 + 8, nb);
+      for (int k = k0; k < k1; ++k) {
+        uint32_t mk = 1u;
+        if constexpr (!kOneCell) {
+          mk = __builtin_amdgcn_readfirstlane(m_next);
+          m_next = sM[min(k + 1, BS - 1)];
+        }
+        const uint32_t hit = cell.mine(mk) & live;
+        if (hit == 0) continue;  // no live cell of this wavefront meets the box
+        const float4 A = sA[k], B = sB[k], C = sC[k];
+        const Box bx = uniform_box(C);
+        // predicated rather than branched inside a cell: a lane that does not
+        // composite adds exact zeros, and the wavefront issues no mask
+        // bookkeeping.  Contraction is off in this kernel: every raster shape
+        // composites with the same roundings.
+        auto composite = [&](const int j) {
+          const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
+          const bool act = s.ok & !done[j];
+          const float a = act ? s.alpha : 0.0f;
+          const float Tn = T[j] * (1.0f - a);
+          const bool stop = act & (Tn < kTMin);
+          const bool comp = act & !stop;
+          const float w = comp ? a * T[j] : 0.0f;
+          c0[j] = __builtin_fmaf(B.z, w, c0[j]);
+          c1[j] = __builtin_fmaf(B.w, w, c1[j]);
+          c2[j] = __builtin_fmaf(C.x, w, c2[j]);
+          D[j] = __builtin_fmaf(C.y, w, D[j]);
+          T[j] = comp ? Tn : T[j];
+          last[j] = comp ? base + k : last[j];
+          done[j] = done[j] | stop;
+        };
+        // one cell at a time (straight-line code over all cells holds more
+        // registers and runs slower here)
 #pragma unroll
-      for (int j = 0; j < PPT; ++j)
-        if (hit & (1u << j)) composite(j);
+        for (int j = 0; j < PPT; ++j)
+          if (hit & (1u << j)) composite(j);
+      }
     }
     n_live = 0;
 #pragma unroll
