@@ -914,81 +914,87 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
     __syncthreads();
     uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
-    for (int k = 0; k < nb; ++k) {
-      uint32_t mk = 1u;
-      if constexpr (!kOneCell) {
-        mk = __builtin_amdgcn_readfirstlane(m_next);
-        m_next = sM[min(k + 1, BS - 1)];
-      }
-      const int pos = end - 1 - k;
-      // cell j takes part if one of its pixels composited this position
-      // and the record's box meets it
+    for (int k0 = 0; k0 < nb; k0 += 8) {
+      // cell j takes part in a group of 8 positions if one of its pixels
+      // composited the group's deepest position or one behind it (a cell
+      // run for a position none of its pixels reached adds exact zeros)
+      const int deepest = end - 1 - min(k0 + 7, nb - 1);
       uint32_t alive = 0;
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) alive |= (uint32_t)(pos <= cell_last[j]) << j;
-      const uint32_t hit = cell.mine(mk) & alive;
-      if (hit == 0) {
-        if (lane < NC) red[wv][k][lane] = 0.0f;
-        continue;
-      }
-      const float4 A = sA[k], B = sB[k], C = sC[k];
-      const Box bx = uniform_box(C);
-      float v[16];
+      for (int j = 0; j < PPT; ++j) alive |= (uint32_t)(deepest <= cell_last[j]) << j;
+      const int k1 = min(k0 + 8, nb);
+      for (int k = k0; k < k1; ++k) {
+        uint32_t mk = 1u;
+        if constexpr (!kOneCell) {
+          mk = __builtin_amdgcn_readfirstlane(m_next);
+          m_next = sM[min(k + 1, BS - 1)];
+        }
+        const int pos = end - 1 - k;
+        // ... and the record's cell mask keeps it
+        const uint32_t hit = cell.mine(mk) & alive;
+        if (hit == 0) {
+          if (lane < NC) red[wv][k][lane] = 0.0f;
+          continue;
+        }
+        const float4 A = sA[k], B = sB[k], C = sC[k];
+        const Box bx = uniform_box(C);
+        float v[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) v[c] = 0.0f;
-      uint64_t contrib = 0;  // lanes that composited this record in some cell
-      // predicated rather than branched inside a cell: a lane whose pixel
-      // does not use this Gaussian runs with alpha = 0 (1 / (1 - 0) is
-      // exact), which leaves T and S unchanged and adds exact zeros to every
-      // term
-      auto adjoint = [&](const int j) {
-        const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
-        const bool act = s.ok & (pos <= last[j]);
-        contrib |= __ballot(act);
-        const float a = act ? s.alpha : 0.0f;
-        const float iom = __builtin_amdgcn_rcpf(1.0f - a);
-        const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
-        const float w = a * Tk;
-        v[6] += g0[j] * w;
-        v[7] += g1[j] * w;
-        v[8] += g2[j] * w;
-        v[9] += gd[j] * w;
-        // dL/dalpha = dL/dC . (c Tk - S / (1 - alpha)), S what lies behind
-        const float gc = g0[j] * B.z + g1[j] * B.w + g2[j] * C.x + gd[j] * C.y;
-        const float da = gc * Tk - GS[j] * iom;
-        GS[j] += gc * w;
-        T[j] = Tk;
-        // alpha not clamped: the opacity and the exponent receive gradient
-        const bool free_alpha = act & (B.y * s.G <= kAlphaMax);
-        const float gG = free_alpha ? s.G : 0.0f;
-        const float dp = free_alpha ? a * da : 0.0f;
-        v[5] += gG * da;
-        // the mean's gradient is linear in (sum dp dx, sum dp dy): the
-        // conic (scaled: Q00 dx + Q01 dy = kQ/2 (2 A.z dx + A.w dy)) is
-        // applied once per record after the reduction
-        v[0] += dp * s.dx;
-        v[1] += dp * s.dy;
-        // d power / d(Q00, Q01, Q11) = -(dx^2 / 2, dx dy, dy^2 / 2): the
-        // constant factors are applied after the reduction
-        v[2] += s.dx * s.dx * dp;
-        v[3] += s.dx * s.dy * dp;
-        v[4] += s.dy * s.dy * dp;
-      };
-      // every cell hit: one straight-line block the compiler can interleave
-      if (hit == (1u << PPT) - 1u) {
+        for (int c = 0; c < 16; ++c) v[c] = 0.0f;
+        uint64_t contrib = 0;  // lanes that composited this record in some cell
+        // predicated rather than branched inside a cell: a lane whose pixel
+        // does not use this Gaussian runs with alpha = 0 (1 / (1 - 0) is
+        // exact), which leaves T and S unchanged and adds exact zeros to every
+        // term
+        auto adjoint = [&](const int j) {
+          const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
+          const bool act = s.ok & (pos <= last[j]);
+          contrib |= __ballot(act);
+          const float a = act ? s.alpha : 0.0f;
+          const float iom = __builtin_amdgcn_rcpf(1.0f - a);
+          const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
+          const float w = a * Tk;
+          v[6] += g0[j] * w;
+          v[7] += g1[j] * w;
+          v[8] += g2[j] * w;
+          v[9] += gd[j] * w;
+          // dL/dalpha = dL/dC . (c Tk - S / (1 - alpha)), S what lies behind
+          const float gc = g0[j] * B.z + g1[j] * B.w + g2[j] * C.x + gd[j] * C.y;
+          const float da = gc * Tk - GS[j] * iom;
+          GS[j] += gc * w;
+          T[j] = Tk;
+          // alpha not clamped: the opacity and the exponent receive gradient
+          const bool free_alpha = act & (B.y * s.G <= kAlphaMax);
+          const float gG = free_alpha ? s.G : 0.0f;
+          const float dp = free_alpha ? a * da : 0.0f;
+          v[5] += gG * da;
+          // the mean's gradient is linear in (sum dp dx, sum dp dy): the
+          // conic (scaled: Q00 dx + Q01 dy = kQ/2 (2 A.z dx + A.w dy)) is
+          // applied once per record after the reduction
+          v[0] += dp * s.dx;
+          v[1] += dp * s.dy;
+          // d power / d(Q00, Q01, Q11) = -(dx^2 / 2, dx dy, dy^2 / 2): the
+          // constant factors are applied after the reduction
+          v[2] += s.dx * s.dx * dp;
+          v[3] += s.dx * s.dy * dp;
+          v[4] += s.dy * s.dy * dp;
+        };
+        // every cell hit: one straight-line block the compiler can interleave
+        if (hit == (1u << PPT) - 1u) {
 #pragma unroll
-        for (int j = 0; j < PPT; ++j) adjoint(j);
-      } else {
+          for (int j = 0; j < PPT; ++j) adjoint(j);
+        } else {
 #pragma unroll
-        for (int j = 0; j < PPT; ++j)
-          if (hit & (1u << j)) adjoint(j);
-      }
-      if (contrib != 0) {
-        const float r = wave_reduce10(v);
-        const int c = bitrev4(lane & 15);
-        if (lane < 16 && c < NC) red[wv][k][c] = r;
-      } else if (lane < NC) {
-        red[wv][k][lane] = 0.0f;
+          for (int j = 0; j < PPT; ++j)
+            if (hit & (1u << j)) adjoint(j);
+        }
+        if (contrib != 0) {
+          const float r = wave_reduce10(v);
+          const int c = bitrev4(lane & 15);
+          if (lane < 16 && c < NC) red[wv][k][c] = r;
+        } else if (lane < NC) {
+          red[wv][k][lane] = 0.0f;
+        }
       }
     }
     __syncthreads();
