@@ -451,11 +451,23 @@ __global__ void k_emit(const uint32_t *__restrict__ rank_of, const uint32_t *__r
   const int n_rect = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
   const uint64_t m = tmask[g];
   uint32_t k = base;
-  int idx = 0;
-  for (int ty = ty0; ty <= ty1; ++ty)
-    for (int tx = tx0; tx <= tx1; ++tx, ++idx)
-      if (tile_kept(m, n_rect, idx))
+  const int wc = tx1 - tx0 + 1;
+  if (n_rect > 64) {  // every tile kept
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx)
         pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | (uint32_t)g;
+    return;
+  }
+  // the kept tiles only: per row of the rectangle, its bits of the mask,
+  // lowest first (row-major order, as the slots are laid out)
+  const uint64_t row_bits = wc >= 64 ? ~uint64_t(0) : ((uint64_t(1) << wc) - 1);
+  uint64_t mm = m;
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    const uint32_t row = view_base + (uint32_t)(ty * tiles_x + tx0);
+    for (uint64_t rb = mm & row_bits; rb != 0; rb &= rb - 1)
+      pairs[k++] = ((uint64_t)(row + (uint32_t)__builtin_ctzll(rb)) << 32) | (uint32_t)g;
+    mm = wc >= 64 ? 0 : (mm >> wc);
+  }
 }
 
 __global__ void k_ranges(const uint64_t *__restrict__ pairs, const int64_t *__restrict__ cnt,
