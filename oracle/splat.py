@@ -24,15 +24,8 @@ Pixel box: r^2 = 2 ln(255 o), e_x = sqrt(r^2 Sigma2_xx), e_y likewise; columns
     ceil(u - e_x - 0.5) .. floor(u + e_x - 0.5) clipped to the image, rows
     likewise.  Outside this box alpha < 1/255 exactly, so the image does not
     depend on the tile size.
-Tiles: of the tiles the box touches, a Gaussian is binned to those whose
-    rectangle of pixel centres inside the box meets the ellipse
-    d^T Q d <= tau' with tau' = (tau + 1e-3 (1 + tau)) / (1 - 16 2^-24 kappa),
-    tau = 2 ln(255 o) (alpha >= 1/255 exactly inside d^T Q d <= tau) and
-    kappa = 2 (Q00 + Q11) / lambda_min(Q), an allowance for the float32
-    evaluation of the samples; all touched tiles when they are more than 64
-    or 16 2^-24 kappa >= 1/2.  A Gaussian left with no tile is culled.  A
-    dropped tile holds no pixel centre with alpha >= 1/255, so neither the
-    image nor the gradients change.
+Tiles: a drawn Gaussian is binned to every tile of the rectangle of tiles
+    its pixel box touches (floor(i/TW), floor(j/TH) of the box corners).
 Order: by the float32 rounding of Z (its bit pattern), then by index.
 Compositing at pixel p, over the Gaussians whose box holds p, front to back:
     power = -1/2 d^T Q d with d = p - (u, v); skip if power > 0;
@@ -49,7 +42,8 @@ form, zero opacity giving the background exactly, two-Gaussian compositing,
 the 13-deep stack at alpha = 1/2, the 0.99 clamp, the projection Jacobian
 against finite differences of the projection, quaternion rotation against
 Hamilton products, brute-force box containment of every alpha >= 1/255
-sample, keys and ranges against a linear scan, and central finite
+sample, keys and ranges against a linear scan, the per-pair alpha maximum
+against closed forms and per-pixel evaluation, and central finite
 differences of the forward for every parameter row.
 """
 from __future__ import annotations
@@ -96,8 +90,6 @@ class Records:
     tile_rect: np.ndarray         # int64 [n, 4]: tx0, tx1, ty0, ty1
     raw_rgb_margin: np.ndarray    # |colour before clamp| (gradient switch)
     key_tie: np.ndarray           # bool: some integer decision within 1e-13 of a flip
-    tile_keep: np.ndarray         # bool per touched tile of the drawn Gaussians, in
-                                  # index order, tiles of a rectangle row-major
     width: int
     height: int
     tile: tuple
@@ -170,14 +162,6 @@ def preprocess(params: np.ndarray, sh_degree: int, cam: dict, tile=(16, 16),
         box = np.where(culled[:, None], 0, box).astype(np.int64)
         TW, TH = tile
         rect = np.stack([box[:, 0] // TW, box[:, 1] // TW, box[:, 2] // TH, box[:, 3] // TH], 1)
-        bd = b.detach().numpy()
-        keep, n_keep, tile_tie = tile_keep(ud, vd, ad, bd, cd, dd, od, box, rect, culled, TW, TH)
-        # a Gaussian left without a tile draws nothing
-        dropped = ~culled & (n_keep == 0)
-        keep = keep[np.repeat(~dropped[~culled], _rect_count(rect[~culled]))]
-        culled = culled | dropped
-        box = np.where(culled[:, None], 0, box)
-        rect = np.stack([box[:, 0] // TW, box[:, 1] // TW, box[:, 2] // TH, box[:, 3] // TH], 1)
         zf = Zd.astype(np.float32)
         zbits = zf.view(np.int32).astype(np.int64)
 
@@ -198,83 +182,54 @@ def preprocess(params: np.ndarray, sh_degree: int, cam: dict, tile=(16, 16),
             m = np.minimum.reduce([m_near, m_guard, m_opac, m_box])
             ulp = np.abs(np.nextafter(zf, np.float32(np.inf)).astype(np.float64) - zf.astype(np.float64))
             mz = np.where(culled, inf, np.abs(np.abs(Zd - zf.astype(np.float64)) - 0.5 * ulp) / np.abs(Zd))
-        key_tie = (m < 1e-13) | (mz < 1e-13) | tile_tie
+        key_tie = (m < 1e-13) | (mz < 1e-13)
         rgb_margin = np.abs(raw.numpy()).min(axis=1)
 
     # The composited depth is its own graph node, so its gradient is the
     # depth-channel term alone (Z also reaches u, v and the conic).
     return Records(params=P, u=u, v=v, conic=conic, opacity=opac, rgb=rgb, z=Z.clone(), zbits=zbits,
                    culled=culled, box=box, tile_rect=rect, raw_rgb_margin=rgb_margin,
-                   key_tie=key_tie, tile_keep=keep, width=W, height=H, tile=tuple(tile))
+                   key_tie=key_tie, width=W, height=H, tile=tuple(tile))
 
 
-def _rect_count(r: np.ndarray) -> np.ndarray:
-    return (r[:, 1] - r[:, 0] + 1) * (r[:, 3] - r[:, 2] + 1)
-
-
-def rect_min(q00, q01, q11, x0, x1, y0, y1) -> np.ndarray:
-    """min of f(x, y) = q00 x^2 + 2 q01 x y + q11 y^2 (positive definite) over
-    the rectangle [x0, x1] x [y0, y1]: 0 when it holds the origin, else the
-    smallest value along the four edges, each at the clamped minimiser of f
-    restricted to its line."""
-    def f(x, y):
-        return q00 * x * x + 2.0 * q01 * x * y + q11 * y * y
-    best = np.full(np.shape(x0), np.inf)
-    for xe in (x0, x1):
-        best = np.minimum(best, f(xe, np.clip(-q01 * xe / q11, y0, y1)))
-    for ye in (y0, y1):
-        best = np.minimum(best, f(np.clip(-q01 * ye / q00, x0, x1), ye))
-    inside = (x0 <= 0) & (x1 >= 0) & (y0 <= 0) & (y1 >= 0)
-    return np.where(inside, 0.0, best)
-
-
-def tile_keep(u, v, a, b, c, det, o, box, rect, culled, TW, TH):
-    """Tile binning by the ellipse (see the module header): per touched tile
-    of each drawn Gaussian (index order, tiles row-major) whether it is kept;
-    kept tiles per Gaussian; Gaussians with a decision within 1e-9 of a
-    flip."""
-    n = culled.size
-    vis = np.nonzero(~culled)[0]
-    nrect = _rect_count(rect[vis])
-    g = np.repeat(vis, nrect)
-    loc = np.arange(nrect.sum()) - np.repeat(np.cumsum(nrect) - nrect, nrect)
-    w = np.repeat(rect[vis, 1] - rect[vis, 0] + 1, nrect)
-    tx = rect[g, 0] + loc % w
-    ty = rect[g, 2] + loc // w
-    x0 = np.maximum(tx * TW, box[g, 0]) + 0.5 - u[g]
-    x1 = np.minimum(tx * TW + TW - 1, box[g, 1]) + 0.5 - u[g]
-    y0 = np.maximum(ty * TH, box[g, 2]) + 0.5 - v[g]
-    y1 = np.minimum(ty * TH + TH - 1, box[g, 3]) + 0.5 - v[g]
-    with np.errstate(divide="ignore", invalid="ignore"):
-        q00, q01, q11 = c / det, -b / det, a / det
-        m = rect_min(q00[g], q01[g], q11[g], x0, x1, y0, y1)
-        half = 0.5 * (a - c)
-        lam = 0.5 * (a + c) + np.sqrt(half * half + b * b)   # largest eigenvalue of Sigma2
-        kappa = 2.0 * (a + c) / det * lam
-        shrink = 1.0 - 16.0 * 2.0 ** -24 * kappa
-        tau = 2.0 * np.log(255.0 * o)
-        lim = (tau + 1e-3 * (1.0 + tau)) / shrink
-    every = np.zeros(n, bool)
-    every[vis] = (nrect > 64) | ~(shrink[vis] > 0.5)
-    keep = np.repeat(every[vis], nrect) | (m <= lim[g])
-    tie_pair = ~np.repeat(every[vis], nrect) & (np.abs(m - lim[g]) <= 1e-9 * (1.0 + np.abs(lim[g])))
-    tie = np.zeros(n, bool)
-    tie[vis] = np.abs(shrink[vis] - 0.5) <= 1e-12
-    np.logical_or.at(tie, g[tie_pair], True)
-    n_keep = np.zeros(n, np.int64)
-    np.add.at(n_keep, g, keep.astype(np.int64))
-    return keep, n_keep, tie
+def pair_alpha_max(rec: Records, g: np.ndarray, tx: np.ndarray, ty: np.ndarray) -> np.ndarray:
+    """For (Gaussian g, tile (tx, ty)) pairs: the largest float64 alpha
+    before the 0.99 clamp, o exp(-1/2 d^T Q d), over the pixel centres that
+    lie both in the tile and in the Gaussian's pixel box (brute force over
+    every such centre; -inf where the two share no pixel).  A pair whose
+    value is below 1/255 adds nothing to any pixel of its tile."""
+    TW, TH = rec.tile
+    g = np.asarray(g, np.int64)
+    tx = np.asarray(tx, np.int64)
+    ty = np.asarray(ty, np.int64)
+    u = rec.u.detach().numpy()[g]
+    v = rec.v.detach().numpy()[g]
+    Q = rec.conic.detach().numpy()[g]
+    o = rec.opacity.detach().numpy()[g]
+    box = rec.box[g]
+    best = np.full(g.shape, -np.inf)
+    for oy in range(TH):
+        j = ty * TH + oy
+        in_y = (j >= box[:, 2]) & (j <= box[:, 3])
+        dy = j + 0.5 - v
+        for ox in range(TW):
+            i = tx * TW + ox
+            ok = in_y & (i >= box[:, 0]) & (i <= box[:, 1])
+            dx = i + 0.5 - u
+            a = o * np.exp(-0.5 * (Q[:, 0] * dx * dx + 2.0 * Q[:, 1] * dx * dy + Q[:, 2] * dy * dy))
+            best = np.where(ok, np.maximum(best, a), best)
+    return best
 
 
 def tile_keys(rec: Records, view: int = 0, tiles_before: int = 0) -> dict:
     """Keys (tile << 32 | float32 depth bits) and values (Gaussian index) for
-    every (Gaussian, touched tile), emitted by index then tiles row-major;
-    then a stable sort and per-tile [start, end) ranges.  `tiles_before` is
-    the global tile id of this view's tile 0."""
+    every (drawn Gaussian, tile of its rectangle), emitted by index then
+    tiles row-major; then a stable sort and per-tile [start, end) ranges.
+    `tiles_before` is the global tile id of this view's tile 0.  Also
+    returns each pair's Gaussian and tile coordinates in sorted order."""
     TW, TH = rec.tile
     tx_n = -(-rec.width // TW)
     ty_n = -(-rec.height // TH)
-    keys, vals = [], []
     vis = np.nonzero(~rec.culled)[0]
     r = rec.tile_rect
     wcount = r[vis, 1] - r[vis, 0] + 1
@@ -286,8 +241,6 @@ def tile_keys(rec: Records, view: int = 0, tiles_before: int = 0) -> dict:
     wrep = np.repeat(wcount, cnt)
     tx = r[g, 0] + local % wrep
     ty = r[g, 2] + local // wrep
-    kp = rec.tile_keep
-    g, tx, ty = g[kp], tx[kp], ty[kp]
     tile_id = tiles_before + ty * tx_n + tx
     keys = (tile_id.astype(np.uint64) << np.uint64(32)) | rec.zbits[g].astype(np.uint64)
     vals = g.astype(np.int64)
@@ -300,7 +253,7 @@ def tile_keys(rec: Records, view: int = 0, tiles_before: int = 0) -> dict:
     counts = np.zeros(rec.culled.size, np.int64)
     np.add.at(counts, g, 1)
     return dict(keys=ks, values=vs, ranges=np.stack([lo, hi], 1), counts=counts,
-                tiles_x=tx_n, tiles_y=ty_n)
+                tiles_x=tx_n, tiles_y=ty_n, tx=tx[order], ty=ty[order])
 
 
 @dataclass

@@ -57,3 +57,63 @@ def assert_grad_close(g, ref, what, mask=None):
         idx = np.argwhere(bad)[:5]
         raise AssertionError(f"{what}: {bad.sum()} of {bad.size} entries off; first {idx.tolist()} "
                              f"gpu={g[tuple(idx.T)]} ref={ref[tuple(idx.T)]}")
+
+
+def check_pruned_keys(gk, gv, granges, gcounts, rec, kr, tiles_before=0, tie=None, what=""):
+    """The kernel's sorted (key, value) list against the oracle's plain list
+    (every tile of each drawn Gaussian's rectangle).  The kernel may leave
+    out (Gaussian, tile) pairs it has shown to hold no sample; the check:
+      - the kernel list equals the oracle list with the left-out pairs
+        removed, bit for bit and in the same order;
+      - every left-out pair, including those of a Gaussian left with no tile
+        at all, holds no pixel centre with alpha >= 1/255 (float64, brute
+        force over the tile's pixels in the box);
+      - per-tile ranges equal those of the oracle's list without the
+        left-out pairs, and per-Gaussian counts its pair counts.
+    Tiles touched by a Gaussian whose key sits within rounding of a decision
+    (`tie`) are left out of the comparison.  Returns (pairs left out,
+    Gaussians left with no tile)."""
+    from oracle import splat as osp
+    gk = np.asarray(gk).view(np.uint64)
+    gv = np.asarray(gv).astype(np.int64)
+    NT = kr["ranges"].shape[0]
+    tb = np.uint64(tiles_before)
+    t_o = ((kr["keys"] >> np.uint64(32)) - tb).astype(np.int64)
+    t_k = ((gk >> np.uint64(32)) - tb).astype(np.int64)
+    assert ((t_k >= 0) & (t_k < NT)).all(), what
+    bad = np.zeros(NT, bool)
+    tie = np.zeros(rec.culled.size, bool) if tie is None else tie
+    for gi in np.nonzero(tie & ~rec.culled)[0]:
+        t = rec.tile_rect[gi]
+        for ty in range(t[2], t[3] + 1):
+            bad[ty * kr["tiles_x"] + t[0]: ty * kr["tiles_x"] + t[1] + 1] = True
+    id_o = kr["values"] * NT + t_o
+    id_k = gv * NT + t_k
+    kept = np.isin(id_o, id_k)
+    ok_o, ok_k = ~bad[t_o], ~bad[t_k]
+    assert np.array_equal(gk[ok_k], kr["keys"][kept & ok_o]), f"{what}: keys differ"
+    assert np.array_equal(gv[ok_k], kr["values"][kept & ok_o]), f"{what}: values differ"
+    assert np.isin(id_k[ok_k], id_o).all(), f"{what}: pair outside the oracle's list"
+    drop = ~kept & ok_o
+    if drop.any():
+        amax = osp.pair_alpha_max(rec, kr["values"][drop], kr["tx"][drop], kr["ty"][drop])
+        assert (amax < 1.0 / 255.0).all(), (
+            f"{what}: {(amax >= 1 / 255).sum()} left-out pairs hold a sample, largest alpha {amax.max()}")
+    g_lo = np.asarray(granges)[:, 0].astype(np.int64)
+    g_hi = np.asarray(granges)[:, 1].astype(np.int64)
+    all_t = np.arange(NT)
+    if not bad.any():
+        t_kept = t_o[kept]
+        assert (g_lo == np.searchsorted(t_kept, all_t, "left")).all(), f"{what}: range starts"
+        assert (g_hi == np.searchsorted(t_kept, all_t, "right")).all(), f"{what}: range ends"
+    else:
+        n_kept = np.bincount(t_o[kept], minlength=NT)
+        assert ((g_hi - g_lo)[~bad] == n_kept[~bad]).all(), f"{what}: range lengths"
+        assert (g_lo == np.searchsorted(t_k, all_t, "left")).all()
+        assert (g_hi == np.searchsorted(t_k, all_t, "right")).all()
+    n = rec.culled.size
+    cnt = np.bincount(kr["values"][kept], minlength=n)
+    ng = ~tie
+    assert (np.asarray(gcounts)[:n][ng] == cnt[ng]).all(), f"{what}: per-Gaussian counts"
+    whole = ~rec.culled & (kr["counts"] > 0) & (cnt == 0) & ng
+    return int(drop.sum()), int(whole.sum())

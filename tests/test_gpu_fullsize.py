@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_helpers import IMG_TOL, assert_grad_close, flagged_pixels
+from gpu_helpers import IMG_TOL, assert_grad_close, check_pruned_keys, flagged_pixels
 from oracle import chunks as oc
 from oracle import splat as osp
 from paper_2511_23030_amd import dcgs as D
@@ -49,20 +49,11 @@ def test_headline_keyframe(ctx):
     kr = osp.tile_keys(rec)
     tie = rec.key_tie
     assert tie.sum() < 1e-4 * n
-    bad_tiles = np.zeros(kr["ranges"].shape[0], bool)
-    for gi in np.nonzero(tie)[0]:
-        t = rec.tile_rect[gi]
-        for ty in range(t[2], t[3] + 1):
-            bad_tiles[ty * kr["tiles_x"] + t[0]: ty * kr["tiles_x"] + t[1] + 1] = True
-    gk = ex["keys"].cpu().numpy().view(np.uint64)
-    gv = ex["values"].cpu().numpy()
-    gr = ex["ranges"].cpu().numpy()
-    assert gk.size == kr["keys"].size
-    for t in np.nonzero(~bad_tiles)[0]:
-        lo, hi = kr["ranges"][t]
-        glo, ghi = gr[t]
-        assert (glo, ghi) == (lo, hi) or bad_tiles[:t].any()
-        assert (gk[glo:ghi] == kr["keys"][lo:hi]).all() and (gv[glo:ghi] == kr["values"][lo:hi]).all()
+    dropped, whole = check_pruned_keys(ex["keys"].cpu().numpy(), ex["values"].cpu().numpy(),
+                                       ex["ranges"].cpu().numpy(), ex["counts"].cpu().numpy(),
+                                       rec, kr, tie=tie, what="indoor keyframe")
+    print(f"  {kr['keys'].size} oracle pairs, {dropped} left out as empty, {whole} Gaussians "
+          f"left with no tile, {tie.sum()} key ties", flush=True)
     print("case fullsize: keys and ranges", flush=True)
 
     rgb, depth, Tg = loop.rgb.cpu().numpy(), loop.depth.cpu().numpy(), T.cpu().numpy()

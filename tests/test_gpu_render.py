@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 
 import scenegen
-from gpu_helpers import (IMG_TOL, SHAPES, assert_grad_close, flagged_pixels, gpu_render)
+from gpu_helpers import (IMG_TOL, SHAPES, assert_grad_close, check_pruned_keys,
+                         flagged_pixels, gpu_render)
 from oracle import splat as osp
 from paper_2511_23030_amd import dcgs as D
 
@@ -31,14 +32,16 @@ def test_keys_ranges_records(ctx, size, tile):
     rec = osp.preprocess(sc["params"], 0, cam, tile)
     kr = osp.tile_keys(rec)
     assert not rec.key_tie.any()
-    assert (g["counts"] == kr["counts"]).all()
-    vis = ~rec.culled
-    assert ((g["counts"] == 0) == rec.culled).all()
+    dropped, whole = check_pruned_keys(g["keys"], g["values"], g["ranges"], g["counts"], rec, kr,
+                                       what=f"size={size} tile={tile}")
+    print(f"  {kr['keys'].size} oracle pairs, {dropped} left out as empty, "
+          f"{whole} Gaussians left with no tile", flush=True)
+    assert g["n_pairs"] == kr["keys"].size - dropped
+    # records of the Gaussians the kernel draws; one it leaves with no tile
+    # draws nothing (all of its pairs were shown empty above)
+    vis = ~rec.culled & (g["counts"] > 0)
+    assert ((g["counts"] > 0) <= ~rec.culled).all()
     assert (g["box"].T[vis] == rec.box[vis]).all()
-    assert g["n_pairs"] == kr["keys"].size
-    assert (g["keys"].view(np.uint64) == kr["keys"]).all()
-    assert (g["values"] == kr["values"]).all()
-    assert (g["ranges"] == kr["ranges"]).all()
     r = g["records"]
     u = rec.u.detach().numpy()[vis]
     v = rec.v.detach().numpy()[vis]
@@ -201,20 +204,10 @@ def test_keys_rotated_camera_sh3(ctx):
     kr = osp.tile_keys(rec)
     tie = rec.key_tie
     assert tie.sum() <= 10
-    ok = ~tie & ~rec.culled
-    assert (g["counts"][ok] == kr["counts"][ok]).all()
     zg = g["records"][9].astype(np.float32).view(np.int32).astype(np.int64)
-    assert (np.abs(zg[tie] - rec.zbits[tie]) <= 1).all()
-    bad_tiles = set()
-    for gi in np.nonzero(tie)[0]:
-        t = rec.tile_rect[gi]
-        for ty in range(t[2], t[3] + 1):
-            for tx in range(t[0], t[1] + 1):
-                bad_tiles.add(ty * kr["tiles_x"] + tx)
-    for t in range(kr["ranges"].shape[0]):
-        if t in bad_tiles:
-            continue
-        lo, hi = kr["ranges"][t]
-        glo, ghi = g["ranges"][t]
-        assert (g["keys"][glo:ghi].view(np.uint64) == kr["keys"][lo:hi]).all()
-        assert (g["values"][glo:ghi] == kr["values"][lo:hi]).all()
+    drawn = g["counts"] > 0
+    assert (np.abs(zg[tie & drawn] - rec.zbits[tie & drawn]) <= 1).all()
+    dropped, whole = check_pruned_keys(g["keys"], g["values"], g["ranges"], g["counts"], rec, kr,
+                                       tie=tie, what="rotated camera SH3")
+    print(f"  {kr['keys'].size} oracle pairs, {dropped} left out as empty, {whole} Gaussians "
+          f"left with no tile, {tie.sum()} key ties", flush=True)

@@ -177,19 +177,14 @@ def test_box_holds_every_visible_sample():
         assert len(ii) > 0
 
 
-def _kept_tiles(rec):
-    """{(g, tx, ty)} of the tiles the binning keeps, from rec.tile_keep."""
-    out, k = set(), 0
-    for g in range(rec.culled.size):
-        if rec.culled[g]:
-            continue
+def _rect_tiles(rec):
+    """{(g, tx, ty)} of every tile of every drawn Gaussian's tile rectangle."""
+    out = set()
+    for g in np.nonzero(~rec.culled)[0]:
         tx0, tx1, ty0, ty1 = rec.tile_rect[g]
         for ty in range(ty0, ty1 + 1):
             for tx in range(tx0, tx1 + 1):
-                if rec.tile_keep[k]:
-                    out.add((g, tx, ty))
-                k += 1
-    assert k == rec.tile_keep.size
+                out.add((g, tx, ty))
     return out
 
 
@@ -198,81 +193,96 @@ def test_keys_and_ranges_linear_scan(tile):
     sc = scenegen.tiny_scene(n=400, seed=6, width=70, height=50, focal=60.0)
     rec = osp.preprocess(sc["params"], 0, sc["camera"], tile=tile)
     kr = osp.tile_keys(rec)
-    kept = _kept_tiles(rec)
+    pairs = _rect_tiles(rec)
     nt = kr["tiles_x"] * kr["tiles_y"]
     for t in range(nt):
         tx, ty = t % kr["tiles_x"], t // kr["tiles_x"]
-        lst = [g for g in range(400) if (g, tx, ty) in kept]
+        lst = [g for g in range(400) if (g, tx, ty) in pairs]
         lst.sort(key=lambda g: (rec.zbits[g], g))
         lo, hi = kr["ranges"][t]
         assert list(kr["values"][lo:hi]) == lst
         assert all(int(k) >> 32 == t for k in kr["keys"][lo:hi])
-    assert kr["counts"].sum() == len(kept) == kr["keys"].size
+        assert (kr["tx"][lo:hi] == tx).all() and (kr["ty"][lo:hi] == ty).all()
+    assert kr["counts"].sum() == len(pairs) == kr["keys"].size
 
 
-def test_rect_min_against_a_bounded_minimiser():
-    from scipy.optimize import minimize
-    rng = np.random.default_rng(11)
-    for _ in range(200):
-        L = rng.normal(size=(2, 2))
-        Q = L @ L.T + 0.05 * np.eye(2)
-        x0, y0 = rng.uniform(-6, 6, 2)
-        x1, y1 = x0 + rng.uniform(0, 8), y0 + rng.uniform(0, 8)
-        got = osp.rect_min(Q[0, 0], Q[0, 1], Q[1, 1], x0, x1, y0, y1)
-        res = minimize(lambda d: d @ Q @ d, [0.5 * (x0 + x1), 0.5 * (y0 + y1)],
-                       jac=lambda d: 2 * Q @ d, bounds=[(x0, x1), (y0, y1)], method="L-BFGS-B",
-                       options=dict(ftol=1e-15, gtol=1e-12))
-        assert abs(got - res.fun) <= 1e-7 * max(1.0, res.fun)
-        # and no sampled point of the rectangle lies below it
-        xs, ys = np.meshgrid(np.linspace(x0, x1, 41), np.linspace(y0, y1, 41))
-        f = Q[0, 0] * xs * xs + 2 * Q[0, 1] * xs * ys + Q[1, 1] * ys * ys
-        assert f.min() >= got - 1e-12 * max(1.0, f.min())
-
-
-def test_binning_keeps_every_tile_holding_a_sample_and_drops_some():
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_every_alpha_sample_lies_in_a_binned_tile(tile):
+    """Brute force over every pixel of the image: a (pixel, Gaussian) sample
+    with alpha >= 1/255 lies in one of the Gaussian's binned tiles."""
     sc = scenegen.tiny_scene(n=3000, seed=4)
     cam = sc["camera"]
-    rec = osp.preprocess(sc["params"], 0, cam, (16, 16))
-    kept = _kept_tiles(rec)
+    rec = osp.preprocess(sc["params"], 0, cam, tile)
+    pairs = _rect_tiles(rec)
     W, H = cam["width"], cam["height"]
     px, py = pixel_grid(W, H)
     u, v = rec.u.detach().numpy(), rec.v.detach().numpy()
     Q, o = rec.conic.detach().numpy(), rec.opacity.detach().numpy()
-    dropped = 0
     for g in np.nonzero(~rec.culled)[0][:400]:
         dx, dy = px - u[g], py - v[g]
         a = o[g] * np.exp(-0.5 * (Q[g, 0] * dx * dx + Q[g, 2] * dy * dy) - Q[g, 1] * dx * dy)
         jj, ii = np.nonzero(a >= 1 / 255)
-        for tx, ty in set(zip(ii // 16, jj // 16)):
-            assert (g, tx, ty) in kept
-        tx0, tx1, ty0, ty1 = rec.tile_rect[g]
-        dropped += (tx1 - tx0 + 1) * (ty1 - ty0 + 1) - sum(1 for t in kept if t[0] == g)
-    assert dropped > 0
+        for tx, ty in set(zip(ii // tile[0], jj // tile[1])):
+            assert (g, tx, ty) in pairs
 
 
-def test_binning_drops_the_far_corner_of_a_thin_diagonal_gaussian():
-    # a long thin Gaussian along the image diagonal: its box spans 3 x 3
-    # tiles, the two off-diagonal corner tiles miss the ellipse
-    cam = scenegen.look_camera([0.0, 0.0, 0.0], 0.0, 0.0, 100.0, 100.0, 96, 96, 0.2, 50.0)
-    P = np.zeros((14, 1))
-    P[0:3, 0] = (-np.asarray(cam["R"]).T @ np.asarray(cam["t"])) + np.asarray(cam["R"]).T @ [0, 0, 3.0]
-    P[3:6, 0] = np.log([0.6, 0.01, 0.01])
-    ang = np.pi / 4
-    Rc = np.asarray(cam["R"], np.float64)
-    Rz = np.array([[np.cos(ang), -np.sin(ang), 0], [np.sin(ang), np.cos(ang), 0], [0, 0, 1]])
-    xyzw = Rotation.from_matrix(Rc.T @ Rz).as_quat()   # long axis along the screen diagonal
-    P[6:10, 0] = [xyzw[3], xyzw[0], xyzw[1], xyzw[2]]
-    P[10, 0] = 4.0
-    rec = osp.preprocess(P, 0, cam, (16, 16))
-    assert not rec.culled[0]
-    tx0, tx1, ty0, ty1 = rec.tile_rect[0]
-    assert tx1 - tx0 >= 2 and ty1 - ty0 >= 2
-    kept = _kept_tiles(rec)
-    # the long axis runs along one screen diagonal: that pair of opposite
-    # corner tiles is kept, the other pair dropped
-    corners = [(tx0, ty0), (tx1, ty1), (tx1, ty0), (tx0, ty1)]
-    k = [(0, tx, ty) in kept for tx, ty in corners]
-    assert k[0] == k[1] and k[2] == k[3] and k[0] != k[2], k
+def test_pair_alpha_max_isotropic_closed_form():
+    """One isotropic Gaussian at u = 32.3, v = 24.2 (continuous pixel
+    coordinates) under 8x8 tiles: the largest alpha of a tile is at its pixel
+    centre nearest to (u, v), o exp(-r^2 / (2 var)) with var = (f s/Z)^2 + 0.3;
+    a tile the box misses reports -inf."""
+    Z, s, logit = 3.0, 0.08, 1.0
+    u0, v0 = 32.3, 24.2
+    # on the optical axis (J = diag(f/Z, f/Z) exactly), principal point at (u0, v0)
+    cam = scenegen.camera(np.eye(3), np.zeros(3), 50.0, 50.0, u0, v0, 64, 48)
+    P = make_params([[0.0, 0.0, Z]], [math.log(s)] * 3, [1, 0, 0, 0], logit, [0.5, 0.5, 0.5])
+    rec = osp.preprocess(P, 0, cam, (8, 8))
+    o = 1 / (1 + math.exp(-logit))
+    var = (50.0 * s / Z) ** 2 + 0.3
+    # tile (4, 3) holds pixel (32, 24), centre (32.5, 24.5); the tile to its
+    # left ends at column 31 (centre 31.5); the one above ends at row 23
+    cases = {(4, 3): (0.2, 0.3), (3, 3): (0.8, 0.3), (4, 2): (0.2, 0.7), (3, 2): (0.8, 0.7),
+             (5, 3): (8.2, 0.3)}
+    g = np.zeros(len(cases), np.int64)
+    tx = np.array([c[0] for c in cases])
+    ty = np.array([c[1] for c in cases])
+    got = osp.pair_alpha_max(rec, g, tx, ty)
+    for k, (dx, dy) in enumerate(cases.values()):
+        exp = o * math.exp(-0.5 * (dx * dx + dy * dy) / var)
+        i0, i1, j0, j1 = rec.box[0]
+        in_box = (tx[k] * 8 + 7 >= i0) and (tx[k] * 8 <= i1) and (ty[k] * 8 + 7 >= j0) and (ty[k] * 8 <= j1)
+        if in_box:
+            assert abs(got[k] - exp) <= 1e-12, (k, got[k], exp)
+        else:
+            assert got[k] == -np.inf
+    # the far tile (5, 3) lies beyond the box of this small Gaussian
+    assert got[4] == -np.inf and rec.box[0][1] < 40
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_pair_alpha_max_against_one_gaussian_renders(seed):
+    """Each Gaussian composited alone: its transmittance is 1 - alpha where it
+    draws and 1 elsewhere, so over a tile the largest 1 - T equals the pair's
+    alpha maximum (clamped at 0.99) when that reaches 1/255, and the tile is
+    untouched (T = 1) when it does not."""
+    sc = scenegen.tiny_scene(n=60, seed=30 + seed, width=64, height=48, focal=50.0)
+    cam = sc["camera"]
+    rec = osp.preprocess(sc["params"], 0, cam, (8, 8))
+    kr = osp.tile_keys(rec)
+    got = osp.pair_alpha_max(rec, kr["values"], kr["tx"], kr["ty"])
+    assert (got > -np.inf).all()            # every rectangle tile meets the box
+    below = 0
+    for k, g in enumerate(kr["values"]):
+        one = osp.preprocess(sc["params"][:, [g]], 0, cam, (8, 8))
+        img = osp.composite(one, np.zeros(3))
+        tx, ty = kr["tx"][k], kr["ty"][k]
+        Tt = img.T.detach().numpy()[ty * 8:ty * 8 + 8, tx * 8:tx * 8 + 8]
+        if got[k] >= 1 / 255:
+            assert abs((1 - Tt.min()) - min(0.99, got[k])) <= 1e-12
+        else:
+            assert (Tt == 1.0).all()
+            below += 1
+    assert below > 0                        # some rectangle tiles hold no sample
 
 
 def _fd_scene(seed, deg=3, n=40):
