@@ -263,7 +263,10 @@ void dcgs_state_destroy(dcgs_state *st);
  *   the other views.
  *   rgb: device [n_views][3][H][W]; depth: device [n_views][H][W];
  *   T: device [n_views][H][W] or null.
- * Outputs are overwritten.  The state keeps what render_bwd needs. */
+ * Outputs are overwritten.  The state keeps what render_bwd needs.
+ * DCGS_E_CAPACITY when the (tile, Gaussian) pairs, counted in 64 bits,
+ * exceed 2^31 - 1 (see dcgs_pairs_fit); the state then holds no forward and
+ * render_bwd on it fails with DCGS_E_INVALID. */
 int dcgs_render_fwd(dcgs_ctx *ctx, dcgs_state *st, const float *params,
                     int64_t n, int64_t stride, int sh_degree,
                     const uint16_t *gmask, int mask_shift,
@@ -546,6 +549,13 @@ int dcgs_profile_enable(dcgs_ctx *ctx, int enable);
 int dcgs_profile_read(dcgs_ctx *ctx, double *ms, int64_t *calls, int n_stages);
 
 /* ---- inspection (for tests and tools) ------------------------------------ */
+
+/* The overflow decision every forward takes on its (tile, Gaussian) pair
+ * count, summed in 64 bits on the device: DCGS_OK when n_pairs fits both
+ * pair_capacity (a window's pair buffers; INT64_MAX for an eager forward,
+ * whose buffers are sized after the count) and the 2^31 - 1 limit of the
+ * 32-bit pair indexing, else DCGS_E_CAPACITY.  Host only, no device. */
+int dcgs_pairs_fit(int64_t n_pairs, int64_t pair_capacity);
 
 /* Sizes of the last forward on st: Gaussians, pairs, tiles in x and y. */
 int dcgs_state_info(const dcgs_state *st, int64_t *n, int64_t *n_pairs,

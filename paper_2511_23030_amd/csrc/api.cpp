@@ -305,6 +305,7 @@ int dcgs_render_bwd(dcgs_ctx *ctx, dcgs_state *st, const float *params, int64_t 
     DCGS_CHECK(st && st->ctx == ctx, DCGS_E_INVALID, "render_bwd: state of another context");
     DCGS_CHECK(n == st->n && st->W > 0 && st->cam_dev.p, DCGS_E_INVALID,
                "render_bwd: n differs from the last forward on this state");
+    DCGS_CHECK(st->fwd_ok, DCGS_E_INVALID, "render_bwd: the last forward on this state failed");
     DCGS_CHECK(dl_drgb && (n == 0 || (params && grad && grad_stride >= n && stride >= n)),
                DCGS_E_INVALID, "render_bwd: bad buffers");
     dcgs::render_backward(st, params, n, stride, dl_drgb, dl_ddepth, grad, grad_stride,
@@ -580,6 +581,10 @@ int dcgs_profile_read(dcgs_ctx *ctx, double *ms, int64_t *calls, int n_stages) {
     }
     ctx->marks.clear();
   });
+}
+
+int dcgs_pairs_fit(int64_t n_pairs, int64_t pair_capacity) {
+  return dcgs::pairs_overflow(n_pairs, pair_capacity, 0) ? DCGS_E_CAPACITY : DCGS_OK;
 }
 
 int dcgs_state_info(const dcgs_state *st, int64_t *n, int64_t *n_pairs, int32_t *tiles_x,

@@ -19,6 +19,18 @@ constexpr int kWave = 64;
 constexpr int kMaxViews = 16;
 constexpr int kRecFloats = 12;  // three float4 per projection record
 
+// Largest pair count one forward handles: pair offsets, gradient slots and
+// list positions are 32-bit, per-tile ranges int32.
+constexpr int64_t kMaxPairs = (int64_t(1) << 31) - 1;
+
+// The overflow decision on a forward's (tile, Gaussian) pair count, taken
+// in 64-bit: more pairs than the pair buffers hold, more than 32-bit
+// indexing allows, or an earlier overflow of the same graph-replayed state
+// (sticky) -- the window then draws nothing.
+__host__ __device__ inline bool pairs_overflow(int64_t total, int64_t pcap, int64_t sticky) {
+  return total > pcap || total > kMaxPairs || sticky != 0;
+}
+
 // Thrown inside the library only; every C entry point converts it to a status.
 struct Error {
   int status;
@@ -137,8 +149,9 @@ struct dcgs_state {
   dcgs::DevBuf<float2> partial;  // [5 * P] per-pair gradient partials (ten floats)
   // launch plan: grids sized for n_grid Gaussians, record planes rs apart,
   // pcap pair slots (planned windows; eager forwards size them exactly).
-  // The device counters [n, nr, pairs, overflow, sticky overflow] follow
-  // the camera constants in cam_dev.
+  // The device counters [n, nr, pairs, overflow, sticky overflow, 64-bit
+  // pair total] follow the camera constants in cam_dev.
+  bool fwd_ok = false;  // the last forward completed (a backward may follow)
   int64_t n_grid = 0, rs = 0, pcap = 0;
   // per tile
   dcgs::DevBuf<int2> ranges;

@@ -402,25 +402,42 @@ __global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_
 
 // Depth rank of every record, and the records' pair counts in depth order
 // (what the pair-offset scan sums, read once here instead of gathered by it).
-__global__ void k_rank(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
-                       const int64_t *__restrict__ cnt, uint32_t *__restrict__ rank_of,
-                       uint32_t *__restrict__ count_sorted) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= cnt[1]) return;
-  const uint32_t r = order[j];
-  rank_of[r] = (uint32_t)j;
-  count_sorted[j] = count[r];
+// The pair total is summed here in 64 bits (cnt[5], zeroed before): the
+// 32-bit scan of the counts wraps beyond 2^32 pairs, and the overflow
+// decision must see the true count.
+constexpr int kRankThreads = 256;
+__global__ void __launch_bounds__(kRankThreads)
+    k_rank(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
+           int64_t *__restrict__ cnt, uint32_t *__restrict__ rank_of,
+           uint32_t *__restrict__ count_sorted) {
+  __shared__ unsigned long long part[kRankThreads / kWave];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long c = 0;
+  if (j < cnt[1]) {
+    const uint32_t r = order[j];
+    rank_of[r] = (uint32_t)j;
+    const uint32_t k = count[r];
+    count_sorted[j] = k;
+    c = k;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int w = 0; w < kRankThreads / kWave; ++w) s += part[w];
+    if (s != 0) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + 5), s);
+  }
 }
 
-// Pair total = scan[nr].  cnt[2] = pairs to process; cnt[3] = the total
-// when it exceeds the pair capacity (or any earlier window of this state
-// overflowed, cnt[4] sticky), else 0.  Every later kernel of the window
-// does nothing when cnt[3] != 0.
-__global__ void k_pairs_total(const uint32_t *__restrict__ scan, int64_t *__restrict__ cnt,
-                              int64_t pcap) {
+// cnt[2] = pairs to process; cnt[3] = the 64-bit total (cnt[5]) when it
+// overflows (pairs_overflow: beyond the pair capacity or 2^31 - 1, or any
+// earlier window of this state overflowed, cnt[4] sticky), else 0.  Every
+// later kernel of the window does nothing when cnt[3] != 0.
+__global__ void k_pairs_total(int64_t *__restrict__ cnt, int64_t pcap) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int64_t total = scan[cnt[1]];
-  const bool over = total > pcap || cnt[4] != 0;
+  const int64_t total = cnt[5];
+  const bool over = pairs_overflow(total, pcap, cnt[4]);
   cnt[2] = over ? 0 : total;
   cnt[3] = over ? (total > 0 ? total : 1) : 0;
   if (over) cnt[4] = 1;
@@ -1486,6 +1503,9 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
   int64_t *cnt = counters(s, st);
   const CamD *dc = (const CamD *)s->cam_dev.p;
   uint32_t *sortkey = s->key_tmp.p, *order = s->order.p;
+  // the 64-bit pair total k_rank sums
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt + 5, (int64_t)1, (int64_t)0);
+  DCGS_LAUNCH_CHECK();
   if (n_grid > 0) {
     StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
     hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, kPrepThreads)), dim3(kPrepThreads),
@@ -1499,14 +1519,14 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
     // depth order of all records: stable sort of the float32 depth bits
     sort_u32_pairs(sortkey, order, sortkey + RS + 1, s->val_tmp.p, nr, 32, s->hist, st,
                    cnt + 1);
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, 256)), dim3(256), 0, st, order, s->count.p,
-                       cnt, s->rank_of.p, sortkey + RS + 1);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, kRankThreads)), dim3(kRankThreads), 0, st,
+                       order, s->count.p, cnt, s->rank_of.p, sortkey + RS + 1);
     DCGS_LAUNCH_CHECK();
   }
   StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
   // the depth sort's second key buffer holds the counts in depth order now
   scan_u32(sortkey + RS + 1, nullptr, s->scan.p, nr, s->scan_part.p, st, cnt + 1);
-  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, st, s->scan.p, cnt, pcap);
+  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, st, cnt, pcap);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1554,6 +1574,7 @@ void size_pairs(dcgs_state *s, int64_t pcap) {
 void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t stride,
                     const uint16_t *gmask, int mask_shift, hipStream_t st, float *rgb,
                     float *depth, float *T) {
+  s->fwd_ok = false;
   s->n = n;
   s->n_grid = n;
   size_buffers(s, n);
@@ -1563,14 +1584,25 @@ void render_forward(dcgs_state *s, const float *params, int64_t n, int64_t strid
   if (!s->cam_pinned) DCGS_HIP(hipHostMalloc(&s->cam_pinned, kStageBytes, hipHostMallocDefault));
   stage_cams(s, s->cam_pinned, n);
   DCGS_HIP(hipMemcpyAsync(s->cam_dev.p, s->cam_pinned, kStageBytes, hipMemcpyHostToDevice, st));
-  // no pair capacity limit here: the pair buffers are sized after the count
+  // an eager forward starts clean: no overflow carried over from the last one
+  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt + 3, (int64_t)2, (int64_t)0);
+  DCGS_LAUNCH_CHECK();
+  // no pair capacity here (the pair buffers are sized after the count),
+  // only the 2^31 - 1 limit of 32-bit pair indexing
   enqueue_front(s, params, n, stride, gmask, mask_shift, INT64_MAX, st);
-  int64_t total = 0;
-  DCGS_HIP(hipMemcpyAsync(&total, cnt + 2, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  int64_t c23[2] = {0, 0};
+  DCGS_HIP(hipMemcpyAsync(c23, cnt + 2, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   DCGS_HIP(hipStreamSynchronize(st));
+  if (c23[1] != 0) {
+    s->n_pairs = 0;
+    throw Error{DCGS_E_CAPACITY, "render_fwd: " + std::to_string(c23[1]) +
+                                     " (tile, Gaussian) pairs exceed the limit of 2^31 - 1"};
+  }
+  const int64_t total = c23[0];
   s->n_pairs = total;
   size_pairs(s, total);
   enqueue_back(s, n, total, st, rgb, depth, T);
+  s->fwd_ok = true;
 }
 
 void render_plan(dcgs_state *s, int64_t n_cap, int64_t pcap) {
@@ -1598,6 +1630,7 @@ void render_forward_planned(dcgs_state *s, const float *params, int64_t stride,
                             float *T) {
   enqueue_front(s, params, s->n_grid, stride, gmask, 0, s->pcap, st);
   enqueue_back(s, s->n_grid, s->pcap, st, rgb, depth, T);
+  s->fwd_ok = true;
 }
 
 int64_t *render_counters(dcgs_state *s, hipStream_t st) { return counters(s, st); }

@@ -120,6 +120,7 @@ SIGNATURES = {
     "dcgs_profile_enable": (INT, [P, INT]),
     "dcgs_profile_read": (INT, [P, P, P, INT]),
     "dcgs_state_info": (INT, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)]),
+    "dcgs_pairs_fit": (INT, [I64, I64]),
     "dcgs_state_work": (INT, [P, C.POINTER(I64), C.POINTER(I64), P]),
     "dcgs_state_export": (INT, [P, P, P, P, P, P, P, P, P]),
 }

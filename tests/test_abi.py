@@ -55,6 +55,23 @@ def test_null_arguments_are_rejected_without_touching_the_device(libpath):
     assert L.dcgs_last_error(None) == b"null context"
 
 
+def test_pair_overflow_decision_is_taken_in_64_bits(libpath):
+    """The decision each forward takes on its pair count (the device sums
+    the count in 64 bits): a count that a 32-bit sum would wrap to a small
+    number, or that 32-bit pair indexing cannot address, is an overflow."""
+    from paper_2511_23030_amd import dcgs
+    L = dcgs.lib()
+    OK, CAP = 0, 2
+    eager = 2**63 - 1               # an eager forward sizes its buffers after the count
+    assert L.dcgs_pairs_fit(0, eager) == OK
+    assert L.dcgs_pairs_fit(2**31 - 1, eager) == OK
+    assert L.dcgs_pairs_fit(2**31, eager) == CAP     # beyond int32 ranges / list positions
+    assert L.dcgs_pairs_fit(2**32, eager) == CAP     # wraps to 0 in a 32-bit sum
+    assert L.dcgs_pairs_fit(2**32 + 5, eager) == CAP  # wraps to 5
+    assert L.dcgs_pairs_fit(1000, 999) == CAP        # a window's pair capacity
+    assert L.dcgs_pairs_fit(999, 999) == OK
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     from paper_2511_23030_amd import dcgs
     monkeypatch.setattr(dcgs, "_lib", None)
