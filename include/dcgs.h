@@ -121,6 +121,22 @@ int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
                        uint64_t *out_ids, uint16_t *out_mask,
                        int32_t *out_count, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * selection as dcgs_select_chunks, same arguments and results, but its
+ * scratch (one 16-bit view mask per chunk) is a static device array of
+ * DCGS_NOALLOC_MAX_CHUNKS entries held by each device until the process
+ * ends, so the call allocates nothing (nor does it time itself under
+ * dcgs_profile_enable).  n_chunks > DCGS_NOALLOC_MAX_CHUNKS returns
+ * DCGS_E_CAPACITY.  Every call on one device shares that array: calls that
+ * overlap on one device (two streams, two contexts or two threads at once)
+ * race; calls ordered on one stream do not. */
+#define DCGS_NOALLOC_MAX_CHUNKS 65536
+int dcgs_select_chunks_noalloc(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
+                               const uint64_t *ids, int n_chunks, double chunk_size,
+                               uint64_t *out_ids, uint16_t *out_mask,
+                               int32_t *out_count, void *stream);
+
 /* ---- residency pool: Sec. III-E "Optimization" / "LRU Eviction Strategy" --- */
 
 /* A chunk store in pinned host memory plus a device pool holding at most

@@ -1,6 +1,7 @@
 // C ABI of libdcgs: argument checks, error capture, and dispatch to the
 // kernels and the host runtime.  No C++ exception leaves this file.
 #include <cstring>
+#include <mutex>
 
 #include "internal.h"
 
@@ -33,6 +34,32 @@ hipEvent_t take_event(dcgs_ctx *ctx) noexcept {
 }  // namespace dcgs
 
 namespace {
+
+// Scratch of dcgs_select_chunks_noalloc: the per-chunk view masks that the
+// visibility kernel writes and the compaction kernel reads, for at most
+// DCGS_NOALLOC_MAX_CHUNKS chunks (128 KB).  Each device holds its own copy
+// until the process ends.  On the host the array's name is not a device
+// address: the address is looked up once per device (with that device
+// current) when a context is created there, and only that pointer is used.
+__device__ __align__(256) uint16_t scratch[DCGS_NOALLOC_MAX_CHUNKS];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint16_t *g_scratch[kScratchDevices] = {};
+
+// The device address of `scratch` on the current device `device`.
+uint16_t *scratch_address(int device) {
+  DCGS_CHECK(device >= 0 && device < kScratchDevices, DCGS_E_INVALID,
+             "device index out of range for the no-allocation scratch");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void *p = nullptr;
+    DCGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    DCGS_CHECK(p != nullptr, DCGS_E_HIP, "no device address for the no-allocation scratch");
+    g_scratch[device] = static_cast<uint16_t *>(p);
+  }
+  return g_scratch[device];
+}
 
 template <typename F>
 int guarded(dcgs_ctx *ctx, F &&f) {
@@ -78,6 +105,7 @@ int dcgs_create(dcgs_ctx **out, int device) {
     DCGS_HIP(hipGetDeviceProperties(&prop, device));
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount;
+    ctx->noalloc_scratch = scratch_address(device);
   });
   if (st != DCGS_OK) {
     delete ctx;
@@ -135,6 +163,32 @@ int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views, cons
     dcgs::StageTimer tm(ctx, DCGS_STAGE_SELECT, S(stream));
     dcgs::launch_select(cams, n_views, ids, n_chunks, chunk_size, tmp, out_ids, out_mask,
                         out_count, S(stream));
+  });
+}
+
+int dcgs_select_chunks_noalloc(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
+                               const uint64_t *ids, int n_chunks, double chunk_size,
+                               uint64_t *out_ids, uint16_t *out_mask, int32_t *out_count,
+                               void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(cams && n_views >= 1 && n_views <= dcgs::kMaxViews, DCGS_E_INVALID,
+               "select_chunks_noalloc: 1..16 views required");
+    for (int v = 0; v < n_views; ++v) check_cam(&cams[v]);
+    DCGS_CHECK(n_chunks >= 0 && chunk_size > 0 && out_count &&
+                   (n_chunks == 0 || (ids && out_ids && out_mask)),
+               DCGS_E_INVALID, "select_chunks_noalloc: bad buffers");
+    DCGS_CHECK(n_chunks <= DCGS_NOALLOC_MAX_CHUNKS, DCGS_E_CAPACITY,
+               "select_chunks_noalloc: " + std::to_string(n_chunks) +
+                   " chunks exceed its scratch of " + std::to_string(DCGS_NOALLOC_MAX_CHUNKS) +
+                   " (use dcgs_select_chunks)");
+    DCGS_CHECK(ctx->noalloc_scratch != nullptr, DCGS_E_INVALID,
+               "select_chunks_noalloc: context without scratch");
+    // the same kernels as dcgs_select_chunks; every mask entry the compaction
+    // reads is written first, so nothing needs clearing.  No stage timer (its
+    // events may be created on first use).
+    dcgs::launch_select(cams, n_views, ids, n_chunks, chunk_size, ctx->noalloc_scratch, out_ids,
+                        out_mask, out_count, S(stream));
   });
 }
 

@@ -102,6 +102,7 @@ struct dcgs_ctx {
   std::vector<Mark> marks;
   std::vector<hipEvent_t> spare_events;
   dcgs::DevBuf<uint16_t> sel_mask;
+  uint16_t *noalloc_scratch = nullptr;  // this device's copy of the static selection scratch
   dcgs::DevBuf<int> flag;
   dcgs::DevBuf<float> loss_part;
   dcgs::DevBuf<float> loss_maps;  // SSIM derivative maps and partial sums

@@ -83,6 +83,7 @@ SIGNATURES = {
     "dcgs_last_error": (C.c_char_p, [P]),
     "dcgs_chunk_ids": (INT, [P, P, I64, I64, DBL, P, P]),
     "dcgs_select_chunks": (INT, [P, P, INT, P, INT, DBL, P, P, P, P]),
+    "dcgs_select_chunks_noalloc": (INT, [P, P, INT, P, INT, DBL, P, P, P, P]),
     "dcgs_pool_create": (INT, [P, INT, I64, C.POINTER(P)]),
     "dcgs_pool_destroy": (None, [P]),
     "dcgs_pool_ingest": (INT, [P, P, I64, DBL, P]),
