@@ -121,6 +121,34 @@ int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
                        uint64_t *out_ids, uint16_t *out_mask,
                        int32_t *out_count, void *stream);
 
+/* ---- keyframe selection: Sec. III-F ---------------------------------------- */
+
+/* SYNC.  For n_keyframes keyframes (host cameras; keyframe k's position p_k
+ * is its camera centre -R^T t, float64, each product and sum rounded in
+ * order) and the chunk grid ids (device, as for dcgs_select_chunks):
+ *   in_set[k] = 1 when floor(p_k / grid) = floor(p_latest / grid) per axis
+ *     (exact floor), i.e. k is in the spatial candidate set K(p_latest) of
+ *     Eq. (8), latest the index of the most recently added keyframe;
+ *   n_visible[k] = |C_v(k)|, the chunks keyframe k sees (the visibility
+ *     test of dcgs_select_chunks);
+ *   n_overlap[k] = |C_v(k) & C_active|, C_active = active_ids (host,
+ *     n_active, strictly ascending; e.g. the resident chunks);
+ *   overlap[k] = n_overlap[k] / n_visible[k] in float64 (Eq. 7), and 1 for
+ *     a keyframe that sees no chunk (it needs nothing loaded).
+ * window (host int32 [n_window], nullable): the batching window formed from
+ * the candidate set, the keyframes of K(p_latest) with the highest overlap,
+ * ties to the more recent (higher index) keyframe; *n_window_out gets its
+ * size (min(n_window, |K(p_latest)|)).  The paper picks keyframes inside
+ * K(p_latest) with CaRtGS's usage-based rule instead, which is not built.
+ * Per-keyframe outputs: host arrays [n_keyframes], each nullable.
+ * 1 <= n_keyframes <= 65536. */
+int dcgs_keyframe_overlap(dcgs_ctx *ctx, const dcgs_camera *keyframes, int n_keyframes,
+                          int latest, double grid, const uint64_t *ids, int n_chunks,
+                          double chunk_size, const uint64_t *active_ids, int n_active,
+                          uint8_t *in_set, int32_t *n_visible, int32_t *n_overlap,
+                          double *overlap, int n_window, int32_t *window,
+                          int32_t *n_window_out, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * selection as dcgs_select_chunks, same arguments and results, but its
@@ -420,7 +448,15 @@ typedef struct dcgs_window_config {
   uint16_t *gmask;               /* [capacity] view mask of each compacted Gaussian */
   float *rgb, *depth, *dl_drgb;  /* [V][3][H][W], [V][H][W], [V][3][H][W] */
   const float *targets;          /* [V][3][H][W] */
-  double *stats;                 /* [2]: sum |d| and sum d^2 of the last launch */
+  double *stats;                 /* sum |d| and sum d^2 of the last launch ([2]); with
+                                    the full loss, the four sums of dcgs_loss_mapping ([4]) */
+  /* The full mapping loss of Eqs. (2)-(4) inside the graph (dcgs_loss_mapping's
+   * terms and normalisation, loss_norm unused) when lambda_s > 0 or
+   * lambda_depth > 0; both 0 keeps the L1 loss above. */
+  double lambda_s, lambda_depth;
+  const float *depth_targets;    /* [V][H][W], read at every launch; needed when
+                                    lambda_depth > 0 */
+  float *dl_ddepth;              /* [V][H][W] when lambda_depth > 0 */
 } dcgs_window_config;
 
 /* SYNC.  Allocate the window's buffers and record its two graph instances. */

@@ -166,6 +166,32 @@ int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views, cons
   });
 }
 
+int dcgs_keyframe_overlap(dcgs_ctx *ctx, const dcgs_camera *keyframes, int n_keyframes,
+                          int latest, double grid, const uint64_t *ids, int n_chunks,
+                          double chunk_size, const uint64_t *active_ids, int n_active,
+                          uint8_t *in_set, int32_t *n_visible, int32_t *n_overlap,
+                          double *overlap, int n_window, int32_t *window,
+                          int32_t *n_window_out, void *stream) {
+  if (!ctx) return DCGS_E_INVALID;
+  return guarded(ctx, [&] {
+    DCGS_CHECK(keyframes && n_keyframes >= 1 && n_keyframes <= 65536 && latest >= 0 &&
+                   latest < n_keyframes && grid > 0,
+               DCGS_E_INVALID, "keyframe_overlap: 1..65536 keyframes, latest among them, grid > 0");
+    for (int k = 0; k < n_keyframes; ++k) check_cam(&keyframes[k]);
+    DCGS_CHECK(n_chunks >= 0 && chunk_size > 0 && (n_chunks == 0 || ids) && n_active >= 0 &&
+                   (n_active == 0 || active_ids),
+               DCGS_E_INVALID, "keyframe_overlap: bad chunk arrays");
+    for (int i = 1; i < n_active; ++i)
+      DCGS_CHECK(active_ids[i - 1] < active_ids[i], DCGS_E_INVALID,
+                 "keyframe_overlap: active ids must be strictly ascending");
+    DCGS_CHECK(n_window >= 0 && (n_window == 0 || window), DCGS_E_INVALID,
+               "keyframe_overlap: bad window buffer");
+    dcgs::keyframe_overlap(ctx, keyframes, n_keyframes, latest, grid, ids, n_chunks, chunk_size,
+                           active_ids, n_active, in_set, n_visible, n_overlap, overlap, n_window,
+                           window, n_window_out, S(stream));
+  });
+}
+
 int dcgs_select_chunks_noalloc(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
                                const uint64_t *ids, int n_chunks, double chunk_size,
                                uint64_t *out_ids, uint16_t *out_mask, int32_t *out_count,

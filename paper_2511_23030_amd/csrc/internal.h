@@ -17,7 +17,7 @@ namespace dcgs {
 
 constexpr int kWave = 64;
 constexpr int kMaxViews = 16;
-constexpr int kRecFloats = 12;  // three float4 per projection record
+constexpr int kRecFloats = 16;  // four float4 per projection record
 
 // Largest pair count one forward handles: pair offsets, gradient slots and
 // list positions are 32-bit, per-tile ranges int32.
@@ -102,6 +102,7 @@ struct dcgs_ctx {
   std::vector<Mark> marks;
   std::vector<hipEvent_t> spare_events;
   dcgs::DevBuf<uint16_t> sel_mask;
+  dcgs::DevBuf<uint8_t> kf_buf;   // keyframe selection: cameras, active ids, outputs
   uint16_t *noalloc_scratch = nullptr;  // this device's copy of the static selection scratch
   dcgs::DevBuf<int> flag;
   dcgs::DevBuf<float> loss_part;
@@ -157,6 +158,13 @@ struct dcgs_state {
   // per tile
   dcgs::DevBuf<int2> ranges;
   dcgs::DevBuf<int> frontier;
+  dcgs::DevBuf<uint32_t> torder;  // raster launch order (tile per workgroup), longest lists first
+  // backward work list: long lists split into segments (render.hip)
+  dcgs::DevBuf<uint32_t> segc, segs, segpart;  // per-order counts, their scans, scan partials
+  dcgs::DevBuf<int2> witem;        // (tile, segment) per backward workgroup
+  dcgs::DevBuf<int> bslot;         // per tile: first boundary-state slot, -1 if not split
+  dcgs::DevBuf<float> bound;       // per slot: T, colour, depth of every pixel of the tile
+  int64_t wcap = 0;                // work items the backward grid is sized for
   // per pixel
   dcgs::DevBuf<float> T_final;
   dcgs::DevBuf<int> last;
@@ -254,6 +262,12 @@ void launch_select(const dcgs_camera *cams, int n_views, const uint64_t *ids,
                    int n_chunks, double s, uint16_t *mask_tmp,
                    uint64_t *out_ids, uint16_t *out_mask, int32_t *out_count,
                    hipStream_t st);
+// Keyframe selection, Sec. III-F (chunks.hip): Eq. (8) membership, Eq. (7)
+// overlap counts, and the window (host outputs; synchronises st).
+void keyframe_overlap(dcgs_ctx *ctx, const dcgs_camera *kf, int n_kf, int latest, double g,
+                      const uint64_t *ids, int n, double s, const uint64_t *act, int n_act,
+                      uint8_t *in_set, int32_t *n_visible, int32_t *n_overlap, double *overlap,
+                      int n_window, int32_t *window, int32_t *n_window_out, hipStream_t st);
 // Per-chunk view mask only (bit v: view v sees the chunk), 1..16 views.
 void launch_select_mask(const dcgs_camera *cams, int n_views, const uint64_t *ids,
                         int n_chunks, double s, uint16_t *mask, hipStream_t st);
@@ -275,6 +289,8 @@ void mapping_loss(dcgs_ctx *ctx, const float *rgb, const float *target, const fl
                   const float *depth_target, int n_views, int H, int W, double lambda_s,
                   double lambda_depth, float *dl_drgb, float *dl_ddepth, double *stats,
                   DevBuf<float> &scratch, hipStream_t st);
+
+void mapping_loss_reserve(int n_views, int H, int W, DevBuf<float> &scratch);
 
 // LoG sampling map (sampling.hip)
 void sample_pixels(dcgs_ctx *ctx, const float *image, const float *render, const float *u,

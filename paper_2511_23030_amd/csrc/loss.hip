@@ -273,6 +273,19 @@ constexpr int kDepthBlocks = 512;
 
 }  // namespace
 
+// Scratch of mapping_loss for n_views images of H x W (sized ahead of a
+// graph capture, where nothing may allocate).
+size_t mapping_loss_scratch(int n_views, int H, int W) {
+  const int64_t HW = (int64_t)W * H;
+  const int planes = 3 * n_views;
+  const int64_t nb = (int64_t)((W + kT - 1) / kT) * ((H + kT - 1) / kT) * planes;
+  return 3 * (size_t)planes * HW + 3 * nb + kDepthBlocks + 16;
+}
+
+void mapping_loss_reserve(int n_views, int H, int W, DevBuf<float> &scratch) {
+  scratch.need(mapping_loss_scratch(n_views, H, W));
+}
+
 void mapping_loss(dcgs_ctx *ctx, const float *rgb, const float *target, const float *depth,
                   const float *depth_target, int n_views, int H, int W, double lambda_s,
                   double lambda_depth, float *dl_drgb, float *dl_ddepth, double *stats,
@@ -287,7 +300,7 @@ void mapping_loss(dcgs_ctx *ctx, const float *rgb, const float *target, const fl
   const int planes = 3 * n_views;
   const dim3 grid((W + kT - 1) / kT, (H + kT - 1) / kT, planes);
   const int64_t nb = (int64_t)grid.x * grid.y * grid.z;
-  float *maps = scratch.need(3 * (size_t)planes * HW + 3 * nb + kDepthBlocks + 16);
+  float *maps = scratch.need(mapping_loss_scratch(n_views, H, W));
   float *amap = maps, *bmap = amap + planes * HW, *cmap = bmap + planes * HW;
   float *pS = cmap + planes * HW, *pL = pS + nb, *pD = pL + 2 * nb;
   const Window11 win = make_window();

@@ -13,9 +13,11 @@
 //    float32 depth key) then agrees with a float64 reference except within
 //    ~1e-15 of a boundary.  The cost is hidden under the 236-byte parameter
 //    read per Gaussian.
-//  * A projection record is three float4 (48 B): u and v relative to the
-//    pixel box corner (small magnitudes keep float32 offsets exact to
-//    ~1e-7 px), conic, opacity, colour, depth and the packed pixel box.
+//  * A projection record is four float4 (64 B, one aligned segment): u and
+//    v relative to the pixel box corner (small magnitudes keep float32
+//    offsets exact to ~1e-7 px), conic, opacity, colour, depth and the
+//    packed pixel box, then the record's pair offset and kept-tile mask
+//    (written by pair emission, read by the backward with the record).
 //  * The depth digits of the (tile, depth) keys are the same for all pairs of
 //    a Gaussian, so the LSD passes over them run on the N Gaussians before
 //    pair expansion; pairs are then emitted in depth order and stably sorted
@@ -30,6 +32,8 @@
 //    butterfly, then a fixed-order sum over waves) and writes them to a
 //    per-pair slot.  A per-Gaussian pass sums its slots in a fixed order:
 //    gradients are bit-reproducible and use no float atomics.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace dcgs {
@@ -338,9 +342,11 @@ __device__ __forceinline__ bool tile_kept(uint64_t m, int n_rect, int k) {
 }
 
 // One thread per Gaussian; it projects the Gaussian into every view whose
-// bit is set in its chunk's view mask.  Record r = v * n + g is three
-// float4 at rec[3 r .. 3 r + 2] (48 contiguous bytes, one gather per record).  cnt[0] = n (device counter; the grid may be
-// sized for a capacity).
+// bit is set in its chunk's view mask.  Record r = v * n + g is the float4s
+// rec[4 r .. 4 r + 3] (64 contiguous bytes, one gather per record; this
+// kernel writes the first three, pair emission the fourth, and a culled
+// record is not written).  cnt[0] = n (device counter; the grid may be sized
+// for a capacity).
 // Four waves per SIMD: the float64 projection is latency-bound, and the
 // compiler fits it in 128 registers without spilling.
 constexpr int kPrepThreads = 64;
@@ -374,13 +380,10 @@ __global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_
       zf = (float)g.Z;
     }
     zkey[r] = __float_as_uint(zf);
-    if (culled) {
+    if (culled) {  // its record is never read: no pairs, and exports zero it
       count[r] = 0;
       tmask[r] = 0;
       sortkey[r] = kCulledKey;
-      rec[3 * r] = make_float4(0, 0, 0, 0);
-      rec[3 * r + 1] = make_float4(0, 0, 0, 0);
-      rec[3 * r + 2] = make_float4(0, 0, 0, 0);
       continue;
     }
     double dir[3], dn, Y[16], raw[3];
@@ -390,11 +393,11 @@ __global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_
     count[r] = n_keep;
     sortkey[r] = __float_as_uint(zf);
     const double id = 1.0 / g.det;
-    rec[3 * r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(-0.5 * kLog2e * g.c * id),
+    rec[4 * r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(-0.5 * kLog2e * g.c * id),
                          (float)(kLog2e * g.b * id));
-    rec[3 * r + 1] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
+    rec[4 * r + 1] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
                               (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
-    rec[3 * r + 2] = make_float4((float)fmax(raw[2], 0.0), zf,
+    rec[4 * r + 2] = make_float4((float)fmax(raw[2], 0.0), zf,
                                   __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
                                   __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
   }
@@ -447,9 +450,9 @@ __global__ void k_pairs_total(int64_t *__restrict__ cnt, int64_t pcap) {
 // depth order (the run of the record of depth rank j starts at scan[j]),
 // tiles of a record row-major.  One thread per record in record order: its
 // count, box and tile mask are read coalesced, and only its run's start is
-// gathered (by depth rank).
+// gathered (by depth rank).  It also writes the record's fourth float4.
 __global__ void k_emit(const uint32_t *__restrict__ rank_of, const uint32_t *__restrict__ count,
-                       const uint32_t *__restrict__ scan, const float4 *__restrict__ rec,
+                       const uint32_t *__restrict__ scan, float4 *__restrict__ rec,
                        const uint64_t *__restrict__ tmask, const int64_t *__restrict__ cnt,
                        int TW, int TH, int tiles_x, int tiles_per_view,
                        uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
@@ -461,12 +464,17 @@ __global__ void k_emit(const uint32_t *__restrict__ rank_of, const uint32_t *__r
   const uint32_t base = scan[rank_of[g]];
   pair_off[g] = base;
   const uint32_t view_base = (uint32_t)(g / n) * (uint32_t)tiles_per_view;
-  const float4 C = rec[3 * g + 2];
+  const float4 C = rec[4 * g + 2];
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
   const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
   const int n_rect = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
   const uint64_t m = tmask[g];
+  // the record's fourth float4: what the backward's epilogue needs to place
+  // its per-tile gradient partials (pair offset and kept-tile mask), staged
+  // with the record instead of gathered at random per (record, tile)
+  rec[4 * g + 3] = make_float4(__uint_as_float(base), __uint_as_float((uint32_t)m),
+                               __uint_as_float((uint32_t)(m >> 32)), 0.0f);
   uint32_t k = base;
   const int wc = tx1 - tx0 + 1;
   if (n_rect > 64) {  // every tile kept
@@ -504,12 +512,29 @@ __global__ void k_ranges(const uint64_t *__restrict__ pairs, const int64_t *__re
   ranges[t] = make_int2((int)lower((uint32_t)t), (int)lower((uint32_t)t + 1));
 }
 
-// XCD-aware block -> tile map: the 8 XCDs receive workgroups round-robin,
-// so workgroup b runs on XCD b % 8; give each XCD a contiguous band of tiles.
-__device__ inline int tile_of_block(int n_tiles) {
+// Raster launch order: workgroup b takes tile order[b].  The 8 XCDs receive
+// workgroups round-robin (workgroup b runs on XCD b % 8), so the base order
+// gives each XCD a contiguous band of tiles (neighbouring tiles share
+// Gaussians in its L2).  That order is then sorted, stably, by the bit
+// length of each tile's list, longest first: the few long lists (the
+// vanishing point of a road holds 100 times the median) start at once
+// instead of ending the launch alone, and within a length class the XCD
+// bands are kept.  Padding blocks get tile ids >= n_tiles and sort last.
+constexpr int kOrderBits = 5;
+__global__ void k_order_keys(const int2 *__restrict__ ranges, const int64_t *__restrict__ cnt,
+                             int n_tiles, int grid, uint32_t *__restrict__ key,
+                             uint32_t *__restrict__ val) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= grid) return;
   const int per = (n_tiles + 7) >> 3;
-  const int b = blockIdx.x;
-  return (b & 7) * per + (b >> 3);
+  const int t = (b & 7) * per + (b >> 3);
+  uint32_t k = 31;
+  if (t < n_tiles && cnt[3] == 0) {
+    const int2 r = ranges[t];
+    k = 31u - (32u - (uint32_t)__clz(r.y - r.x));  // 31 - bit length
+  }
+  key[b] = k;
+  val[b] = (uint32_t)t;
 }
 
 struct Sample {
@@ -651,22 +676,79 @@ __device__ __forceinline__ Box uniform_box(const float4 &C) {
   return b;
 }
 
+// Long lists are split for the backward into segments of 64 list positions
+// per pixel of the tile (4096 for 8x8 tiles, 16384 for 16x16; a multiple of
+// every raster batch size): one workgroup per (tile, segment).  The forward walks the whole list as before and, for a
+// split tile, stores each pixel's compositing state (T, colour, depth) at
+// every segment end (the list's end included), so a segment's backward
+// starts where the reverse sweep of the whole list would be at that
+// position: T from the stored state, and the colour and depth composited
+// behind it as the final values minus those stored.
+constexpr int kSegPerPixel = 64;
+constexpr int kStateVals = 5;  // T, colour r, g, b, depth
+
+__host__ __device__ constexpr int seg_len(int tw, int th) { return kSegPerPixel * tw * th; }
+__device__ __forceinline__ int seg_count(int L, int S) { return L > S ? (L + S - 1) / S : 1; }
+
+// Per position b of the launch order: work items (segments) of its tile,
+// and boundary-state slots (one per segment of a split tile).
+__global__ void k_seg_count(const uint32_t *__restrict__ order, const int2 *__restrict__ ranges,
+                            int n_tiles, int grid, int S, uint32_t *__restrict__ cw,
+                            uint32_t *__restrict__ cb) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= grid) return;
+  const int t = (int)order[b];
+  uint32_t w = 0, bs = 0;
+  if (t < n_tiles) {
+    const int2 r = ranges[t];
+    const int ns = seg_count(r.y - r.x, S);
+    w = (uint32_t)ns;
+    bs = ns > 1 ? (uint32_t)ns : 0u;
+  }
+  cw[b] = w;
+  cb[b] = bs;
+}
+
+// The work list (tile, segment) in launch order, each tile's first
+// boundary slot (-1: not split), and the work-item count cnt[6].
+__global__ void k_seg_fill(const uint32_t *__restrict__ order, int n_tiles, int grid,
+                           const uint32_t *__restrict__ cw, const uint32_t *__restrict__ sw,
+                           const uint32_t *__restrict__ cb, const uint32_t *__restrict__ sb,
+                           int2 *__restrict__ witem, int *__restrict__ bslot,
+                           int64_t *__restrict__ cnt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b == 0) cnt[6] = (int64_t)sw[grid];
+  if (b >= grid) return;
+  const int t = (int)order[b];
+  if (t >= n_tiles) return;
+  const uint32_t w0 = sw[b];
+  for (uint32_t i = 0; i < cw[b]; ++i) witem[w0 + i] = make_int2(t, (int)i);
+  bslot[t] = cb[b] != 0 ? (int)sb[b] : -1;
+}
+
+// Records per straight-line group of the one-cell forward rasterizer.
+constexpr int kFwdGroup = 4;
+
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_fwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
+                 const uint32_t *__restrict__ order,
                  const float4 *__restrict__ rec, int64_t RS, int W, int H, int tiles_x,
                  int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  float *__restrict__ rgb, float *__restrict__ depth, float *__restrict__ Tout,
-                 float *__restrict__ Tstate, int *__restrict__ last_out) {
+                 float *__restrict__ Tstate, int *__restrict__ last_out,
+                 const int *__restrict__ bslot, float *__restrict__ bound) {
 #pragma clang fp contract(off)
   constexpr int NT = TW * TH / PPT;
   constexpr int BS = NT;
+  constexpr int kSegLen = seg_len(TW, TH);
+  static_assert(kSegLen % BS == 0, "segment ends fall on batch starts");
   __shared__ float4 sA[BS], sB[BS], sC[BS];
   __shared__ uint32_t sM[BS];
   // a one-cell tile needs no cell masks: every record of its list meets it
   // or is rejected pixel by pixel
   constexpr bool kOneCell = CellLayout<TW, TH, PPT>::kCells == 1;
-  const int gt = tile_of_block(n_tiles);
+  const int gt = (int)order[blockIdx.x];
   if (gt >= n_tiles) return;
   const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
@@ -694,12 +776,33 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     done[j] = !(cell.X0[j] + lx < W && cell.Y0[j] + ly < H);
     n_live += !done[j];
   }
+  // a split tile stores each pixel's state at every segment end: slot
+  // bs + i holds it after the records before segment i + 1 (the last slot:
+  // after the whole list)
+  const int bs = bslot[gt];
+  auto store_state = [&](const int slot) {
+    float *o = bound + (int64_t)slot * kStateVals * (TW * TH);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int lp = (cell.Y0[j] - ty * TH + ly) * TW + (cell.X0[j] - tx * TW + lx);
+      o[lp] = T[j];
+      o[TW * TH + lp] = c0[j];
+      o[2 * TW * TH + lp] = c1[j];
+      o[3 * TW * TH + lp] = c2[j];
+      o[4 * TW * TH + lp] = D[j];
+    }
+  };
   for (int base = rg.x; base < rg.y; base += BS) {
+    // once every pixel is saturated no later segment end is needed: a
+    // segment's backward reads its end state only for pixels that
+    // composited a record behind that end
     if (__syncthreads_count(n_live) == 0) break;
+    if (bs >= 0 && base > rg.x && (base - rg.x) % kSegLen == 0)
+      store_state(bs + (base - rg.x) / kSegLen - 1);
     const int p = base + threadIdx.x;
     if (p < rg.y) {
       const uint32_t g = (uint32_t)pairs[p];
-      const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
+      const float4 *q = rec + 4 * (int64_t)g;  // a 64-byte record: its first 48 bytes
       const float4 A = q[0], B = q[1], C = q[2];
       sA[threadIdx.x] = A;
       sB[threadIdx.x] = B;
@@ -709,6 +812,27 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
     __syncthreads();
     const int nb = min(BS, rg.y - base);
+    // one compositing step of cell j with the record's sample s: predicated
+    // rather than branched inside a cell (a lane that does not composite
+    // adds exact zeros, and the wavefront issues no mask bookkeeping);
+    // contraction is off in this kernel, so every raster shape composites
+    // with the same roundings
+    auto composite = [&](const int j, const Sample &s, const bool valid, const float4 &B,
+                         const float4 &C, const int pos) {
+      const bool act = valid & s.ok & !done[j];
+      const float a = act ? s.alpha : 0.0f;
+      const float Tn = T[j] * (1.0f - a);
+      const bool stop = act & (Tn < kTMin);
+      const bool comp = act & !stop;
+      const float w = comp ? a * T[j] : 0.0f;
+      c0[j] = __builtin_fmaf(B.z, w, c0[j]);
+      c1[j] = __builtin_fmaf(B.w, w, c1[j]);
+      c2[j] = __builtin_fmaf(C.x, w, c2[j]);
+      D[j] = __builtin_fmaf(C.y, w, D[j]);
+      T[j] = comp ? Tn : T[j];
+      last[j] = comp ? pos : last[j];
+      done[j] = done[j] | stop;
+    };
     uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
     for (int k0 = 0; k0 < nb; k0 += 8) {
       // every 8 records: cells whose pixels are all saturated leave the
@@ -718,47 +842,51 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       for (int j = 0; j < PPT; ++j) live |= (uint32_t)(__ballot(!done[j]) != 0) << j;
       if (live == 0) break;
       const int k1 = min(k0 + 8, nb);
-      for (int k = k0; k < k1; ++k) {
-        uint32_t mk = 1u;
-        if constexpr (!kOneCell) {
-          mk = __builtin_amdgcn_readfirstlane(m_next);
-          m_next = sM[min(k + 1, BS - 1)];
+      if constexpr (kOneCell) {
+        // one cell per tile: no masks, every record of the list is taken.
+        // Records go in straight-line groups: the group's samples do not
+        // depend on the compositing state, so their loads and arithmetic
+        // overlap, and the compositing steps follow in list order.  A slot
+        // past the batch repeats its last record with valid false (it
+        // changes nothing).
+        for (int kg = k0; kg < k1; kg += kFwdGroup) {
+          Sample sg[kFwdGroup];
+          float4 Bg[kFwdGroup], Cg[kFwdGroup];
+#pragma unroll
+          for (int g = 0; g < kFwdGroup; ++g) {
+            const int k = min(kg + g, k1 - 1);
+            const float4 A = sA[k];
+            Bg[g] = sB[k];
+            Cg[g] = sC[k];
+            sg[g] = sample(lx, ly, lxh, lyh, cell.X0[0], cell.Y0[0], uniform_box(Cg[g]), A, Bg[g]);
+          }
+#pragma unroll
+          for (int g = 0; g < kFwdGroup; ++g)
+            composite(0, sg[g], kg + g < k1, Bg[g], Cg[g], base + kg + g);
         }
+        continue;
+      }
+      for (int k = k0; k < k1; ++k) {
+        const uint32_t mk = __builtin_amdgcn_readfirstlane(m_next);
+        m_next = sM[min(k + 1, BS - 1)];
         const uint32_t hit = cell.mine(mk) & live;
         if (hit == 0) continue;  // no live cell of this wavefront meets the box
         const float4 A = sA[k], B = sB[k], C = sC[k];
         const Box bx = uniform_box(C);
-        // predicated rather than branched inside a cell: a lane that does not
-        // composite adds exact zeros, and the wavefront issues no mask
-        // bookkeeping.  Contraction is off in this kernel: every raster shape
-        // composites with the same roundings.
-        auto composite = [&](const int j) {
-          const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
-          const bool act = s.ok & !done[j];
-          const float a = act ? s.alpha : 0.0f;
-          const float Tn = T[j] * (1.0f - a);
-          const bool stop = act & (Tn < kTMin);
-          const bool comp = act & !stop;
-          const float w = comp ? a * T[j] : 0.0f;
-          c0[j] = __builtin_fmaf(B.z, w, c0[j]);
-          c1[j] = __builtin_fmaf(B.w, w, c1[j]);
-          c2[j] = __builtin_fmaf(C.x, w, c2[j]);
-          D[j] = __builtin_fmaf(C.y, w, D[j]);
-          T[j] = comp ? Tn : T[j];
-          last[j] = comp ? base + k : last[j];
-          done[j] = done[j] | stop;
-        };
         // one cell at a time (straight-line code over all cells holds more
         // registers and runs slower here)
 #pragma unroll
         for (int j = 0; j < PPT; ++j)
-          if (hit & (1u << j)) composite(j);
+          if (hit & (1u << j))
+            composite(j, sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B), true, B, C,
+                      base + k);
       }
     }
     n_live = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) n_live += !done[j];
   }
+  if (bs >= 0) store_state(bs + seg_count(rg.y - rg.x, kSegLen) - 1);
   const int64_t HW = (int64_t)W * H;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
@@ -857,24 +985,28 @@ __device__ __forceinline__ int bitrev4(int l) {
 template <int TW, int TH, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_bwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
+                 const int2 *__restrict__ witem, const int64_t *__restrict__ cnt,
                  const float4 *__restrict__ rec, int64_t RS, int W, int H, int tiles_x,
                  int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  const float *__restrict__ Tstate, const int *__restrict__ last_in,
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
-                 const uint32_t *__restrict__ pair_off, const uint32_t *__restrict__ rank_of,
-                 const uint64_t *__restrict__ tmask, float2 *__restrict__ partial,
-                 int *__restrict__ frontier) {
+                 const uint32_t *__restrict__ rank_of, float2 *__restrict__ partial,
+                 int *__restrict__ frontier, const int *__restrict__ bslot,
+                 const float *__restrict__ bound) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
   constexpr int BS = NT < 128 ? NT : 128;  // records per batch
   constexpr int NC = 10;
   __shared__ float4 sA[BS], sB[BS], sC[BS];
-  __shared__ uint32_t sG[BS], sM[BS];
+  __shared__ uint32_t sP[BS], sM[BS];  // pair offset of the record, cell mask
+  __shared__ uint64_t sT[BS];          // kept-tile mask of the record
   __shared__ float red[NW][BS][NC];
   constexpr bool kOneCell = CellLayout<TW, TH, PPT>::kCells == 1;  // no cell masks needed
   __shared__ int max_last;
-  const int gt = tile_of_block(n_tiles);
-  if (gt >= n_tiles) return;
+  // work item: segment seg of tile gt (the whole list when it is not split)
+  if (blockIdx.x >= cnt[6]) return;
+  const int2 wi = witem[blockIdx.x];
+  const int gt = wi.x, seg = wi.y;
   const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   {  // this view's images and upstream gradients
@@ -889,6 +1021,11 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   const float lxh = (float)lx + 0.5f, lyh = (float)ly + 0.5f;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int2 rg = ranges[gt];
+  constexpr int kSegLen = seg_len(TW, TH);
+  static_assert(kSegLen % BS == 0, "segment ends fall on batch starts");
+  const int nseg = seg_count(rg.y - rg.x, kSegLen);
+  const int s_lo = rg.x + seg * kSegLen, s_hi = nseg > 1 ? min(s_lo + kSegLen, rg.y) : rg.y;
+  const int bs = nseg > 1 ? bslot[gt] : -1;
   const int64_t HW = (int64_t)W * H;
   // GS = dL/dC . (colour and depth composited behind the current Gaussian,
   // background included): dalpha needs only this dot product
@@ -911,6 +1048,21 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       if (dl_ddepth) gd[j] = dl_ddepth[pix];
     }
     GS[j] = T[j] * (g0[j] * bg0 + g1[j] * bg1 + g2[j] * bg2);
+    if (bs >= 0 && last[j] >= s_hi) {
+      // the pixel composited records behind this segment: its sweep enters
+      // the segment at the segment's end, with T stored there by the
+      // forward and, behind it, the final colour (background included) and
+      // depth minus those accumulated up to that end
+      const int lp = (cell.Y0[j] - ty * TH + ly) * TW + (cell.X0[j] - tx * TW + lx);
+      const float *e = bound + (int64_t)(bs + seg) * kStateVals * (TW * TH) + lp;
+      const float *f = bound + (int64_t)(bs + nseg - 1) * kStateVals * (TW * TH) + lp;
+      const float Tf = f[0];
+      T[j] = e[0];
+      GS[j] = g0[j] * ((f[TW * TH] + Tf * bg0) - e[TW * TH]) +
+              g1[j] * ((f[2 * TW * TH] + Tf * bg1) - e[2 * TW * TH]) +
+              g2[j] * ((f[3 * TW * TH] + Tf * bg2) - e[3 * TW * TH]) +
+              gd[j] * (f[4 * TW * TH] - e[4 * TW * TH]);
+    }
     // the last list position any pixel of cell j composited (uniform)
     int m = last[j];
 #pragma unroll
@@ -922,19 +1074,21 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   __syncthreads();
   if (lane == 0 && my_last >= 0) atomicMax(&max_last, my_last);
   __syncthreads();
+  // top: the deepest position any pixel of the tile composited; the
+  // segment holding it (segment 0 when there is none) records the frontier
   const int top = max_last;
-  if (top < rg.x) {
-    if (threadIdx.x == 0) frontier[gt] = -1;
-    return;
-  }
-  for (int end = top + 1; end > rg.x; end -= BS) {
-    const int beg = max(rg.x, end - BS);
+  if (threadIdx.x == 0 && ((top >= s_lo && top < s_hi) || (top < rg.x && seg == 0)))
+    frontier[gt] = top < rg.x ? -1 : (int)rank_of[(uint32_t)pairs[top]];
+  const int seg_top = min(top, s_hi - 1);
+  for (int end = seg_top + 1; end > s_lo; end -= BS) {
+    const int beg = max(s_lo, end - BS);
     const int nb = end - beg;
     if (threadIdx.x < nb) {  // slot k holds position end - 1 - k
       const uint32_t g = (uint32_t)pairs[end - 1 - threadIdx.x];
-      sG[threadIdx.x] = g;
-      const float4 *q = rec + 3 * (int64_t)g;  // one record: 48 contiguous bytes
-      const float4 A = q[0], B = q[1], C = q[2];
+      const float4 *q = rec + 4 * (int64_t)g;  // one 64-byte record
+      const float4 A = q[0], B = q[1], C = q[2], Dq = q[3];
+      sP[threadIdx.x] = __float_as_uint(Dq.x);
+      sT[threadIdx.x] = (uint64_t)__float_as_uint(Dq.y) | ((uint64_t)__float_as_uint(Dq.z) << 32);
       sA[threadIdx.x] = A;
       sB[threadIdx.x] = B;
       sC[threadIdx.x] = C;
@@ -942,6 +1096,46 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(A, B, C, tx, ty);
     }
     __syncthreads();
+    // one adjoint step of cell j for the record (s, B, C) at list position
+    // pos, into the record's accumulators v (lanes that composited it are
+    // added to contrib).  Predicated rather than branched inside a cell: a
+    // lane whose pixel does not use this Gaussian runs with alpha = 0 (1 / (1
+    // - 0) is exact), which leaves T and S unchanged and adds exact zeros to
+    // every term.
+    auto adjoint = [&](const int j, const Sample &s, const bool valid, const float4 &B,
+                       const float4 &C, const int pos, float (&v)[16], uint64_t &contrib) {
+      const bool act = valid & s.ok & (pos <= last[j]);
+      contrib |= __ballot(act);
+      const float a = act ? s.alpha : 0.0f;
+      const float iom = __builtin_amdgcn_rcpf(1.0f - a);
+      const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
+      const float w = a * Tk;
+      v[6] += g0[j] * w;
+      v[7] += g1[j] * w;
+      v[8] += g2[j] * w;
+      v[9] += gd[j] * w;
+      // dL/dalpha = dL/dC . (c Tk - S / (1 - alpha)), S what lies behind
+      const float gc = g0[j] * B.z + g1[j] * B.w + g2[j] * C.x + gd[j] * C.y;
+      const float da = gc * Tk - GS[j] * iom;
+      GS[j] += gc * w;
+      T[j] = Tk;
+      // alpha not clamped: the opacity and the exponent receive gradient
+      const bool free_alpha = act & (B.y * s.G <= kAlphaMax);
+      const float gG = free_alpha ? s.G : 0.0f;
+      const float dp = free_alpha ? a * da : 0.0f;
+      v[5] += gG * da;
+      // the mean's gradient is linear in (sum dp dx, sum dp dy): the conic
+      // (scaled: Q00 dx + Q01 dy = kQ/2 (2 A.z dx + A.w dy)) is applied once
+      // per record after the reduction
+      v[0] += dp * s.dx;
+      v[1] += dp * s.dy;
+      // d power / d(Q00, Q01, Q11) = -(dx^2 / 2, dx dy, dy^2 / 2): the
+      // constant factors are applied after the reduction
+      v[2] += s.dx * s.dx * dp;
+      v[3] += s.dx * s.dy * dp;
+      v[4] += s.dy * s.dy * dp;
+    };
+    const int c_red = bitrev4(lane & 15);  // the value a reduction leaves in this lane
     uint32_t m_next = kOneCell ? 1u : sM[0];  // the next record's cell mask, read a step ahead
     for (int k0 = 0; k0 < nb; k0 += 8) {
       // cell j takes part in a group of 8 positions if one of its pixels
@@ -971,56 +1165,22 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 #pragma unroll
         for (int c = 0; c < 16; ++c) v[c] = 0.0f;
         uint64_t contrib = 0;  // lanes that composited this record in some cell
-        // predicated rather than branched inside a cell: a lane whose pixel
-        // does not use this Gaussian runs with alpha = 0 (1 / (1 - 0) is
-        // exact), which leaves T and S unchanged and adds exact zeros to every
-        // term
-        auto adjoint = [&](const int j) {
-          const Sample s = sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B);
-          const bool act = s.ok & (pos <= last[j]);
-          contrib |= __ballot(act);
-          const float a = act ? s.alpha : 0.0f;
-          const float iom = __builtin_amdgcn_rcpf(1.0f - a);
-          const float Tk = T[j] * iom;  // transmittance in front of this Gaussian
-          const float w = a * Tk;
-          v[6] += g0[j] * w;
-          v[7] += g1[j] * w;
-          v[8] += g2[j] * w;
-          v[9] += gd[j] * w;
-          // dL/dalpha = dL/dC . (c Tk - S / (1 - alpha)), S what lies behind
-          const float gc = g0[j] * B.z + g1[j] * B.w + g2[j] * C.x + gd[j] * C.y;
-          const float da = gc * Tk - GS[j] * iom;
-          GS[j] += gc * w;
-          T[j] = Tk;
-          // alpha not clamped: the opacity and the exponent receive gradient
-          const bool free_alpha = act & (B.y * s.G <= kAlphaMax);
-          const float gG = free_alpha ? s.G : 0.0f;
-          const float dp = free_alpha ? a * da : 0.0f;
-          v[5] += gG * da;
-          // the mean's gradient is linear in (sum dp dx, sum dp dy): the
-          // conic (scaled: Q00 dx + Q01 dy = kQ/2 (2 A.z dx + A.w dy)) is
-          // applied once per record after the reduction
-          v[0] += dp * s.dx;
-          v[1] += dp * s.dy;
-          // d power / d(Q00, Q01, Q11) = -(dx^2 / 2, dx dy, dy^2 / 2): the
-          // constant factors are applied after the reduction
-          v[2] += s.dx * s.dx * dp;
-          v[3] += s.dx * s.dy * dp;
-          v[4] += s.dy * s.dy * dp;
-        };
         // every cell hit: one straight-line block the compiler can interleave
         if (hit == (1u << PPT) - 1u) {
 #pragma unroll
-          for (int j = 0; j < PPT; ++j) adjoint(j);
+          for (int j = 0; j < PPT; ++j)
+            adjoint(j, sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B), true, B, C, pos,
+                    v, contrib);
         } else {
 #pragma unroll
           for (int j = 0; j < PPT; ++j)
-            if (hit & (1u << j)) adjoint(j);
+            if (hit & (1u << j))
+              adjoint(j, sample(lx, ly, lxh, lyh, cell.X0[j], cell.Y0[j], bx, A, B), true, B, C,
+                      pos, v, contrib);
         }
         if (contrib != 0) {
           const float r = wave_reduce10(v);
-          const int c = bitrev4(lane & 15);
-          if (lane < 16 && c < NC) red[wv][k][c] = r;
+          if (lane < 16 && c_red < NC) red[wv][k][c_red] = r;
         } else if (lane < NC) {
           red[wv][k][lane] = 0.0f;
         }
@@ -1046,13 +1206,12 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       s[2] *= -0.5f;
       s[3] = -s[3];
       s[4] *= -0.5f;
-      const uint32_t g = sG[k];
       const float4 C = sC[k];
       const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
       const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
       const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
       const int wc = tx1 - tx0 + 1;
-      const uint32_t slot = pair_off[g] + kept_rank(tmask[g], wc * (ty1 - ty0 + 1),
+      const uint32_t slot = sP[k] + kept_rank(sT[k], wc * (ty1 - ty0 + 1),
                                                     (ty - ty0) * wc + (tx - tx0));
       float2 *pp = partial + 5 * (int64_t)slot;  // ten floats, 40 B per slot
       pp[0] = make_float2(s[0], s[1]);
@@ -1063,7 +1222,6 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) frontier[gt] = (int)rank_of[(uint32_t)pairs[top]];
 }
 
 // Chain the ten screen-space gradient terms s[] of one (view, Gaussian)
@@ -1186,7 +1344,7 @@ __global__ void __launch_bounds__(256)
   // planes are written (as zeros) only for a caller's own output buffer
   if (count[r] == 0 && !zero_undrawn) return;
   if (count[r] > 0) {
-    const float4 C = rec[3 * r + 2];
+    const float4 C = rec[4 * r + 2];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
     const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
     const int ty0 = (int)(by & 0xFFFF) / TH, ty1 = (int)(by >> 16) / TH;
@@ -1323,7 +1481,7 @@ __global__ void __launch_bounds__(256)
     if (l < rg.x) continue;
     walk += (unsigned long long)(l - rg.x + 1);
     for (int p = rg.x; p <= l; ++p) {
-      const float4 C = rec[3 * (int64_t)(uint32_t)pairs[p] + 2];
+      const float4 C = rec[4 * (int64_t)(uint32_t)pairs[p] + 2];
       const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
       inbox += (px >= (int)(bx & 0xFFFF) && px <= (int)(bx >> 16) && py >= (int)(by & 0xFFFF) &&
                 py <= (int)(by >> 16));
@@ -1355,11 +1513,13 @@ __global__ void k_export_rec(const float4 *__restrict__ rec, int64_t RS,
                              float *__restrict__ out, int32_t *__restrict__ box) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float4 A = rec[3 * i], B = rec[3 * i + 1], C = rec[3 * i + 2];
+  const bool cul = count[i] == 0;  // a culled record is never written
+  const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const float4 A = cul ? z : rec[4 * i], B = cul ? z : rec[4 * i + 1],
+               C = cul ? z : rec[4 * i + 2];
   const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
   const int i0 = bx & 0xFFFF, j0 = by & 0xFFFF;
   if (out) {
-    const bool cul = count[i] == 0;
     out[0 * n + i] = cul ? 0.0f : A.x + (float)i0;
     out[1 * n + i] = cul ? 0.0f : A.y + (float)j0;
     out[2 * n + i] = A.z * kQ;         // the conic Q00, Q01, Q11
@@ -1386,6 +1546,11 @@ __global__ void k_copy_u32_as_i32(const uint32_t *__restrict__ a, int64_t n, int
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// Workgroups of a raster launch over nt tiles (a multiple of the 8 XCDs).
+inline int raster_grid(int nt) { return 8 * ((nt + 7) / 8); }
+
+int64_t *counters(dcgs_state *s, hipStream_t st);
+
 __global__ void k_fill_i64(int64_t *__restrict__ a, int64_t n, int64_t v) {
   for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a[i] = v;
 }
@@ -1393,23 +1558,25 @@ __global__ void k_fill_i64(int64_t *__restrict__ a, int64_t n, int64_t v) {
 template <int TW, int TH, int PPT>
 void launch_fwd_t(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *T) {
   const int nt = s->tiles_x * s->tiles_y * s->V;
-  const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
+  const unsigned grid = (unsigned)raster_grid(nt);
   hipLaunchKernelGGL((k_raster_fwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
-                     s->pairs.p, s->ranges.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
+                     s->pairs.p, s->ranges.p, s->torder.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
                      s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], rgb, depth, T,
-                     s->T_final.p, s->last.p);
+                     s->T_final.p, s->last.p, s->bslot.p, s->bound.p);
   DCGS_LAUNCH_CHECK();
 }
 
 template <int TW, int TH, int PPT>
 void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const float *dl_ddepth) {
   const int nt = s->tiles_x * s->tiles_y * s->V;
-  const unsigned grid = 8u * (unsigned)((nt + 7) / 8);
+  // one workgroup per work item (tile segment); the grid is sized for the
+  // most the pair capacity allows, the count is read on the device
+  const unsigned grid = (unsigned)raster_grid((int)s->wcap);
   hipLaunchKernelGGL((k_raster_bwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
-                     s->pairs.p, s->ranges.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
-                     s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], s->T_final.p,
-                     s->last.p, dl_drgb, dl_ddepth, s->pair_off.p, s->rank_of.p, s->tmask.p,
-                     s->partial.p, s->frontier.p);
+                     s->pairs.p, s->ranges.p, s->witem.p, counters(s, st), s->rec.p, s->rs, s->W,
+                     s->H, s->tiles_x, nt, s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2],
+                     s->T_final.p, s->last.p, dl_drgb, dl_ddepth, s->rank_of.p, s->partial.p,
+                     s->frontier.p, s->bslot.p, s->bound.p);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1476,7 +1643,7 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   const int64_t nr = n_grid * V;
   const int64_t HW = (int64_t)s->W * s->H;
   s->rs = nr;
-  s->rec.need(3 * (size_t)nr + 1);
+  s->rec.need(4 * (size_t)nr + 1);
   s->zkey.need(nr + 1);
   s->count.need(nr + 1);
   s->order.need(nr + 1);
@@ -1488,6 +1655,12 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   s->scan.need(nr + 2);
   s->ranges.need(nt + 1);
   s->frontier.need(nt + 1);
+  s->torder.need(4 * (size_t)raster_grid(nt) + 4);  // keys, order, and their sort buffers
+  const size_t gs = (size_t)raster_grid(nt) + 2;
+  s->segc.need(2 * gs);
+  s->segs.need(2 * gs);
+  s->segpart.need(2 * (scan_part_size(raster_grid(nt)) + 2));
+  s->bslot.need(nt + 1);
   s->T_final.need(V * HW + 1);
   s->last.need(V * HW + 1);
   s->scan_part.need(scan_part_size(nr) + 2);
@@ -1558,6 +1731,23 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
     hipLaunchKernelGGL(k_ranges, dim3(blocks_for(nt, 256)), dim3(256), 0, st, s->pairs.p, cnt,
                        nt, s->ranges.p);
     DCGS_LAUNCH_CHECK();
+    // the raster launch order, longest lists first
+    const int grid = raster_grid(nt);
+    uint32_t *key = s->torder.p + grid, *ktmp = key + grid, *vtmp = ktmp + grid;
+    hipLaunchKernelGGL(k_order_keys, dim3(blocks_for(grid, 256)), dim3(256), 0, st, s->ranges.p,
+                       cnt, nt, grid, key, s->torder.p);
+    DCGS_LAUNCH_CHECK();
+    sort_u32_pairs(key, s->torder.p, ktmp, vtmp, grid, kOrderBits, s->hist, st);
+    // the backward's work list: long lists split into segments, in launch order
+    uint32_t *cw = s->segc.p, *cb = cw + grid + 2, *sw = s->segs.p, *sb = sw + grid + 2;
+    hipLaunchKernelGGL(k_seg_count, dim3(blocks_for(grid, 256)), dim3(256), 0, st, s->torder.p,
+                       s->ranges.p, nt, grid, seg_len(s->TW, s->TH), cw, cb);
+    DCGS_LAUNCH_CHECK();
+    scan_u32(cw, nullptr, sw, grid, s->segpart.p, st);
+    scan_u32(cb, nullptr, sb, grid, s->segpart.p + scan_part_size(grid) + 2, st);
+    hipLaunchKernelGGL(k_seg_fill, dim3(blocks_for(grid, 256)), dim3(256), 0, st, s->torder.p, nt,
+                       grid, cw, sw, cb, sb, s->witem.p, s->bslot.p, cnt);
+    DCGS_LAUNCH_CHECK();
   }
   StageTimer tf(ctx, DCGS_STAGE_RASTER_FWD, st);
   launch_fwd(s, st, rgb, depth, T);
@@ -1567,6 +1757,13 @@ void size_pairs(dcgs_state *s, int64_t pcap) {
   s->pairs.need((size_t)pcap + 1);
   s->pairs_tmp.need((size_t)pcap + 1);
   s->partial.need(5 * (size_t)pcap + 5);
+  // a split tile has more than S pairs: at most pcap / S extra work
+  // items, and at most 2 pcap / S boundary states
+  const int64_t nt = (int64_t)s->tiles_x * s->tiles_y * s->V;
+  const int64_t S = seg_len(s->TW, s->TH);
+  s->wcap = nt + pcap / S + 1;
+  s->witem.need((size_t)s->wcap + 8);
+  s->bound.need((size_t)(2 * (pcap / S) + 1) * kStateVals * s->TW * s->TH);
 }
 
 }  // namespace
@@ -1610,7 +1807,8 @@ void render_plan(dcgs_state *s, int64_t n_cap, int64_t pcap) {
   s->pcap = pcap;
   size_buffers(s, n_cap);
   size_pairs(s, pcap);
-  s->hist.need(radix_scratch(std::max(s->rs, pcap)));
+  const int nt = s->tiles_x * s->tiles_y * s->V;
+  s->hist.need(radix_scratch(std::max({s->rs, pcap, (int64_t)raster_grid(nt)})));
 }
 
 bool raster_shape_supported(int tw, int th, int ppt) {

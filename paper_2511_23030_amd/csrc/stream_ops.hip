@@ -1,8 +1,9 @@
 // Streaming kernels of the mapping step for gfx950: compaction of resident
 // chunks into one SoA buffer (Sec. III-E), the per-Gaussian Adam update with
-// scatter back into the resident pool, and the L1 image loss (Eqs. 2-4
-// without SSIM).  All three are HBM-bound: coalesced row-wise access,
-// enough workgroups to fill 256 CUs, no atomics.
+// scatter back into the resident pool (float64 arithmetic, one rounding per
+// stored value), and the L1 image loss (Eqs. 2-4 without SSIM).  All three
+// are HBM-bound: coalesced row-wise access, enough workgroups to fill 256
+// CUs, no atomics.
 #include "internal.h"
 
 namespace dcgs {
@@ -57,17 +58,21 @@ __global__ void __launch_bounds__(256)
   const int64_t page = slot >> L2, k = slot & (PG - 1);
   const int t = step[page * PG + k] + 1;
   step[page * PG + k] = t;
-  const float bc1 = (float)(1.0 - pow((double)a.b1, (double)t));
-  const float bc2 = (float)(1.0 - pow((double)a.b2, (double)t));
+  // float64 arithmetic from the float32 state and gradient, each result
+  // rounded once to float32 (the kernel is bound by its 1.6 KB of traffic
+  // per Gaussian, not by these operations)
+  const double b1 = a.b1, b2 = a.b2, eps = a.eps;
+  const double bc1 = 1.0 - pow(b1, (double)t), bc2 = 1.0 - pow(b2, (double)t);
   const int64_t base = page * R * PG + k;
   for (int r = 0; r < R; ++r) {
-    const float g = grad[r * gs + i];
+    const double g = grad[r * gs + i];
     const int64_t idx = base + (int64_t)r * PG;
-    const float m = a.b1 * M[idx] + (1.0f - a.b1) * g;
-    const float v = a.b2 * V[idx] + (1.0f - a.b2) * g * g;
-    M[idx] = m;
-    V[idx] = v;
-    P[idx] -= a.lr[group_of_row(r)] * (m / bc1) / (sqrtf(v / bc2) + a.eps);
+    const double m = b1 * (double)M[idx] + (1.0 - b1) * g;
+    const double v = b2 * (double)V[idx] + (1.0 - b2) * (g * g);
+    M[idx] = (float)m;
+    V[idx] = (float)v;
+    const double lr = a.lr[group_of_row(r)];
+    P[idx] = (float)((double)P[idx] - lr * (m / bc1) / (sqrt(v / bc2) + eps));
   }
 }
 

@@ -33,6 +33,7 @@ struct dcgs_window {
   int next = 0;
   int64_t overflow = 0;
   dcgs::DevBuf<float> loss_part;
+  dcgs::DevBuf<float> loss_maps;  // the full loss's SSIM maps and partial sums
 };
 
 namespace dcgs {
@@ -63,10 +64,18 @@ void capture(dcgs_window *w, int x) {
     DCGS_HIP(hipMemcpyAsync(s->cam_dev.p, w->staging[x], render_stage_bytes(),
                             hipMemcpyHostToDevice, cs));
     render_forward_planned(s, c.params, c.capacity, c.gmask, cs, c.rgb, c.depth, nullptr);
-    launch_loss_l1(c.rgb, c.targets, (int64_t)c.n_views * 3 * HW, c.loss_norm, c.dl_drgb,
-                   c.stats, w->loss_part.p, cs);
-    render_backward(s, c.params, 0, c.capacity, c.dl_drgb, nullptr, c.grad, c.capacity, 0,
-                    nullptr, cs);
+    const bool full = c.lambda_s > 0.0 || c.lambda_depth > 0.0;
+    const bool with_depth = c.lambda_depth > 0.0;
+    if (full)  // its scratch was sized at creation: no allocation under capture
+      mapping_loss(w->ctx, c.rgb, c.targets, with_depth ? c.depth : nullptr,
+                   with_depth ? c.depth_targets : nullptr, c.n_views, c.height, c.width,
+                   c.lambda_s, c.lambda_depth, c.dl_drgb, with_depth ? c.dl_ddepth : nullptr,
+                   c.stats, w->loss_maps, cs);
+    else
+      launch_loss_l1(c.rgb, c.targets, (int64_t)c.n_views * 3 * HW, c.loss_norm, c.dl_drgb,
+                     c.stats, w->loss_part.p, cs);
+    render_backward(s, c.params, 0, c.capacity, c.dl_drgb, with_depth ? c.dl_ddepth : nullptr,
+                    c.grad, c.capacity, 0, nullptr, cs);
     dcgs_pool *p = w->pool;
     launch_adam(p->d_params, p->d_m, p->d_v, p->d_step, p->R, c.src, c.grad, c.capacity,
                 c.capacity, c.adam, cs, cnt);
@@ -92,7 +101,9 @@ void window_create(dcgs_ctx *ctx, dcgs_pool *pool, const dcgs_window_config *cfg
   DCGS_CHECK(c.n_views >= 1 && c.n_views <= kMaxViews && c.width > 0 && c.height > 0 &&
                  c.width < 65536 && c.height < 65536 && c.capacity > 0 &&
                  c.pair_capacity > 0 && c.pair_capacity < (int64_t(1) << 31) &&
-                 c.sh_degree == pool->deg && c.loss_norm > 0,
+                 c.sh_degree == pool->deg && c.loss_norm > 0 && c.lambda_s >= 0 &&
+                 c.lambda_s <= 1 && c.lambda_depth >= 0 &&
+                 (c.lambda_depth == 0 || (c.depth_targets && c.dl_ddepth)),
              DCGS_E_INVALID, "window_create: bad configuration");
   DCGS_CHECK(c.params && c.grad && c.src && c.gmask && c.rgb && c.depth && c.dl_drgb &&
                  c.targets && c.stats,
@@ -135,6 +146,8 @@ void window_create(dcgs_ctx *ctx, dcgs_pool *pool, const dcgs_window_config *cfg
   render_plan(s, c.capacity, c.pair_capacity);
   s->grad2d.need(10 * (size_t)s->rs + 1);
   w->loss_part.need(2 * 1024);
+  if (c.lambda_s > 0.0 || c.lambda_depth > 0.0)
+    mapping_loss_reserve(c.n_views, c.height, c.width, w->loss_maps);
   DCGS_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
   const size_t sb = ((render_stage_bytes() + 63) / 64) * 64 + 64;
   for (int x = 0; x < 2; ++x) {

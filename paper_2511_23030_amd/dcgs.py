@@ -66,7 +66,8 @@ class WindowConfig(C.Structure):
                 ("adam", AdamConfig), ("params", C.c_void_p), ("grad", C.c_void_p),
                 ("src", C.c_void_p), ("gmask", C.c_void_p), ("rgb", C.c_void_p),
                 ("depth", C.c_void_p), ("dl_drgb", C.c_void_p), ("targets", C.c_void_p),
-                ("stats", C.c_void_p)]
+                ("stats", C.c_void_p), ("lambda_s", C.c_double), ("lambda_depth", C.c_double),
+                ("depth_targets", C.c_void_p), ("dl_ddepth", C.c_void_p)]
 
 
 P = C.c_void_p
@@ -84,6 +85,8 @@ SIGNATURES = {
     "dcgs_chunk_ids": (INT, [P, P, I64, I64, DBL, P, P]),
     "dcgs_select_chunks": (INT, [P, P, INT, P, INT, DBL, P, P, P, P]),
     "dcgs_select_chunks_noalloc": (INT, [P, P, INT, P, INT, DBL, P, P, P, P]),
+    "dcgs_keyframe_overlap": (INT, [P, P, INT, INT, DBL, P, INT, DBL, P, INT, P, P, P, P, INT,
+                                    P, P, P]),
     "dcgs_pool_create": (INT, [P, INT, I64, C.POINTER(P)]),
     "dcgs_pool_destroy": (None, [P]),
     "dcgs_pool_ingest": (INT, [P, P, I64, DBL, P]),
@@ -214,6 +217,32 @@ class Context:
                                             chunk_size, ptr(out_ids), ptr(out_mask), ptr(count),
                                             stream_handle(stream)))
         return out_ids, out_mask, count
+
+    def keyframe_overlap(self, keyframes: list, latest: int, ids, chunk_size: float,
+                         active_ids: np.ndarray, grid: float = 200.0, n_window: int = 0,
+                         stream=None) -> dict:
+        """Keyframe selection quantities (dcgs_keyframe_overlap) for host
+        cameras `keyframes`: in_set (Eq. 8 membership of K(p_latest)),
+        n_visible, n_overlap, overlap (Eq. 7) and, when n_window > 0, the
+        window chosen from the candidate set.  ids: the device chunk grid
+        (int64 tensor of uint64 bit patterns, or a pool's (address, count)
+        from Pool.device_ids()); active_ids: host uint64."""
+        m = len(keyframes)
+        addr, n_ids = ids if isinstance(ids, tuple) else (ptr(ids), ids.numel())
+        arr = (Camera * m)(*[Camera.of(c) for c in keyframes])
+        act = np.ascontiguousarray(np.unique(np.asarray(active_ids, np.uint64)))
+        out = dict(in_set=np.zeros(m, np.uint8), n_visible=np.zeros(m, np.int32),
+                   n_overlap=np.zeros(m, np.int32), overlap=np.zeros(m, np.float64))
+        win = np.zeros(max(n_window, 1), np.int32)
+        nw = I32(0)
+        self.check(lib().dcgs_keyframe_overlap(
+            self.h, C.cast(arr, P), m, int(latest), float(grid), addr, n_ids,
+            float(chunk_size), act.ctypes.data if act.size else None, act.size,
+            out["in_set"].ctypes.data, out["n_visible"].ctypes.data,
+            out["n_overlap"].ctypes.data, out["overlap"].ctypes.data, int(n_window),
+            win.ctypes.data if n_window > 0 else None, C.byref(nw), stream_handle(stream)))
+        out["window"] = win[:nw.value].copy() if n_window > 0 else None
+        return out
 
     STAGES = ("select", "compact", "preprocess", "depth_sort", "scan_emit", "tile_sort",
               "ranges", "raster_fwd", "loss", "raster_bwd", "preprocess_bwd", "adam")
@@ -520,7 +549,9 @@ class Window:
 
     def __init__(self, ctx: "Context", pool: "Pool", sh_degree: int, width: int, height: int,
                  n_views: int, tile, ppt: int, capacity: int, pair_capacity: int, bg, adam,
-                 params, grad, src, gmask, rgb, depth, dl, targets, stats, loss_norm: float):
+                 params, grad, src, gmask, rgb, depth, dl, targets, stats, loss_norm: float,
+                 lambda_s: float = 0.0, lambda_depth: float = 0.0, depth_targets=None,
+                 dl_ddepth=None):
         self.ctx, self.pool = ctx, pool
         c = WindowConfig()
         c.sh_degree, c.width, c.height, c.n_views = sh_degree, width, height, n_views
@@ -528,12 +559,15 @@ class Window:
         c.capacity, c.pair_capacity = int(capacity), int(pair_capacity)
         c.bg[:] = [float(x) for x in bg]
         c.loss_norm = float(loss_norm)
+        c.lambda_s, c.lambda_depth = float(lambda_s), float(lambda_depth)
+        c.depth_targets, c.dl_ddepth = ptr(depth_targets), ptr(dl_ddepth)
         c.adam = adam
         for name, t in (("params", params), ("grad", grad), ("src", src), ("gmask", gmask),
                         ("rgb", rgb), ("depth", depth), ("dl_drgb", dl), ("targets", targets),
                         ("stats", stats)):
             setattr(c, name, ptr(t))
-        self._keep = (params, grad, src, gmask, rgb, depth, dl, targets, stats)
+        self._keep = (params, grad, src, gmask, rgb, depth, dl, targets, stats, depth_targets,
+                      dl_ddepth)
         self.cfg = c
         h = P()
         ctx.check(lib().dcgs_window_create(ctx.h, pool.h, C.byref(c), C.byref(h)))

@@ -86,6 +86,16 @@ class MappingLoop:
                                         dl_out=dl, dld_out=dld, stats=st)
         return g
 
+    def schedule_window(self, keyframes: list, latest: int, n: int, grid: float = 200.0
+                        ) -> np.ndarray:
+        """Keyframe selection of a batching window (dcgs_keyframe_overlap):
+        among the keyframes in the same `grid` cell as keyframe `latest`
+        (the spatial candidate set), the n whose visible chunks are most
+        resident in the pool (chunk overlap), ties to the more recent one."""
+        res = self.ctx.keyframe_overlap(keyframes, latest, self.pool.device_ids(), self.s,
+                                        self.pool.resident()[0], grid=grid, n_window=n)
+        return res["window"]
+
     def select(self, cam: dict) -> np.ndarray:
         """Visible chunk ids of `cam` (host copy; one sync)."""
         return self.select_window([cam])[0]
@@ -197,37 +207,46 @@ class MappingLoop:
         H, W = self.rgb.shape[1], self.rgb.shape[2]
         if getattr(self, "gtargets", None) is None or self.gtargets.shape[0] != V:
             self.gtargets = torch.empty(V, 3, H, W, dtype=torch.float32, device=self.rgb.device)
+            self.gdtargets = torch.empty(V, H, W, dtype=torch.float32, device=self.rgb.device)
         if getattr(self, "win", None) is not None:
             self.win.close()
         ppt = self.ppt or {8: 1, 16: 2}.get(self.tile[0], 4)
         self.win = D.Window(self.ctx, self.pool, self.deg, W, H, V, self.tile, ppt, self.cap,
                             int(pair_capacity), self.bg, self.adam, self.params, self.grad,
                             self.src, self.gmask, self.rgb_v, self.depth_v, self.dl_v,
-                            self.gtargets, self.stats, 3.0 * H * W)
+                            self.gtargets, self.stats, 3.0 * H * W, self.lambda_s,
+                            self.lambda_depth, self.gdtargets, self.dld_v)
         self.win_pairs = int(pair_capacity)
         self._pending = []
         return self.win
 
-    def _launch_graph(self, cams, targets, sel) -> int:
+    def _launch_graph(self, cams, targets, sel, target_depths=None) -> int:
         ids, masks = sel
         self.gtargets.copy_(targets)
+        if self.lambda_depth > 0.0:
+            self.gdtargets.copy_(target_depths)
         return self.win.launch(ids, masks, cams)
 
-    def window_step_graph(self, cams: list, targets: torch.Tensor, sel=None) -> dict:
-        """window_step through the graph-captured window (build_graph first).
-        If a window overflowed its pair capacity (it and every later launch
-        then changed nothing), the window is rebuilt with room for the
-        pairs and the skipped windows run again, in order."""
+    def window_step_graph(self, cams: list, targets: torch.Tensor, sel=None,
+                          target_depths: torch.Tensor | None = None) -> dict:
+        """window_step through the graph-captured window (build_graph first),
+        with the loss the loop was made with (L1, or the full loss with SSIM
+        and, when lambda_depth > 0, the depth term: target_depths then
+        required).  If a window overflowed its pair capacity (it and every
+        later launch then changed nothing), the window is rebuilt with room
+        for the pairs and the skipped windows run again, in order."""
+        if self.lambda_depth > 0.0 and target_depths is None:
+            raise ValueError("the graph's loss has a depth term: target_depths required")
         V = len(cams)
         ids, masks = self.select_window(cams) if sel is None else sel
         loaded, evicted = self.pool.require(ids, now=self.iter)
         try:
-            n = self._launch_graph(cams, targets, (ids, masks))
+            n = self._launch_graph(cams, targets, (ids, masks), target_depths)
         except D.DcgsError as e:
             if e.status != 2:
                 raise
-            n = self._recover_graph(cams, targets, (ids, masks))
-        self._pending = (self._pending + [(cams, targets, (ids, masks))])[-2:]
+            n = self._recover_graph(cams, targets, (ids, masks), target_depths)
+        self._pending = (self._pending + [(cams, targets, (ids, masks), target_depths)])[-2:]
         self.iter += 1
         self.last = dict(n_active=n, n_chunks=int(ids.size), loaded=loaded, evicted=evicted,
                          views=V)
@@ -238,16 +257,16 @@ class MappingLoop:
         recent windows again, in order."""
         redo = self._pending[len(self._pending) - skipped:] if skipped else []
         self.build_graph(V, max(int(need * 1.25) + 1024, 2 * self.win_pairs))
-        for c, t, s_ in redo:
+        for c, t, s_, d_ in redo:
             self.pool.require(s_[0], now=self.iter)
-            self._launch_graph(c, t, s_)
+            self._launch_graph(c, t, s_, d_)
         self._pending = list(redo)
 
-    def _recover_graph(self, cams, targets, sel) -> int:
+    def _recover_graph(self, cams, targets, sel, target_depths=None) -> int:
         need, skipped = self.win.sync()
         self._redo(need, skipped, len(cams))
         self.pool.require(sel[0], now=self.iter)
-        return self._launch_graph(cams, targets, sel)
+        return self._launch_graph(cams, targets, sel, target_depths)
 
     def sync_graph(self):
         """Wait for the graph launches; run again any that overflowed."""

@@ -22,10 +22,10 @@ def room():
     return scenegen.perturb(sc["params"], seed=12), cams
 
 
-def _loop(ctx, params, V):
+def _loop(ctx, params, V, **loss):
     pool = D.Pool(ctx, 3, budget=10**9)
     pool.ingest(params, 2.0)
-    loop = mapping.MappingLoop(ctx, pool, 3, 2.0, 320_000, W, H, (16, 16), ppt=2)
+    loop = mapping.MappingLoop(ctx, pool, 3, 2.0, 320_000, W, H, (16, 16), ppt=2, **loss)
     loop._window_buffers(V)
     return pool, loop
 
@@ -95,6 +95,37 @@ def test_graph_overflow_is_redone_in_order(ctx, room):
     assert loop_b.win_pairs > 2000
     assert torch.equal(loop_a.rgb_v, loop_b.rgb_v)
     _compare_pools(pool_a, pool_b)
+    loop_b.win.close()
+    pool_a.close()
+    pool_b.close()
+
+
+def test_graph_full_loss_matches_eager(ctx, room):
+    """The full mapping loss (SSIM, lambda_s = 0.2, and depth L1, lambda_depth
+    = 0.1) inside the graph: images, the four loss sums and the pool after
+    every window equal the eager batched window bit for bit."""
+    params, cams = room
+    V = 4
+    wins = _windows(cams, V, 3)
+    loss = dict(lambda_s=0.2, lambda_depth=0.1)
+    pool_a, loop_a = _loop(ctx, params, V, **loss)
+    pool_b, loop_b = _loop(ctx, params, V, **loss)
+    loop_b.build_graph(V, pair_capacity=4_000_000)
+    for w, cw in enumerate(wins):
+        tg = _targets(V, 400 + w)
+        td = torch.from_numpy(scenegen.target_image(W, H, seed=500 + w, channels=V) * 4.0).cuda()
+        print(f"case graph full loss window {w}", flush=True)
+        loop_a.window_step(cw, tg, target_depths=td)
+        loop_b.window_step_graph(cw, tg, target_depths=td)
+        loop_b.sync_graph()
+        torch.cuda.synchronize()
+        assert torch.equal(loop_a.rgb_v, loop_b.rgb_v)
+        assert torch.equal(loop_a.depth_v, loop_b.depth_v)
+        assert torch.equal(loop_a.stats, loop_b.stats)
+        assert float(loop_b.stats[2]) > 0 and float(loop_b.stats[3]) > 0
+    _compare_pools(pool_a, pool_b)
+    with pytest.raises(ValueError):
+        loop_b.window_step_graph(wins[0], _targets(V, 600))
     loop_b.win.close()
     pool_a.close()
     pool_b.close()

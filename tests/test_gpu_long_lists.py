@@ -1,0 +1,103 @@
+"""Tiles whose lists are far longer than one backward segment (64 list
+positions per pixel of the tile: 4096 at 8x8, 16384 at 16x16, 32768 at
+32x16): hundreds of thousands of faint, pixel-sized Gaussians in front of
+a 32x32 image, so every tile's list is split for the backward and no pixel
+saturates (each segment's backward starts from the compositing state the
+forward stored at its end).  Images and gradients against the oracle, for
+every raster shape; a two-view window against the per-view path bit for
+bit."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen
+from gpu_helpers import IMG_TOL, SHAPES, assert_grad_close, flagged_pixels, gpu_render
+from oracle import splat as osp
+from paper_2511_23030_amd import dcgs as D
+
+pytestmark = pytest.mark.gpu
+
+SEG_PER_PIXEL = 64
+W = H = 32
+F = 50.0
+
+
+def _dense(n=480_000, seed=50):
+    rng = np.random.default_rng(seed)
+    P = scenegen.tiny_scene(n=n, seed=seed, width=W, height=H, focal=F)["params"].astype(np.float64)
+    Z = rng.uniform(3.0, 4.0, n)
+    P[0] = rng.uniform(-0.5, 0.5, n) * (W / F) * Z
+    P[1] = rng.uniform(-0.5, 0.5, n) * (H / F) * Z
+    P[2] = Z
+    P[3:6] = np.log(0.004) + rng.normal(0.0, 0.2, (3, n))
+    P[10] = rng.normal(-5.0, 0.25, n)          # opacity ~ 0.007: far from saturating
+    return P.astype(np.float32)
+
+
+def _cam(shift=0.0):
+    return scenegen.camera(np.eye(3), np.array([shift, 0.0, 0.0]), F, F, W / 2.0, H / 2.0, W, H)
+
+
+def test_split_lists_images_and_gradients(ctx):
+    P = _dense()
+    cam = _cam()
+    bg = np.array([0.2, 0.1, 0.3])
+    rec = osp.preprocess(P, 0, cam, requires_grad=True)
+    img = osp.composite(rec, bg)
+    flag = flagged_pixels(img)
+    print(f"case long lists: {flag.sum()} of {flag.size} pixels within rounding reach of a "
+          f"threshold, excluded", flush=True)
+    assert flag.sum() <= 0.05 * flag.size           # ~700 Gaussians reach each pixel
+    assert img.T.detach().numpy().min() > 1e-3      # nothing saturates: every segment matters
+    dl = scenegen.upstream_grad(W, H, seed=51, scale=1e-3)
+    dld = scenegen.upstream_grad(W, H, seed=52, channels=1, scale=1e-4)[0]
+    dl[:, flag] = 0.0
+    dld[flag] = 0.0
+    gr = osp.render_grad(rec, img, dl, dld)
+    vis = ~rec.culled
+    imgs = []
+    for shape in SHAPES:
+        g = gpu_render(ctx, P, 0, cam, bg, shape[:2], dl, dld, ppt=shape[2])
+        lens = g["ranges"][:, 1] - g["ranges"][:, 0]
+        seg = SEG_PER_PIXEL * shape[0] * shape[1]
+        print(f"case long lists shape={shape}: longest list {lens.max()}, "
+              f"{int((lens > seg).sum())} of {lens.size} tiles split", flush=True)
+        assert lens.max() > 2 * seg
+        ok = ~flag
+        assert np.abs(g["rgb"] - img.rgb.detach().numpy())[:, ok].max() <= IMG_TOL
+        assert np.abs(g["T"] - img.T.detach().numpy())[ok].max() <= IMG_TOL
+        imgs.append(g["rgb"])
+        g2 = g["grad2d"]
+        assert_grad_close(g2[0:2], gr.uv.T, "d(u,v)", vis)
+        assert_grad_close(g2[2:5], gr.conic.T, "d conic", vis)
+        assert_grad_close(g2[5:6], gr.opacity[None], "d opacity", vis)
+        assert_grad_close(g2[6:9], gr.rgb.T, "d colour", vis)
+        assert_grad_close(g2[9:10], gr.z[None], "d depth", vis)
+        colour_ok = vis & (rec.raw_rgb_margin > 1e-5)
+        assert_grad_close(g["grad"][0:3], gr.params[0:3], "d mean", colour_ok)
+        assert_grad_close(g["grad"][3:11], gr.params[3:11], "d scale, rotation, opacity", vis)
+        assert_grad_close(g["grad"][11:], gr.params[11:], "d SH", colour_ok)
+    for other in imgs[1:]:
+        assert (other == imgs[0]).all()             # the forward is not split: bitwise
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 4), (8, 8, 1)])
+def test_split_lists_batched_equals_per_view(ctx, shape):
+    P = torch.from_numpy(_dense(seed=53)).cuda()
+    n = P.shape[1]
+    cams = [_cam(0.0), _cam(0.02)]
+    rng = np.random.default_rng(54)
+    dl = torch.from_numpy((rng.normal(size=(2, 3, H, W)) * 1e-3).astype(np.float32)).cuda()
+    st_b = D.RenderState(ctx)
+    rgb_b, depth_b = st_b.forward(P, n, 0, cams, (0.1, 0.1, 0.1), shape[:2], ppt=shape[2])
+    grad_b = st_b.backward(P, n, dl, None)
+    st_s = D.RenderState(ctx)
+    grad_s = torch.empty_like(grad_b)
+    for v in range(2):
+        rgb, depth = st_s.forward(P, n, 0, cams[v], (0.1, 0.1, 0.1), shape[:2], ppt=shape[2])
+        assert torch.equal(rgb, rgb_b[v]) and torch.equal(depth, depth_b[v])
+        st_s.backward(P, n, dl[v].contiguous(), None, grad_s, accumulate=v > 0)
+    torch.cuda.synchronize()
+    assert torch.equal(grad_b[:, :n], grad_s[:, :n])
+    st_b.close()
+    st_s.close()
