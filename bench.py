@@ -2,9 +2,13 @@
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload indoor-2m]
 
-One step = one full mapping iteration for one keyframe (visible-chunk
-selection, residency, compaction, projection, depth and tile sorts, raster
-forward, L1 loss, raster backward, projection backward, Adam into the pool).
+One step = one batched mapping window: one pass of the whole hot path over a
+window of 16 keyframes (visible-chunk selection, residency, compaction,
+projection, depth and tile sorts, raster forward, L1 loss, raster backward,
+projection backward, one Adam step into the pool).  K steps are timed after
+W untimed ones, on each path (graph-replayed, eager batched, sequential);
+the plain path (one Adam step per keyframe) runs the same number of
+keyframes.  The metric counts iterations as keyframe views (16 per step).
 Inputs are resident in HBM before the timed region.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -32,7 +36,7 @@ WORKLOADS = {
     # room, SH degree 3, 2 m chunks, 1200x680 views (fx = fy = 600) along a
     # smooth random walk, z_far = 5 m (about 19 of 57 chunks per keyframe).
     "indoor-2m": dict(n=5_750_000, deg=3, chunk=2.0, W=1200, H=680, f=600.0, z_far=5.0,
-                      frames=400, every=8),
+                      frames=1000, every=8),
     # The same room with 1.5M Gaussians (the indoor configuration as stated).
     "indoor-1.5m": dict(n=1_500_000, deg=3, chunk=2.0, W=1200, H=680, f=600.0, z_far=5.0,
                         frames=400, every=8),
@@ -86,8 +90,6 @@ def measured_traffic(workload: str, kernel: str, instance: str | None = None):
     another instance of the kernel (template arguments: the raster shape),
     or when the kernel's source changed since the counters were taken."""
     import json
-
-    from paper_2511_23030_amd import profsummary
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -96,9 +98,16 @@ def measured_traffic(workload: str, kernel: str, instance: str | None = None):
     if instance is not None and t.get("kernel_regex") != instance:
         return None
     src = os.path.join(ROOT, t["source"])
-    if not os.path.exists(src) or profsummary.source_digest(src) != t["source_sha256"]:
+    if not os.path.exists(src) or source_digest(src) != t["source_sha256"]:
         return None
     return t["bytes_per_launch"]
+
+
+def source_digest(path: str) -> str:
+    """SHA-256 of a source file (ties a counter summary to the kernel it measured)."""
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 # Algorithmic HBM bytes per launch of each streaming stage (SH degree 3:
@@ -116,49 +125,73 @@ def stage_bytes(stage: str, N: float, P: float, Npx: float, R: int) -> float:
     }.get(stage, 0.0)
 
 
-# FP32 operations per (pixel, Gaussian) evaluation of the raster kernels,
-# counted from the kernels' arithmetic (an FMA counts 2, exp counts 1);
+# FP32 operations per (pixel, Gaussian) evaluation of the raster kernels:
+# about 25 and one exponential forward, 70 and one exponential backward
+# (the algorithm's operation count, not the kernels' instruction mix);
 # evaluations are counted inside the Gaussian's pixel box only.
-RASTER_FLOPS = {"raster_fwd": 30.0, "raster_bwd": 80.0}
+RASTER_FLOPS = {"raster_fwd": 26.0, "raster_bwd": 71.0}
+
+# Algorithmic HBM bytes of the splatting forward and backward of one view
+# (projection, sorts, pair emission, ranges, both rasters, projection
+# backward; SH degree 3): per active Gaussian 236 read + 52 written by the
+# projection, 24 of the scan, 40 screen-space gradients, 236 + 40 read and
+# 236 written by the projection backward; per (tile, Gaussian) pair 12
+# emitted, 24 sorted, 8 of ranges, 40 gathered forward and 40 backward; per
+# pixel 24 written forward and 36 read backward.
+SPLAT_BYTES = {"per_gaussian": 864.0, "per_pair": 124.0, "per_pixel": 60.0}
+SPLAT_STAGES = ("preprocess", "depth_sort", "scan_emit", "tile_sort", "ranges", "raster_fwd",
+                "raster_bwd", "preprocess_bwd")
 
 
-def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray, budget_s: float = 20.0) -> dict:
-    """The FP64 oracle timed on the host on a bounded sample of one mapping
-    iteration: projection forward+backward of 1/16 of the active Gaussians
-    and compositing forward+backward of a 48x48 pixel crop at the image
-    centre, each scaled to the whole iteration."""
-    import torch
-
-    from oracle import chunks as oc
+def _oracle_sample(w: dict, cam: dict, Pa: np.ndarray, every: int, c: int) -> tuple:
+    """Seconds of one mapping iteration of the FP64 oracle, extrapolated
+    from projection fwd+bwd of 1/every of the active Gaussians and
+    compositing fwd+bwd of a c x c crop at the image centre."""
     from oracle import splat as osp
-    P = w["start"]
-    cid = oc.encode_id(oc.chunk_coord(P[0:3].T, w["chunk"]))
-    act = np.isin(cid, ids_active)
-    Pa = P[:, act]
     n_act = Pa.shape[1]
-    sub = Pa[:, ::16]
+    sub = Pa[:, ::every]
     t0 = time.perf_counter()
     rec = osp.preprocess(sub, w["deg"], cam, requires_grad=True)
     (rec.u.sum() + rec.v.sum() + rec.conic.sum() + rec.rgb.sum() + rec.opacity.sum()).backward()
     t_pre = (time.perf_counter() - t0) * (n_act / sub.shape[1])
-    W, H, c = w["W"], w["H"], 48
+    W, H = w["W"], w["H"]
     crop = (W // 2 - c // 2, W // 2 + c // 2, H // 2 - c // 2, H // 2 + c // 2)
-    t0 = time.perf_counter()
     rec = osp.preprocess(Pa, w["deg"], cam, requires_grad=True)
-    t_full_pre = time.perf_counter() - t0
     t0 = time.perf_counter()
     img = osp.composite(rec, np.zeros(3), crop)
     dl = np.ones((3, c, c)) / (3 * W * H)
     osp.render_grad(rec, img, dl)
     t_crop = time.perf_counter() - t0
     t_iter = t_pre + t_crop * (W * H) / (c * c)
-    return {"value": 1.0 / t_iter, "unit": "iters/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": (f"FP64 oracle on one keyframe of the workload ({n_act} active Gaussians): "
-                       f"projection fwd+bwd of 1/16 of them scaled x16 ({t_pre:.1f} s) plus "
-                       f"compositing fwd+bwd of a {c}x{c} crop scaled to {W}x{H} "
-                       f"({t_crop:.2f} s x {W * H / (c * c):.0f}); the crop's projection "
-                       f"({t_full_pre:.1f} s) is not counted twice")}
+    desc = (f"projection fwd+bwd of 1/{every} of the {n_act} active Gaussians scaled x{every} "
+            f"({t_pre:.1f} s) plus compositing fwd+bwd of a {c}x{c} crop scaled to {W}x{H} "
+            f"({t_crop:.2f} s x {W * H / (c * c):.0f})")
+    return t_iter, desc
+
+
+def cpu_baseline(w: dict, cam: dict, ids_active: np.ndarray) -> dict:
+    """The FP64 oracle timed on the host on a bounded sample of one mapping
+    iteration of one keyframe, with all threads and again on one core."""
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    from oracle import chunks as oc
+    P = w["start"]
+    cid = oc.encode_id(oc.chunk_coord(P[0:3].T, w["chunk"]))
+    Pa = P[:, np.isin(cid, ids_active)]
+    t_all, desc = _oracle_sample(w, cam, Pa, 16, 48)
+    threads = torch.get_num_threads()
+    n0 = torch.get_num_threads()
+    try:
+        torch.set_num_threads(1)
+        with threadpool_limits(limits=1):
+            t_one, desc1 = _oracle_sample(w, cam, Pa, 64, 24)
+    finally:
+        torch.set_num_threads(n0)
+    return {"value": 1.0 / t_all, "unit": "iters/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle on one keyframe of the workload: {desc}",
+            "one_core": {"value": 1.0 / t_one, "unit": "iters/s", "cores": 1,
+                         "sample": f"the same with torch and BLAS held to one thread: {desc1}"}}
 
 
 def prefetch_study(ctx, w, make_loop, targets, n_walk, log) -> dict:
@@ -231,6 +264,122 @@ def prefetch_study(ctx, w, make_loop, targets, n_walk, log) -> dict:
         pool.close()
         del loop
     rep["plain_keyframes"] = n_walk
+    return rep, net
+
+
+def window_prefetch_study(w, make_loop, targets, net, n_windows, V, shape, pair_cap, log) -> dict:
+    """The graph-replayed batched path over the driving walk, three ways,
+    each from a fresh pool over the same windows: no staging ahead (chunks
+    a window needs are loaded when it is required), staging the prefetch
+    network's predictions from the last 8 poses at each window's newest
+    keyframe, staging the next window's exact selection.  The staging
+    changes no arithmetic, so all three leave identical pools and images
+    (the rendered PSNR of the last window is reported for each)."""
+    import torch
+    cams_all, every = w["cams_all"], w["every"]
+    n_windows = min(n_windows, len(cams_all) // V - 2)
+    K = len(targets)
+    tcache = {}
+
+    def tstack(j):
+        if j % (K // V) not in tcache:
+            i0 = (j % (K // V)) * V
+            tcache[j % (K // V)] = torch.stack([targets[i] for i in range(i0, i0 + V)])
+        return tcache[j % (K // V)]
+
+    def walk(loop, mode, j0, n):
+        sel = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(j0, j0 + n):
+            loop.window_step_graph(cams_all[j * V:(j + 1) * V], tstack(j), sel=sel)
+            sel = None
+            if mode == "exact":
+                sel = loop.prefetch_window(cams_all[(j + 1) * V:(j + 2) * V])
+            elif mode == "mlp":
+                k = (j + 1) * V - 1
+                loop.prefetch_predicted(net, [w["all_cams"][max(k * every - h, 0)]
+                                              for h in range(8)])
+        loop.sync_graph()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    rep = {"windows": n_windows, "views": n_windows * V}
+    keys = ("loads", "misses", "hits", "prefetched", "evictions", "bytes_h2d")
+    for mode in ("none", "mlp", "exact"):
+        pool, loop = make_loop()
+        loop.tile, loop.ppt = shape[:2], shape[2]
+        loop.build_graph(V, pair_cap)
+        walk(loop, mode, 0, 2)                 # warm: the first windows' chunks and the graph
+        s0 = pool.stats()
+        t = walk(loop, mode, 2, n_windows)
+        s1 = pool.stats()
+        st = {k: s1[k] - s0[k] for k in keys}
+        # PSNR of the last window's views after the walk
+        j = 1 + n_windows
+        cams = cams_all[j * V:(j + 1) * V]
+        ids, masks = loop.select_window(cams)
+        loop.pool.require(ids, now=loop.iter)
+        n = loop.pool.compact(ids, loop.params, loop.src, masks=masks, out_gmask=loop.gmask)
+        loop.state.forward(loop.params, n, w["deg"], cams, (0, 0, 0), shape[:2], loop.rgb_v,
+                           loop.depth_v, ppt=shape[2], gmask=loop.gmask)
+        loop.ctx.loss_l1(loop.rgb_v, tstack(j), loop.dl_v, loop.stats, norm=3.0 * w["W"] * w["H"])
+        sse = float(loop.stats.cpu().numpy()[1])
+        psnr = 10 * math.log10(1.0 / (sse / (V * 3 * w["W"] * w["H"])))
+        rep[f"batched_{mode}_views_per_s"] = round(n_windows * V / t, 3)
+        rep[f"batched_{mode}_pool"] = st
+        rep[f"batched_{mode}_psnr_db"] = round(psnr, 6)
+        log(f"batched graph, prefetch {mode}: {n_windows * V / t:.1f} views/s over {n_windows} "
+            f"windows, pool {st}, PSNR {psnr:.4f}")
+        loop.win.close()
+        pool.close()
+        del loop
+    return rep
+
+
+def schedule_study(w, make_loop, targets, n_win, V, log) -> dict:
+    """Keyframe selection of the batching windows on the driving corridor
+    (keyframes arrive every 2 m; after every V new ones a batched window
+    runs): the V newest keyframes ("consecutive"), or the V keyframes of the
+    newest keyframe's 200 m cell whose visible chunks are most resident in
+    the pool ("scheduled", dcgs_keyframe_overlap).  Each from a fresh pool
+    over the same arrivals; window steps are timed, the scheduling call
+    apart."""
+    import torch
+    cams = w["cams"]
+    n_win = min(n_win, len(cams) // V)
+    rep = {"windows": n_win}
+    keys = ("loads", "misses", "hits", "evictions", "bytes_h2d")
+    for mode in ("consecutive", "scheduled"):
+        pool, loop = make_loop()
+        t_step, t_sched, views, sizes = 0.0, 0.0, 0, []
+        s0 = pool.stats()
+        for j in range(n_win):
+            latest = (j + 1) * V - 1
+            if mode == "consecutive":
+                win = list(range(j * V, latest + 1))
+            else:
+                t0 = time.perf_counter()
+                win = loop.schedule_window(cams[:latest + 1], latest, V).tolist()
+                t_sched += time.perf_counter() - t0
+            tgt = torch.stack([targets[i] for i in win])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            loop.window_step([cams[i] for i in win], tgt)
+            torch.cuda.synchronize()
+            t_step += time.perf_counter() - t0
+            views += len(win)
+            sizes.append(len(win))
+        s1 = pool.stats()
+        st = {k: s1[k] - s0[k] for k in keys}
+        rep[mode] = {"views_per_s": round(views / t_step, 2), "views": views, "pool": st,
+                     "loads_per_window": round(st["loads"] / n_win, 2)}
+        if mode == "scheduled":
+            rep[mode]["schedule_ms_per_window"] = round(1e3 * t_sched / n_win, 3)
+            rep[mode]["window_sizes"] = sizes
+        log(f"windows {mode}: {views / t_step:.1f} views/s, pool {st}")
+        pool.close()
+        del loop
     return rep
 
 
@@ -306,8 +455,9 @@ def next_rows(ctx, w, loop, tstack, V, log) -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
-    ap.add_argument("--steps", type=int, default=64, help="keyframe views timed per path")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed windows per path")
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps per path; a step is one batched window of --window keyframes")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed steps (windows) per path")
     ap.add_argument("--window", type=int, default=16, help="keyframes per batched window")
     ap.add_argument("--workload", default="indoor-2m", choices=sorted(WORKLOADS))
     ap.add_argument("--tile", default="auto", help="WxH, or auto (autotuner)")
@@ -351,9 +501,12 @@ def main():
 
     V = args.window
     walk = w["walk"]
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
     if walk:
         # the camera only moves forward: warmup windows, then the timed ones
-        n_win = args.warmup + -(-max(args.steps, V) // V)
+        n_win = args.warmup + args.steps
         w["cams_all"] = w["cams"]
         w["cams"] = w["cams"][:n_win * V]
     K = len(w["cams"])
@@ -458,7 +611,7 @@ def main():
         args.ppt = tuned[2]
         log(f"autotuned raster shape {tuned} ({tuned1} for one view); fwd+bwd ms per shape "
             f"{[round(t, 2) for t in tune_ms]}")
-    n_views = max(args.steps, V)
+    n_views = args.steps * V
     run(loop_b, "batched", args.warmup * V)
     run(loop_s, "sequential", args.warmup * V)
     # graph window sized from the pair counts seen so far (it grows itself
@@ -466,12 +619,21 @@ def main():
     pairs_seen = loop_b.state.info()["n_pairs"]
     loop_g.build_graph(V, int(pairs_seen * 1.5) + 4096)
     run(loop_g, "graph", args.warmup * V)
-    log(f"setup {time.perf_counter() - t_setup:.1f} s; timing {n_views} views per path")
+    log(f"setup {time.perf_counter() - t_setup:.1f} s; timing {args.steps} windows "
+        f"({n_views} views) per path")
+    # the eager batched path runs with the stage timers on (HIP events on
+    # the launch stream around each kernel): the dominant kernel's average
+    # launch time below comes from these timed windows
+    k_timed0 = cursor.get("batched", (0, None))[0]
+    ctx.profile(True)
     t_b = run(loop_b, "batched", n_views)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    timed_windows = [k % len(windows) for k in range(k_timed0, k_timed0 + args.steps)]
     t_s = run(loop_s, "sequential", n_views)
     t_g = run(loop_g, "graph", n_views)
     pool_stats = pool_g.stats()
-    n_timed = ((n_views + V - 1) // V) * V
+    n_timed = n_views
     dt = t_g
     # equal-PSNR check: every pool received the same windows, so the same update
     psnrs = {}
@@ -496,8 +658,8 @@ def main():
     for p_ in (pool_s, pool_g):
         p_.close()
     del loop_s, loop_g
-    # the paper's schedule: one Adam step per keyframe
-    n_plain = max(args.steps // 2, 8)
+    # the paper's schedule: one Adam step per keyframe, as many keyframes
+    n_plain = n_views
     if tuned1 is not None:
         loop_b.tile, loop_b.ppt = tuned1[:2], tuned1[2]
     t_p = run(loop_b, "plain", n_plain)
@@ -505,27 +667,25 @@ def main():
     l1, psnr = loop_b.loss_psnr(3 * w["W"] * w["H"])
     prefetch_report = None
     if walk and not args.no_prefetch_mlp:
-        prefetch_report = prefetch_study(ctx, w, make_loop, targets, max(n_plain, 400), log)
+        prefetch_report, net = prefetch_study(ctx, w, make_loop, targets, max(n_plain, 400), log)
+        prefetch_report["window"] = window_prefetch_study(
+            w, make_loop, targets, net, max(args.steps, 20), V, (tw, th, args.ppt),
+            int(pairs_seen * 1.5) + 4096, log)
+    schedule_report = None
+    if walk:
+        schedule_report = schedule_study(w, make_loop, targets, args.steps, V, log)
 
-    # stage profile of the batched path, outside the timed region
+    # work of the timed windows, measured after the timing on the same
+    # windows: active Gaussians (the window's union and the sum over views
+    # of each view's own set), pairs, positions the compositing walks, and
+    # the (pixel, Gaussian) evaluations inside the Gaussian's pixel box (the
+    # ones no raster kernel can skip)
     if tuned is not None:
         loop_b.tile, loop_b.ppt = tuned[:2], tuned[2]
-    ctx.profile(True)
-    Ns, Ps, Es, Ews = [], [], [], []
-    for k in range(args.profile_steps):
-        wi = k % len(windows)
-        cams = [w["cams"][i] for i in windows[wi]]
-        loop_b.window_step(cams, tstack[wi])
-        Ns.append(loop_b.last["n_active"])
-        Ps.append(loop_b.state.info()["n_pairs"])
-    torch.cuda.synchronize()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    # work of the profiled windows, measured after the timing: positions the
-    # compositing walks, and the (pixel, Gaussian) evaluations inside the
-    # Gaussian's pixel box (the ones no raster kernel can skip)
-    for k in range(args.profile_steps):
-        wi = k % len(windows)
+    chunk_ids, chunk_counts = loop_b.pool.chunks()
+    count_of = dict(zip(chunk_ids.tolist(), chunk_counts.tolist()))
+    Ns, NVs, Ps, Es, Ews = [], [], [], [], []
+    for wi in timed_windows:
         cams = [w["cams"][i] for i in windows[wi]]
         ids, masks = loop_b.select_window(cams)
         loop_b.pool.require(ids, now=loop_b.iter)
@@ -533,10 +693,15 @@ def main():
         loop_b.state.forward(loop_b.params, n, w["deg"], cams, (0, 0, 0), (tw, th), loop_b.rgb_v,
                              loop_b.depth_v, ppt=args.ppt, gmask=loop_b.gmask)
         walked, inbox = loop_b.state.work()
+        Ns.append(n)
+        NVs.append(sum(bin(int(m) & 0xFFFF).count("1") * count_of[int(i)]
+                       for i, m in zip(ids.tolist(), masks.tolist())))
+        Ps.append(loop_b.state.info()["n_pairs"])
         Ews.append(walked)
         Es.append(inbox)
-    N, Pp, E, Npx = float(np.mean(Ns)), float(np.mean(Ps)), float(np.mean(Es)), w["W"] * w["H"] * V
-    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items()}
+    N, NV, Pp, E = (float(np.mean(x)) for x in (Ns, NVs, Ps, Es))
+    Npx = w["W"] * w["H"] * V
+    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
     dominant = max(stages, key=stages.get)
     avg_ms = stages[dominant]
     # pixels per lane of the forward (bits 0-3) and backward (bits 4-7) rasters
@@ -547,12 +712,26 @@ def main():
         achieved = RASTER_FLOPS[dominant] * E / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(args.workload, dominant, inst), "kernel": inst}
+                "traffic": measured_traffic(args.workload, dominant, inst), "kernel": inst,
+                "avg_ms": round(avg_ms, 4), "flop_per_evaluation": RASTER_FLOPS[dominant],
+                "evaluations_per_launch": round(E)}
     else:
         achieved = stage_bytes(dominant, N, Pp, Npx, R) / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant}
+                "traffic": measured_traffic(args.workload, dominant), "kernel": dominant,
+                "avg_ms": round(avg_ms, 4)}
+    # the batched splatting forward + backward against the HBM roofline:
+    # algorithmic bytes of every view's plain splatting over the measured
+    # time of the window's splatting stages
+    splat_ms = sum(stages.get(k, 0.0) for k in SPLAT_STAGES)
+    splat_bytes = (SPLAT_BYTES["per_gaussian"] * NV + SPLAT_BYTES["per_pair"] * Pp +
+                   SPLAT_BYTES["per_pixel"] * Npx)
+    splat_gbs = splat_bytes / (splat_ms * 1e-3) / 1e9
+    splat_hbm = {"algorithmic_bytes_per_window": round(splat_bytes), "ms_per_window": round(splat_ms, 3),
+                 "achieved_GBs": round(splat_gbs, 1), "peak_GBs": HBM_PEAK_GBS,
+                 "frac": round(splat_gbs / HBM_PEAK_GBS, 4), "stages": list(SPLAT_STAGES),
+                 "gaussians_summed_over_views": round(NV), "pairs": round(Pp), "pixels": Npx}
     loop = loop_b
 
     cpu = None
@@ -576,16 +755,20 @@ def main():
         f"fwd+bwd splat mapping iters/s @{w['W']}x{w['H']}, {args.workload}; batched vs plain")
     out = {
         "metric": metric, "value": round(n_timed / dt, 3), "unit": "iters/s", "n_gpus": 1,
-        "steps": n_timed, "warmup": args.warmup * V, "ms_per_step": round(1e3 * dt / n_timed, 3),
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {scene} {w['n']} Gaussians SH{w['deg']}, "
                                f"{w['W']}x{w['H']}, {w['chunk']:g} m chunks, device budget "
                                f"{min(w['budget'], w['n'])} Gaussians, tile {tw}x{th}, "
                                f"{ppt_f} px/lane forward, {ppt_b} backward; value = graph-replayed batched "
-                               f"windows of {V} keyframes (one iteration = one keyframe view)",
+                               f"windows of {V} keyframes (one step = one window, one iteration "
+                               f"= one keyframe view)",
+                   "views_per_step": V, "timed_views": n_timed,
                    "pool_batched": pool_stats,
-                   "active_gaussians_per_window_mean": round(N), "pairs_per_window_mean": round(Pp),
+                   "active_gaussians_per_window_mean": round(N),
+                   "active_gaussians_summed_over_views_mean": round(NV),
+                   "pairs_per_window_mean": round(Pp),
                    "evaluations_per_window_mean": round(E),
                    "walked_positions_per_window_mean": round(float(np.mean(Ews))),
                    "graph_views_per_s": round(n_timed / t_g, 3),
@@ -596,11 +779,13 @@ def main():
                    "psnr_graph_db": round(psnr_g, 4),
                    "psnr_delta_db": round(max(abs(psnr_b - psnr_s), abs(psnr_g - psnr_s)), 6),
                    "prefetch": prefetch_report,
+                   "keyframe_schedule": schedule_report,
                    "next_rows": extra_rows,
                    "raster_shape": [tw, th, ppt_f, ppt_b],
                    "raster_shape_one_view": None if tuned1 is None else list(tuned1),
                    "autotune_ms": [round(t, 3) for t in tune_ms]},
         "roofline": roof,
+        "splat_fwd_bwd_hbm": splat_hbm,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "l1": round(l1, 5), "psnr_db": round(psnr, 3),
