@@ -164,7 +164,9 @@ struct dcgs_state {
   dcgs::DevBuf<int2> witem;        // (tile, segment) per backward workgroup
   dcgs::DevBuf<int> bslot;         // per tile: first boundary-state slot, -1 if not split
   dcgs::DevBuf<float> bound;       // per slot: T, colour, depth of every pixel of the tile
+  dcgs::DevBuf<float> fseg;        // per slot of a forward-split tile: product, last, how it ended
   int64_t wcap = 0;                // work items the backward grid is sized for
+  int64_t fcap = 0;                // work items of forward-split tiles the forward grids cover
   // per pixel
   dcgs::DevBuf<float> T_final;
   dcgs::DevBuf<int> last;
@@ -172,6 +174,7 @@ struct dcgs_state {
   dcgs::DevBuf<uint32_t> hist;
   dcgs::DevBuf<float> grad2d;  // [10][n] when the caller passes none
   dcgs::DevBuf<uint32_t> scan_part;  // block totals of the pair-count scan
+  dcgs::DevBuf<unsigned long long> rank_part;  // 64-bit pair-count sums per k_rank workgroup
 };
 
 struct HostChunk {

@@ -405,14 +405,14 @@ __global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_
 
 // Depth rank of every record, and the records' pair counts in depth order
 // (what the pair-offset scan sums, read once here instead of gathered by it).
-// The pair total is summed here in 64 bits (cnt[5], zeroed before): the
-// 32-bit scan of the counts wraps beyond 2^32 pairs, and the overflow
-// decision must see the true count.
+// Each workgroup also writes the 64-bit sum of its counts; k_pairs_total
+// adds those up: the 32-bit scan of the counts wraps beyond 2^32 pairs, and
+// the overflow decision must see the true count.
 constexpr int kRankThreads = 256;
 __global__ void __launch_bounds__(kRankThreads)
     k_rank(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
-           int64_t *__restrict__ cnt, uint32_t *__restrict__ rank_of,
-           uint32_t *__restrict__ count_sorted) {
+           const int64_t *__restrict__ cnt, uint32_t *__restrict__ rank_of,
+           uint32_t *__restrict__ count_sorted, unsigned long long *__restrict__ part_sum) {
   __shared__ unsigned long long part[kRankThreads / kWave];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c = 0;
@@ -429,17 +429,31 @@ __global__ void __launch_bounds__(kRankThreads)
   if (threadIdx.x == 0) {
     unsigned long long s = 0;
     for (int w = 0; w < kRankThreads / kWave; ++w) s += part[w];
-    if (s != 0) atomicAdd(reinterpret_cast<unsigned long long *>(cnt + 5), s);
+    part_sum[blockIdx.x] = s;
   }
 }
 
-// cnt[2] = pairs to process; cnt[3] = the 64-bit total (cnt[5]) when it
-// overflows (pairs_overflow: beyond the pair capacity or 2^31 - 1, or any
-// earlier window of this state overflowed, cnt[4] sticky), else 0.  Every
-// later kernel of the window does nothing when cnt[3] != 0.
-__global__ void k_pairs_total(int64_t *__restrict__ cnt, int64_t pcap) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int64_t total = cnt[5];
+// One workgroup: cnt[5] = the 64-bit pair total (the sum of k_rank's
+// per-workgroup sums, in a fixed order); cnt[2] = pairs to process; cnt[3] =
+// the total when it overflows (pairs_overflow: beyond the pair capacity or
+// 2^31 - 1, or any earlier window of this state overflowed, cnt[4] sticky),
+// else 0.  Every later kernel of the window does nothing when cnt[3] != 0.
+constexpr int kTotalThreads = 1024;
+__global__ void __launch_bounds__(kTotalThreads)
+    k_pairs_total(const unsigned long long *__restrict__ part_sum, int64_t *__restrict__ cnt,
+                  int64_t pcap) {
+  __shared__ unsigned long long wsum[kTotalThreads / kWave];
+  const int64_t nb = (cnt[1] + kRankThreads - 1) / kRankThreads;
+  unsigned long long s = 0;
+  for (int64_t b = threadIdx.x; b < nb; b += kTotalThreads) s += part_sum[b];
+  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) wsum[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  unsigned long long t = 0;
+  for (int w = 0; w < kTotalThreads / kWave; ++w) t += wsum[w];
+  const int64_t total = (int64_t)t;
+  cnt[5] = total;
   const bool over = pairs_overflow(total, pcap, cnt[4]);
   cnt[2] = over ? 0 : total;
   cnt[3] = over ? (total > 0 ? total : 1) : 0;
@@ -519,10 +533,13 @@ __global__ void k_ranges(const uint64_t *__restrict__ pairs, const int64_t *__re
 // length of each tile's list, longest first: the few long lists (the
 // vanishing point of a road holds 100 times the median) start at once
 // instead of ending the launch alone, and within a length class the XCD
-// bands are kept.  Padding blocks get tile ids >= n_tiles and sort last.
+// bands are kept.  Tiles whose forward is split (more than
+// (kFwdSplit - 1) S pairs, S the segment length) go before every other
+// tile, so their segments head the work list.  Padding blocks get tile ids >= n_tiles and sort last.
 constexpr int kOrderBits = 5;
+constexpr int kFwdSplit = 4;  // segments from which a tile's forward is split too
 __global__ void k_order_keys(const int2 *__restrict__ ranges, const int64_t *__restrict__ cnt,
-                             int n_tiles, int grid, uint32_t *__restrict__ key,
+                             int n_tiles, int grid, int S, uint32_t *__restrict__ key,
                              uint32_t *__restrict__ val) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= grid) return;
@@ -531,7 +548,12 @@ __global__ void k_order_keys(const int2 *__restrict__ ranges, const int64_t *__r
   uint32_t k = 31;
   if (t < n_tiles && cnt[3] == 0) {
     const int2 r = ranges[t];
-    k = 31u - (32u - (uint32_t)__clz(r.y - r.x));  // 31 - bit length
+    const int L = r.y - r.x;
+    k = 31u - (32u - (uint32_t)__clz(L));  // 31 - bit length
+    // a forward-split list sorts before every list of at most
+    // (kFwdSplit - 1) S pairs (whose keys are at least 31 - that bound's
+    // bit length)
+    if (L > (kFwdSplit - 1) * S) k = min(k, 30u - (32u - (uint32_t)__clz((kFwdSplit - 1) * S)));
   }
   key[b] = k;
   val[b] = (uint32_t)t;
@@ -710,15 +732,25 @@ __global__ void k_seg_count(const uint32_t *__restrict__ order, const int2 *__re
 }
 
 // The work list (tile, segment) in launch order, each tile's first
-// boundary slot (-1: not split), and the work-item count cnt[6].
-__global__ void k_seg_fill(const uint32_t *__restrict__ order, int n_tiles, int grid,
-                           const uint32_t *__restrict__ cw, const uint32_t *__restrict__ sw,
-                           const uint32_t *__restrict__ cb, const uint32_t *__restrict__ sb,
-                           int2 *__restrict__ witem, int *__restrict__ bslot,
-                           int64_t *__restrict__ cnt) {
+// boundary slot (-1: not split), the work-item count cnt[6] and cnt[7], the
+// count of work items of forward-split tiles (the first ones of the list).
+__global__ void k_seg_fill(const uint32_t *__restrict__ order, const int2 *__restrict__ ranges,
+                           int n_tiles, int grid, int S, const uint32_t *__restrict__ cw,
+                           const uint32_t *__restrict__ sw, const uint32_t *__restrict__ cb,
+                           const uint32_t *__restrict__ sb, int2 *__restrict__ witem,
+                           int *__restrict__ bslot, int64_t *__restrict__ cnt) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b == 0) cnt[6] = (int64_t)sw[grid];
   if (b >= grid) return;
+  auto fwd_split = [&](const int q) {
+    const int u = (int)order[q];
+    if (u >= n_tiles) return false;
+    const int2 r = ranges[u];
+    return seg_count(r.y - r.x, S) >= kFwdSplit;
+  };
+  const bool fs = fwd_split(b);
+  if (b == 0 && !fs) cnt[7] = 0;
+  if (fs && (b + 1 == grid || !fwd_split(b + 1))) cnt[7] = (int64_t)sw[b + 1];
   const int t = (int)order[b];
   if (t >= n_tiles) return;
   const uint32_t w0 = sw[b];
@@ -729,7 +761,24 @@ __global__ void k_seg_fill(const uint32_t *__restrict__ order, int n_tiles, int 
 // Records per straight-line group of the one-cell forward rasterizer.
 constexpr int kFwdGroup = 4;
 
-template <int TW, int TH, int PPT>
+// A list of at least kFwdSplit segments is also split in the forward (a
+// single wavefront walking it would end the launch alone): pass 1 takes,
+// per segment and pixel, the product of (1 - alpha) over the segment's
+// samples; pass 2 composites each segment from the transmittance the
+// earlier segments' products leave (a pixel whose product chain falls
+// below 1e-4 stopped in that segment), with colour and depth from zero;
+// a combine kernel sums the segments in order into the pixel's outputs and
+// rewrites the segment-end states as running totals for the backward.
+// Pass 0 is the whole-list forward of every other tile.  Per segment slot
+// the pass state holds 3 planes: the product, the last composited position
+// and how the segment ended for the pixel.  These tiles' work items are the
+// first cnt[7] of the work list: the three kernels' grids cover at most
+// k pairs / ((k - 1) S) of them, k = kFwdSplit (a split list of
+// L > (k - 1) S pairs has at most L / S + 1 < k L / ((k - 1) S) segments).
+constexpr int kFsegVals = 3;
+enum : int { kSegAlive = 0, kSegStopped = 1, kSegDead = 2 };
+
+template <int TW, int TH, int PPT, int PASS>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_raster_fwd(const uint64_t *__restrict__ pairs, const int2 *__restrict__ ranges,
                  const uint32_t *__restrict__ order,
@@ -737,10 +786,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                  int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  float *__restrict__ rgb, float *__restrict__ depth, float *__restrict__ Tout,
                  float *__restrict__ Tstate, int *__restrict__ last_out,
-                 const int *__restrict__ bslot, float *__restrict__ bound) {
+                 const int *__restrict__ bslot, float *__restrict__ bound,
+                 const int2 *__restrict__ witem, const int64_t *__restrict__ cnt,
+                 float *__restrict__ fseg) {
 #pragma clang fp contract(off)
   constexpr int NT = TW * TH / PPT;
   constexpr int BS = NT;
+  constexpr int PX = TW * TH;
   constexpr int kSegLen = seg_len(TW, TH);
   static_assert(kSegLen % BS == 0, "segment ends fall on batch starts");
   __shared__ float4 sA[BS], sB[BS], sC[BS];
@@ -748,8 +800,21 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   // a one-cell tile needs no cell masks: every record of its list meets it
   // or is rejected pixel by pixel
   constexpr bool kOneCell = CellLayout<TW, TH, PPT>::kCells == 1;
-  const int gt = (int)order[blockIdx.x];
-  if (gt >= n_tiles) return;
+  int gt, seg = 0;
+  if constexpr (PASS == 0) {
+    gt = (int)order[blockIdx.x];
+    if (gt >= n_tiles) return;
+  } else {  // one segment of a forward-split tile
+    if (blockIdx.x >= cnt[7]) return;
+    const int2 wi = witem[blockIdx.x];
+    gt = wi.x;
+    seg = wi.y;
+  }
+  const int2 rg = ranges[gt];
+  const int nseg = seg_count(rg.y - rg.x, kSegLen);
+  if ((PASS == 0) == (nseg >= kFwdSplit)) return;  // the other passes' tile
+  const int r_lo = PASS == 0 ? rg.x : rg.x + seg * kSegLen;
+  const int r_hi = PASS == 0 ? rg.y : min(r_lo + kSegLen, rg.y);
   const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   {  // this view's images
@@ -763,7 +828,6 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   const CellLayout<TW, TH, PPT> cell(tx, ty);
   const int lx = threadIdx.x & 7, ly = (threadIdx.x >> 3) & 7;
   const float lxh = (float)lx + 0.5f, lyh = (float)ly + 0.5f;
-  const int2 rg = ranges[gt];
   float T[PPT], c0[PPT], c1[PPT], c2[PPT], D[PPT];
   int last[PPT];
   bool done[PPT];
@@ -780,11 +844,36 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   // bs + i holds it after the records before segment i + 1 (the last slot:
   // after the whole list)
   const int bs = bslot[gt];
+  auto lpix = [&](const int j) {
+    return (cell.Y0[j] - ty * TH + ly) * TW + (cell.X0[j] - tx * TW + lx);
+  };
+  if constexpr (PASS == 2) {
+    // the transmittance entering this segment: the earlier segments'
+    // products in order; a pixel whose chain falls below 1e-4 stopped in
+    // an earlier segment and takes nothing here
+    n_live = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      float Tr = 1.0f;
+      bool dead = done[j];
+      for (int q = 0; q < seg && !dead; ++q) {
+        const float Tn = Tr * fseg[(int64_t)(bs + q) * kFsegVals * PX + lpix(j)];
+        dead = Tn < kTMin;
+        Tr = dead ? Tr : Tn;
+      }
+      T[j] = Tr;
+      done[j] = dead;
+      n_live += !dead;
+    }
+  }
+  bool dead_in[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) dead_in[j] = done[j];
   auto store_state = [&](const int slot) {
     float *o = bound + (int64_t)slot * kStateVals * (TW * TH);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-      const int lp = (cell.Y0[j] - ty * TH + ly) * TW + (cell.X0[j] - tx * TW + lx);
+      const int lp = lpix(j);
       o[lp] = T[j];
       o[TW * TH + lp] = c0[j];
       o[2 * TW * TH + lp] = c1[j];
@@ -792,15 +881,15 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       o[4 * TW * TH + lp] = D[j];
     }
   };
-  for (int base = rg.x; base < rg.y; base += BS) {
+  for (int base = r_lo; base < r_hi; base += BS) {
     // once every pixel is saturated no later segment end is needed: a
     // segment's backward reads its end state only for pixels that
     // composited a record behind that end
     if (__syncthreads_count(n_live) == 0) break;
-    if (bs >= 0 && base > rg.x && (base - rg.x) % kSegLen == 0)
+    if (PASS == 0 && bs >= 0 && base > rg.x && (base - rg.x) % kSegLen == 0)
       store_state(bs + (base - rg.x) / kSegLen - 1);
     const int p = base + threadIdx.x;
-    if (p < rg.y) {
+    if (p < r_hi) {
       const uint32_t g = (uint32_t)pairs[p];
       const float4 *q = rec + 4 * (int64_t)g;  // a 64-byte record: its first 48 bytes
       const float4 A = q[0], B = q[1], C = q[2];
@@ -811,7 +900,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         sM[threadIdx.x] = CellLayout<TW, TH, PPT>::cell_mask(A, B, C, tx, ty);
     }
     __syncthreads();
-    const int nb = min(BS, rg.y - base);
+    const int nb = min(BS, r_hi - base);
     // one compositing step of cell j with the record's sample s: predicated
     // rather than branched inside a cell (a lane that does not composite
     // adds exact zeros, and the wavefront issues no mask bookkeeping);
@@ -819,6 +908,11 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     // with the same roundings
     auto composite = [&](const int j, const Sample &s, const bool valid, const float4 &B,
                          const float4 &C, const int pos) {
+      if constexpr (PASS == 1) {  // the segment's product of (1 - alpha), no stopping
+        const bool act = valid & s.ok & !done[j];
+        T[j] = T[j] * (1.0f - (act ? s.alpha : 0.0f));
+        return;
+      }
       const bool act = valid & s.ok & !done[j];
       const float a = act ? s.alpha : 0.0f;
       const float Tn = T[j] * (1.0f - a);
@@ -886,7 +980,24 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 #pragma unroll
     for (int j = 0; j < PPT; ++j) n_live += !done[j];
   }
-  if (bs >= 0) store_state(bs + seg_count(rg.y - rg.x, kSegLen) - 1);
+  if constexpr (PASS == 1) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) fseg[(int64_t)(bs + seg) * kFsegVals * PX + lpix(j)] = T[j];
+    return;
+  }
+  if constexpr (PASS == 2) {
+    // the segment's own colour and depth, its end transmittance, last
+    // position and how it ended (the combine kernel makes totals of them)
+    store_state(bs + seg);
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      float *f = fseg + (int64_t)(bs + seg) * kFsegVals * PX + lpix(j);
+      f[PX] = __int_as_float(last[j]);
+      f[2 * PX] = __int_as_float(dead_in[j] ? kSegDead : done[j] ? kSegStopped : kSegAlive);
+    }
+    return;
+  }
+  if (bs >= 0) store_state(bs + nseg - 1);
   const int64_t HW = (int64_t)W * H;
 #pragma unroll
   for (int j = 0; j < PPT; ++j) {
@@ -901,6 +1012,71 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     Tstate[pix] = T[j];
     last_out[pix] = last[j];
   }
+}
+
+// The forward of a tile split into kFwdSplit or more segments, finished:
+// one thread per pixel of the tile walks its segments in order, adding
+// their colour and depth (fixed order) up to the segment where it stopped,
+// writes the pixel's outputs, and turns each segment-end state into
+// running totals (what the backward reads there).
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH)
+    k_fwd_combine(const int2 *__restrict__ ranges, const int2 *__restrict__ witem,
+                  const int64_t *__restrict__ cnt, const int *__restrict__ bslot, int W, int H,
+                  int tiles_x, int tiles_per_view, float bg0, float bg1, float bg2,
+                  float *__restrict__ rgb, float *__restrict__ depth, float *__restrict__ Tout,
+                  float *__restrict__ Tstate, int *__restrict__ last_out,
+                  float *__restrict__ bound, const float *__restrict__ fseg) {
+#pragma clang fp contract(off)
+  constexpr int PX = TW * TH;
+  constexpr int kSegLen = seg_len(TW, TH);
+  if (blockIdx.x >= cnt[7]) return;
+  const int2 wi = witem[blockIdx.x];
+  if (wi.y != 0) return;  // one workgroup per tile
+  const int gt = wi.x;
+  const int2 rg = ranges[gt];
+  const int nseg = seg_count(rg.y - rg.x, kSegLen);
+  if (nseg < kFwdSplit) return;
+  const int bs = bslot[gt];
+  const int lp = threadIdx.x;
+  float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, Dd = 0.0f, Tf = 1.0f;
+  int lastp = -1;
+  bool ended = false;
+  for (int i = 0; i < nseg; ++i) {
+    float *o = bound + (int64_t)(bs + i) * kStateVals * PX + lp;
+    const float *f = fseg + (int64_t)(bs + i) * kFsegVals * PX + lp;
+    if (!ended) {
+      const int how = __float_as_int(f[2 * PX]);
+      if (how == kSegDead) {
+        ended = true;
+      } else {
+        C0 += o[PX];
+        C1 += o[2 * PX];
+        C2 += o[3 * PX];
+        Dd += o[4 * PX];
+        Tf = o[0];
+        const int l = __float_as_int(f[PX]);
+        lastp = l >= 0 ? l : lastp;
+        ended = how == kSegStopped;
+      }
+    }
+    o[0] = Tf;
+    o[PX] = C0;
+    o[2 * PX] = C1;
+    o[3 * PX] = C2;
+    o[4 * PX] = Dd;
+  }
+  const int view = gt / tiles_per_view, tile = gt - view * tiles_per_view;
+  const int px = (tile % tiles_x) * TW + lp % TW, py = (tile / tiles_x) * TH + lp / TW;
+  if (!(px < W && py < H)) return;
+  const int64_t HW = (int64_t)W * H, o = (int64_t)py * W + px;
+  rgb[(3 * view) * HW + o] = __builtin_fmaf(Tf, bg0, C0);
+  rgb[(3 * view + 1) * HW + o] = __builtin_fmaf(Tf, bg1, C1);
+  rgb[(3 * view + 2) * HW + o] = __builtin_fmaf(Tf, bg2, C2);
+  if (depth) depth[view * HW + o] = Dd;
+  if (Tout) Tout[view * HW + o] = Tf;
+  Tstate[view * HW + o] = Tf;
+  last_out[view * HW + o] = lastp;
 }
 
 // Cross-lane moves inside 16-lane rows through DPP (VALU, no LDS path).
@@ -1558,11 +1734,24 @@ __global__ void k_fill_i64(int64_t *__restrict__ a, int64_t n, int64_t v) {
 template <int TW, int TH, int PPT>
 void launch_fwd_t(dcgs_state *s, hipStream_t st, float *rgb, float *depth, float *T) {
   const int nt = s->tiles_x * s->tiles_y * s->V;
-  const unsigned grid = (unsigned)raster_grid(nt);
-  hipLaunchKernelGGL((k_raster_fwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
-                     s->pairs.p, s->ranges.p, s->torder.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, nt,
-                     s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], rgb, depth, T,
-                     s->T_final.p, s->last.p, s->bslot.p, s->bound.p);
+  const unsigned grid = (unsigned)raster_grid(nt), wgrid = (unsigned)s->fcap;
+  const int64_t *cnt = counters(s, st);
+  // segments of the longest lists first (products, then compositing), the
+  // whole-list tiles, then the split tiles' totals
+#define DCGS_FWD_PASS(P, G)                                                                        \
+  hipLaunchKernelGGL((k_raster_fwd<TW, TH, PPT, P>), dim3(G), dim3(TW * TH / PPT), 0, st,          \
+                     s->pairs.p, s->ranges.p, s->torder.p, s->rec.p, s->rs, s->W, s->H, s->tiles_x, \
+                     nt, s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2], rgb, depth, T,      \
+                     s->T_final.p, s->last.p, s->bslot.p, s->bound.p, s->witem.p, cnt, s->fseg.p); \
+  DCGS_LAUNCH_CHECK()
+  DCGS_FWD_PASS(1, wgrid);
+  DCGS_FWD_PASS(2, wgrid);
+  DCGS_FWD_PASS(0, grid);
+#undef DCGS_FWD_PASS
+  hipLaunchKernelGGL((k_fwd_combine<TW, TH>), dim3(wgrid), dim3(TW * TH), 0, st, s->ranges.p,
+                     s->witem.p, cnt, s->bslot.p, s->W, s->H, s->tiles_x, s->tiles_x * s->tiles_y,
+                     s->bg[0], s->bg[1], s->bg[2], rgb, depth, T, s->T_final.p, s->last.p,
+                     s->bound.p, s->fseg.p);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1664,6 +1853,7 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   s->T_final.need(V * HW + 1);
   s->last.need(V * HW + 1);
   s->scan_part.need(scan_part_size(nr) + 2);
+  s->rank_part.need(nr / 256 + 2);
 }
 
 // Projection, depth order and pair count for a grid of n_grid Gaussians
@@ -1676,9 +1866,6 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
   int64_t *cnt = counters(s, st);
   const CamD *dc = (const CamD *)s->cam_dev.p;
   uint32_t *sortkey = s->key_tmp.p, *order = s->order.p;
-  // the 64-bit pair total k_rank sums
-  hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, st, cnt + 5, (int64_t)1, (int64_t)0);
-  DCGS_LAUNCH_CHECK();
   if (n_grid > 0) {
     StageTimer tp(ctx, DCGS_STAGE_PREPROCESS, st);
     hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, kPrepThreads)), dim3(kPrepThreads),
@@ -1693,13 +1880,14 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
     sort_u32_pairs(sortkey, order, sortkey + RS + 1, s->val_tmp.p, nr, 32, s->hist, st,
                    cnt + 1);
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, kRankThreads)), dim3(kRankThreads), 0, st,
-                       order, s->count.p, cnt, s->rank_of.p, sortkey + RS + 1);
+                       order, s->count.p, cnt, s->rank_of.p, sortkey + RS + 1, s->rank_part.p);
     DCGS_LAUNCH_CHECK();
   }
   StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
   // the depth sort's second key buffer holds the counts in depth order now
   scan_u32(sortkey + RS + 1, nullptr, s->scan.p, nr, s->scan_part.p, st, cnt + 1);
-  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(64), 0, st, cnt, pcap);
+  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(kTotalThreads), 0, st, s->rank_part.p, cnt,
+                     pcap);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1735,7 +1923,7 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
     const int grid = raster_grid(nt);
     uint32_t *key = s->torder.p + grid, *ktmp = key + grid, *vtmp = ktmp + grid;
     hipLaunchKernelGGL(k_order_keys, dim3(blocks_for(grid, 256)), dim3(256), 0, st, s->ranges.p,
-                       cnt, nt, grid, key, s->torder.p);
+                       cnt, nt, grid, seg_len(s->TW, s->TH), key, s->torder.p);
     DCGS_LAUNCH_CHECK();
     sort_u32_pairs(key, s->torder.p, ktmp, vtmp, grid, kOrderBits, s->hist, st);
     // the backward's work list: long lists split into segments, in launch order
@@ -1745,8 +1933,9 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
     DCGS_LAUNCH_CHECK();
     scan_u32(cw, nullptr, sw, grid, s->segpart.p, st);
     scan_u32(cb, nullptr, sb, grid, s->segpart.p + scan_part_size(grid) + 2, st);
-    hipLaunchKernelGGL(k_seg_fill, dim3(blocks_for(grid, 256)), dim3(256), 0, st, s->torder.p, nt,
-                       grid, cw, sw, cb, sb, s->witem.p, s->bslot.p, cnt);
+    hipLaunchKernelGGL(k_seg_fill, dim3(blocks_for(grid, 256)), dim3(256), 0, st, s->torder.p,
+                       s->ranges.p, nt, grid, seg_len(s->TW, s->TH), cw, sw, cb, sb, s->witem.p,
+                       s->bslot.p, cnt);
     DCGS_LAUNCH_CHECK();
   }
   StageTimer tf(ctx, DCGS_STAGE_RASTER_FWD, st);
@@ -1762,8 +1951,10 @@ void size_pairs(dcgs_state *s, int64_t pcap) {
   const int64_t nt = (int64_t)s->tiles_x * s->tiles_y * s->V;
   const int64_t S = seg_len(s->TW, s->TH);
   s->wcap = nt + pcap / S + 1;
+  s->fcap = std::min(s->wcap, kFwdSplit * pcap / ((kFwdSplit - 1) * S) + 1);
   s->witem.need((size_t)s->wcap + 8);
   s->bound.need((size_t)(2 * (pcap / S) + 1) * kStateVals * s->TW * s->TH);
+  s->fseg.need((size_t)(2 * (pcap / S) + 1) * kFsegVals * s->TW * s->TH);
 }
 
 }  // namespace

@@ -1,11 +1,16 @@
-"""Tiles whose lists are far longer than one backward segment (64 list
-positions per pixel of the tile: 4096 at 8x8, 16384 at 16x16, 32768 at
-32x16): hundreds of thousands of faint, pixel-sized Gaussians in front of
-a 32x32 image, so every tile's list is split for the backward and no pixel
-saturates (each segment's backward starts from the compositing state the
-forward stored at its end).  Images and gradients against the oracle, for
-every raster shape; a two-view window against the per-view path bit for
-bit."""
+"""Tiles whose lists are far longer than one segment (64 list positions per
+pixel of the tile: 4096 at 8x8, 16384 at 16x16, 32768 at 32x16):
+hundreds of thousands of faint, pixel-sized Gaussians in front of a 32x32
+image, so every tile's list is split and no pixel saturates.  With 160k
+Gaussians every list has 3 segments: split for the backward only (each
+segment's backward starts from the compositing state the forward stored at
+its end).  With 480k they have about 8: the forward is split too (segment
+products, then segments composited from the transmittance those leave,
+then summed).  A mixed scene puts both kinds of tile side by side (480k
+Gaussians' density in the left half of the image, 80k's in the right), so
+forward-split tiles head the work list and the rest follow.  Images and
+gradients against the oracle, for every raster shape; a two-view window
+against the per-view path bit for bit."""
 import numpy as np
 import pytest
 import torch
@@ -18,15 +23,16 @@ from paper_2511_23030_amd import dcgs as D
 pytestmark = pytest.mark.gpu
 
 SEG_PER_PIXEL = 64
+FWD_SPLIT = 4                                   # segments from which the forward splits
 W = H = 32
 F = 50.0
 
 
-def _dense(n=480_000, seed=50):
+def _dense(n=480_000, seed=50, xs=(-0.5, 0.5)):
     rng = np.random.default_rng(seed)
     P = scenegen.tiny_scene(n=n, seed=seed, width=W, height=H, focal=F)["params"].astype(np.float64)
     Z = rng.uniform(3.0, 4.0, n)
-    P[0] = rng.uniform(-0.5, 0.5, n) * (W / F) * Z
+    P[0] = rng.uniform(xs[0], xs[1], n) * (W / F) * Z
     P[1] = rng.uniform(-0.5, 0.5, n) * (H / F) * Z
     P[2] = Z
     P[3:6] = np.log(0.004) + rng.normal(0.0, 0.2, (3, n))
@@ -34,12 +40,22 @@ def _dense(n=480_000, seed=50):
     return P.astype(np.float32)
 
 
+def _scene(kind, seed):
+    if kind == "bwd":
+        return _dense(160_000, seed)
+    if kind == "fwd":
+        return _dense(480_000, seed)
+    return np.concatenate([_dense(240_000, seed, (-0.5, 0.0)),
+                           _dense(40_000, seed + 5, (0.0, 0.5))], axis=1)
+
+
 def _cam(shift=0.0):
     return scenegen.camera(np.eye(3), np.array([shift, 0.0, 0.0]), F, F, W / 2.0, H / 2.0, W, H)
 
 
-def test_split_lists_images_and_gradients(ctx):
-    P = _dense()
+@pytest.mark.parametrize("kind", ["bwd", "fwd", "mixed"])
+def test_split_lists_images_and_gradients(ctx, kind):
+    P = _scene(kind, 50)
     cam = _cam()
     bg = np.array([0.2, 0.1, 0.3])
     rec = osp.preprocess(P, 0, cam, requires_grad=True)
@@ -60,9 +76,17 @@ def test_split_lists_images_and_gradients(ctx):
         g = gpu_render(ctx, P, 0, cam, bg, shape[:2], dl, dld, ppt=shape[2])
         lens = g["ranges"][:, 1] - g["ranges"][:, 0]
         seg = SEG_PER_PIXEL * shape[0] * shape[1]
-        print(f"case long lists shape={shape}: longest list {lens.max()}, "
-              f"{int((lens > seg).sum())} of {lens.size} tiles split", flush=True)
-        assert lens.max() > 2 * seg
+        fwd = lens > (FWD_SPLIT - 1) * seg
+        print(f"case long lists {kind} shape={shape}: lists {lens.min()}..{lens.max()}, "
+              f"{int((lens > seg).sum())} of {lens.size} tiles split, {int(fwd.sum())} in the "
+              f"forward too", flush=True)
+        assert lens.min() > seg                     # every list split
+        if kind == "fwd":
+            assert fwd.all()
+        elif kind == "bwd":
+            assert not fwd.any()
+        elif shape[0] <= 16:                        # a 32-wide tile spans both halves
+            assert fwd.any() and not fwd.all()
         ok = ~flag
         assert np.abs(g["rgb"] - img.rgb.detach().numpy())[:, ok].max() <= IMG_TOL
         assert np.abs(g["T"] - img.T.detach().numpy())[ok].max() <= IMG_TOL
@@ -77,13 +101,15 @@ def test_split_lists_images_and_gradients(ctx):
         assert_grad_close(g["grad"][0:3], gr.params[0:3], "d mean", colour_ok)
         assert_grad_close(g["grad"][3:11], gr.params[3:11], "d scale, rotation, opacity", vis)
         assert_grad_close(g["grad"][11:], gr.params[11:], "d SH", colour_ok)
-    for other in imgs[1:]:
-        assert (other == imgs[0]).all()             # the forward is not split: bitwise
+    if kind == "bwd":
+        for other in imgs[1:]:
+            assert (other == imgs[0]).all()         # one walk per list: bitwise across shapes
 
 
 @pytest.mark.parametrize("shape", [(16, 16, 4), (8, 8, 1)])
-def test_split_lists_batched_equals_per_view(ctx, shape):
-    P = torch.from_numpy(_dense(seed=53)).cuda()
+@pytest.mark.parametrize("kind", ["bwd", "fwd", "mixed"])
+def test_split_lists_batched_equals_per_view(ctx, shape, kind):
+    P = torch.from_numpy(np.ascontiguousarray(_scene(kind, 53))).cuda()
     n = P.shape[1]
     cams = [_cam(0.0), _cam(0.02)]
     rng = np.random.default_rng(54)
