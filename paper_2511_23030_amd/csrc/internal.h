@@ -144,7 +144,8 @@ struct dcgs_state {
   dcgs::DevBuf<uint32_t> rank_of;  // [n] Gaussian -> depth rank
   dcgs::DevBuf<uint32_t> key_tmp, val_tmp;
   dcgs::DevBuf<uint32_t> scan;      // [n + 1] pair offsets in depth order
-  dcgs::DevBuf<uint32_t> pair_off;  // [n] pair offset by Gaussian
+  dcgs::DevBuf<uint32_t> seg_tot;   // pair count per projection segment (view, workgroup)
+  dcgs::DevBuf<uint32_t> seg_off;   // their exclusive scan: gradient slot bases
   dcgs::DevBuf<uint64_t> tmask;     // [n] kept tiles of the record's tile rectangle
   // per pair
   dcgs::DevBuf<uint64_t> pairs, pairs_tmp;

@@ -16,8 +16,9 @@
 //  * A projection record is four float4 (64 B, one aligned segment): u and
 //    v relative to the pixel box corner (small magnitudes keep float32
 //    offsets exact to ~1e-7 px), conic, opacity, colour, depth and the
-//    packed pixel box, then the record's pair offset and kept-tile mask
-//    (written by pair emission, read by the backward with the record).
+//    packed pixel box, then where the record's gradient slots start and its
+//    kept-tile mask (read by the backward with the record); the projection
+//    writes all 64 bytes at once.
 //  * The depth digits of the (tile, depth) keys are the same for all pairs of
 //    a Gaussian, so the LSD passes over them run on the N Gaussians before
 //    pair expansion; pairs are then emitted in depth order and stably sorted
@@ -341,12 +342,27 @@ __device__ __forceinline__ bool tile_kept(uint64_t m, int n_rect, int k) {
   return n_rect > 64 || ((m >> k) & 1);
 }
 
+// Per-pair gradient slots: record r's kept tiles take slots base(r) ..
+// base(r) + count[r] - 1 (row-major), in record order.  The projection's
+// workgroups cover 64 consecutive Gaussians, so within one view a
+// workgroup's records form a segment v * gridDim + block of consecutive
+// records; base(r) = seg_off[segment] + the record's prefix inside its
+// segment, seg_off the exclusive scan of the segment totals.  The record
+// carries its prefix and segment id, so it is written whole here, and the
+// pass that sums a record's slots finds neighbouring records' slots side by
+// side.
+__device__ __forceinline__ uint32_t slot_base(const uint32_t *__restrict__ seg_off,
+                                              const float4 &D) {
+  return seg_off[__float_as_uint(D.w)] + __float_as_uint(D.x);
+}
+
 // One thread per Gaussian; it projects the Gaussian into every view whose
 // bit is set in its chunk's view mask.  Record r = v * n + g is the float4s
-// rec[4 r .. 4 r + 3] (64 contiguous bytes, one gather per record; this
-// kernel writes the first three, pair emission the fourth, and a culled
-// record is not written).  cnt[0] = n (device counter; the grid may be sized
-// for a capacity).
+// rec[4 r .. 4 r + 3] (64 contiguous bytes, one gather per record: geometry,
+// colour, depth and box, then the slot prefix, kept-tile mask and segment
+// id; a culled record is not written).  seg_tot[v * gridDim + block] = the
+// pair count of the workgroup's records of view v.  cnt[0] = n (device
+// counter; the grid may be sized for a capacity).
 // Four waves per SIMD: the float64 projection is latency-bound, and the
 // compiler fits it in 128 registers without spilling.
 constexpr int kPrepThreads = 64;
@@ -356,50 +372,76 @@ __global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_
                  const uint16_t *__restrict__ gmask, int mask_shift, int TW, int TH,
                  float4 *__restrict__ rec, int64_t RS, uint32_t *__restrict__ zkey,
                  uint32_t *__restrict__ sortkey, uint32_t *__restrict__ order,
-                 uint32_t *__restrict__ count, uint64_t *__restrict__ tmask) {
+                 uint32_t *__restrict__ count, uint64_t *__restrict__ tmask,
+                 uint32_t *__restrict__ seg_tot) {
+  static_assert(kPrepThreads == kWave, "one wavefront per segment");
   // the Gaussian's colour coefficients, read once for all views into this
   // thread's LDS column (each thread reads back only its own column)
   __shared__ float shc[48][kPrepThreads];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0];
-  if (i >= n) return;
+  // every lane takes part in the segment prefix sums, past n too (with no
+  // pairs); a workgroup wholly past n only writes zero segment totals
+  const bool live = i < n;
   Geo g;
-  load_gauss(P, stride, i, g);
-  for (int r = 0; r < 3 * (deg + 1) * (deg + 1); ++r)
-    shc[r][threadIdx.x] = P[(11 + r) * stride + i];
-  const unsigned m = gmask ? ((unsigned)gmask[i] >> mask_shift) : 0xFFFFu;
+  unsigned m = 0;
+  if (live) {
+    load_gauss(P, stride, i, g);
+    for (int r = 0; r < 3 * (deg + 1) * (deg + 1); ++r)
+      shc[r][threadIdx.x] = P[(11 + r) * stride + i];
+    m = gmask ? ((unsigned)gmask[i] >> mask_shift) : 0xFFFFu;
+  }
+  const int lane = threadIdx.x;
   for (int v = 0; v < V; ++v) {
     const int64_t r = v * n + i;
-    order[r] = (uint32_t)r;
-    const CamD &cam = cams[v];
-    bool culled = !((m >> v) & 1u);
+    uint32_t n_keep = 0;
+    uint64_t tm = 0;
+    bool drawn = false;
     float zf = 0.0f;
-    if (!culled) {
-      project(cam, g);
-      culled = g.culled;
-      zf = (float)g.Z;
+    if (live) {
+      order[r] = (uint32_t)r;
+      bool culled = !((m >> v) & 1u);
+      if (!culled) {
+        project(cams[v], g);
+        culled = g.culled;
+        zf = (float)g.Z;
+      }
+      zkey[r] = __float_as_uint(zf);
+      if (culled) {  // its record is never read: no pairs, and exports zero it
+        count[r] = 0;
+        tmask[r] = 0;
+        sortkey[r] = kCulledKey;
+      } else {
+        drawn = true;
+        tm = tile_mask(g, TW, TH, n_keep);
+        tmask[r] = tm;
+        count[r] = n_keep;
+        sortkey[r] = __float_as_uint(zf);
+      }
     }
-    zkey[r] = __float_as_uint(zf);
-    if (culled) {  // its record is never read: no pairs, and exports zero it
-      count[r] = 0;
-      tmask[r] = 0;
-      sortkey[r] = kCulledKey;
-      continue;
+    // the segment's inclusive prefix of pair counts (lane order = record order)
+    uint32_t incl = n_keep;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t t = __shfl_up(incl, off);
+      if (lane >= off) incl += t;
     }
-    double dir[3], dn, Y[16], raw[3];
-    color_raw(&shc[0][threadIdx.x], kPrepThreads, deg, g, cam, dir, dn, Y, raw);
-    uint32_t n_keep;
-    tmask[r] = tile_mask(g, TW, TH, n_keep);
-    count[r] = n_keep;
-    sortkey[r] = __float_as_uint(zf);
-    const double id = 1.0 / g.det;
-    rec[4 * r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0), (float)(-0.5 * kLog2e * g.c * id),
-                         (float)(kLog2e * g.b * id));
-    rec[4 * r + 1] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
-                              (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
-    rec[4 * r + 2] = make_float4((float)fmax(raw[2], 0.0), zf,
-                                  __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
-                                  __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
+    const uint32_t segment = (uint32_t)v * gridDim.x + blockIdx.x;
+    if (lane == kWave - 1) seg_tot[segment] = incl;
+    if (drawn) {
+      double dir[3], dn, Y[16], raw[3];
+      color_raw(&shc[0][threadIdx.x], kPrepThreads, deg, g, cams[v], dir, dn, Y, raw);
+      const double id = 1.0 / g.det;
+      rec[4 * r] = make_float4((float)(g.u - g.i0), (float)(g.v - g.j0),
+                               (float)(-0.5 * kLog2e * g.c * id), (float)(kLog2e * g.b * id));
+      rec[4 * r + 1] = make_float4((float)(-0.5 * kLog2e * g.a * id), (float)g.o,
+                                   (float)fmax(raw[0], 0.0), (float)fmax(raw[1], 0.0));
+      rec[4 * r + 2] = make_float4((float)fmax(raw[2], 0.0), zf,
+                                   __uint_as_float((uint32_t)g.i0 | ((uint32_t)g.i1 << 16)),
+                                   __uint_as_float((uint32_t)g.j0 | ((uint32_t)g.j1 << 16)));
+      rec[4 * r + 3] = make_float4(__uint_as_float(incl - n_keep), __uint_as_float((uint32_t)tm),
+                                   __uint_as_float((uint32_t)(tm >> 32)), __uint_as_float(segment));
+    }
   }
 }
 
@@ -460,52 +502,85 @@ __global__ void __launch_bounds__(kTotalThreads)
   if (over) cnt[4] = 1;
 }
 
-// Pairs of record r = v n + g: (global tile v T + t) << 32 | r, laid out in
-// depth order (the run of the record of depth rank j starts at scan[j]),
-// tiles of a record row-major.  One thread per record in record order: its
-// count, box and tile mask are read coalesced, and only its run's start is
-// gathered (by depth rank).  It also writes the record's fourth float4.
-__global__ void k_emit(const uint32_t *__restrict__ rank_of, const uint32_t *__restrict__ count,
-                       const uint32_t *__restrict__ scan, float4 *__restrict__ rec,
-                       const uint64_t *__restrict__ tmask, const int64_t *__restrict__ cnt,
-                       int TW, int TH, int tiles_x, int tiles_per_view,
-                       uint64_t *__restrict__ pairs, uint32_t *__restrict__ pair_off) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n = cnt[0], nr = cnt[1];
-  if (g >= nr || cnt[3] != 0) return;
-  const uint32_t c = count[g];
-  if (c == 0) return;  // no pairs; its pair offset is never read
-  const uint32_t base = scan[rank_of[g]];
-  pair_off[g] = base;
-  const uint32_t view_base = (uint32_t)(g / n) * (uint32_t)tiles_per_view;
-  const float4 C = rec[4 * g + 2];
-  const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
-  const int tx0 = (bx & 0xFFFF) / TW, tx1 = (bx >> 16) / TW;
-  const int ty0 = (by & 0xFFFF) / TH, ty1 = (by >> 16) / TH;
-  const int n_rect = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-  const uint64_t m = tmask[g];
-  // the record's fourth float4: what the backward's epilogue needs to place
-  // its per-tile gradient partials (pair offset and kept-tile mask), staged
-  // with the record instead of gathered at random per (record, tile)
-  rec[4 * g + 3] = make_float4(__uint_as_float(base), __uint_as_float((uint32_t)m),
-                               __uint_as_float((uint32_t)(m >> 32)), 0.0f);
-  uint32_t k = base;
-  const int wc = tx1 - tx0 + 1;
-  if (n_rect > 64) {  // every tile kept
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx)
-        pairs[k++] = ((uint64_t)(view_base + (uint32_t)(ty * tiles_x + tx)) << 32) | (uint32_t)g;
-    return;
+// Position of the k-th set bit (k from 0) of m, which has more than k set
+// bits: six halving steps.
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = m & ((uint64_t(1) << w) - 1);
+    const int c = __popcll(low);
+    if (k >= c) {
+      k -= c;
+      pos += w;
+      m >>= w;
+    }
   }
-  // the kept tiles only: per row of the rectangle, its bits of the mask,
-  // lowest first (row-major order, as the slots are laid out)
-  const uint64_t row_bits = wc >= 64 ? ~uint64_t(0) : ((uint64_t(1) << wc) - 1);
-  uint64_t mm = m;
-  for (int ty = ty0; ty <= ty1; ++ty) {
-    const uint32_t row = view_base + (uint32_t)(ty * tiles_x + tx0);
-    for (uint64_t rb = mm & row_bits; rb != 0; rb &= rb - 1)
-      pairs[k++] = ((uint64_t)(row + (uint32_t)__builtin_ctzll(rb)) << 32) | (uint32_t)g;
-    mm = wc >= 64 ? 0 : (mm >> wc);
+  return pos;
+}
+
+// Pairs of record r = v n + g: (global tile v T + t) << 32 | r, in depth
+// order (the run of the record of depth rank j starts at scan[j]), a
+// record's kept tiles row-major.  A workgroup takes 256 consecutive depth
+// ranks, whose runs are one contiguous stretch of the pair array: it stages
+// their records' run starts, ids, tile rectangles and masks in LDS, and its
+// threads then write the stretch position by position (coalesced stores, a
+// long run spread over all lanes), each finding its record by binary search
+// over the staged run starts.
+constexpr int kEmitThreads = 256;
+__global__ void __launch_bounds__(kEmitThreads)
+    k_emit(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count_sorted,
+           const uint32_t *__restrict__ scan, const float4 *__restrict__ rec,
+           const uint64_t *__restrict__ tmask, const int64_t *__restrict__ cnt, int TW, int TH,
+           int tiles_x, int tiles_per_view, uint64_t *__restrict__ pairs) {
+  __shared__ uint32_t s_start[kEmitThreads], s_g[kEmitThreads], s_row[kEmitThreads];
+  __shared__ uint32_t s_wc[kEmitThreads];
+  __shared__ uint64_t s_mask[kEmitThreads];
+  const int64_t n = cnt[0], nr = cnt[1];
+  if (cnt[3] != 0) return;
+  const int64_t j0 = (int64_t)blockIdx.x * kEmitThreads;
+  if (j0 >= nr) return;
+  const int64_t j1 = min(j0 + (int64_t)kEmitThreads, nr);
+  const uint32_t first = scan[j0], last = scan[j1];
+  const int t = threadIdx.x;
+  const int64_t j = j0 + t;
+  // an empty or absent entry starts where the next one does; the search
+  // below returns the last entry starting at or before a position, which
+  // always has pairs (an empty one is followed by one of the same start)
+  uint32_t start = last;
+  if (j < j1) {
+    start = scan[j];
+    if (count_sorted[j] > 0) {
+      const uint32_t g = order[j];
+      const float4 C = rec[4 * (int64_t)g + 2];
+      const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
+      const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
+      const int ty0 = (int)(by & 0xFFFF) / TH, ty1 = (int)(by >> 16) / TH;
+      const int wc = tx1 - tx0 + 1, n_rect = wc * (ty1 - ty0 + 1);
+      s_g[t] = g;
+      // the global tile id of the rectangle's top-left tile, and its width
+      // (top bit: every tile kept, the mask unused beyond 64 tiles)
+      s_row[t] = (uint32_t)(g / n) * (uint32_t)tiles_per_view + (uint32_t)(ty0 * tiles_x + tx0);
+      s_wc[t] = (uint32_t)wc | (n_rect > 64 ? 0x80000000u : 0u);
+      s_mask[t] = tmask[g];
+    }
+  }
+  s_start[t] = start;
+  __syncthreads();
+  for (uint32_t p = first + (uint32_t)t; p < last; p += kEmitThreads) {
+    int lo = 0, hi = kEmitThreads;  // last entry with start <= p: in [lo, hi)
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (s_start[mid] <= p) lo = mid;
+      else hi = mid;
+    }
+    const int k = (int)(p - s_start[lo]);
+    const uint32_t wf = s_wc[lo];
+    const int wc = (int)(wf & 0x7FFFFFFFu);
+    const int pos = (wf >> 31) ? k : nth_set_bit(s_mask[lo], k);
+    const int dy = pos / wc, dx = pos - dy * wc;
+    const uint32_t tile = s_row[lo] + (uint32_t)(dy * tiles_x + dx);
+    pairs[p] = ((uint64_t)tile << 32) | s_g[lo];
   }
 }
 
@@ -1168,13 +1243,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
                  const uint32_t *__restrict__ rank_of, float2 *__restrict__ partial,
                  int *__restrict__ frontier, const int *__restrict__ bslot,
-                 const float *__restrict__ bound) {
+                 const float *__restrict__ bound, const uint32_t *__restrict__ seg_off) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
   constexpr int BS = NT < 128 ? NT : 128;  // records per batch
   constexpr int NC = 10;
   __shared__ float4 sA[BS], sB[BS], sC[BS];
-  __shared__ uint32_t sP[BS], sM[BS];  // pair offset of the record, cell mask
+  __shared__ uint32_t sP[BS], sM[BS];  // gradient slot base of the record, cell mask
   __shared__ uint64_t sT[BS];          // kept-tile mask of the record
   __shared__ float red[NW][BS][NC];
   constexpr bool kOneCell = CellLayout<TW, TH, PPT>::kCells == 1;  // no cell masks needed
@@ -1263,7 +1338,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
       const uint32_t g = (uint32_t)pairs[end - 1 - threadIdx.x];
       const float4 *q = rec + 4 * (int64_t)g;  // one 64-byte record
       const float4 A = q[0], B = q[1], C = q[2], Dq = q[3];
-      sP[threadIdx.x] = __float_as_uint(Dq.x);
+      sP[threadIdx.x] = slot_base(seg_off, Dq);
       sT[threadIdx.x] = (uint64_t)__float_as_uint(Dq.y) | ((uint64_t)__float_as_uint(Dq.z) << 32);
       sA[threadIdx.x] = A;
       sB[threadIdx.x] = B;
@@ -1503,13 +1578,14 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
 }
 
 // Per record (view v, Gaussian g) with a non-empty tile rect: the sum of its
-// per-tile partials in emission order (only tiles whose backward reached it),
-// written as ten planes s2d[c][r].  Integer box from the packed record.
+// per-tile partials in slot order (only tiles whose backward reached it),
+// written as ten planes s2d[c][r].  Integer box, slot base and kept-tile
+// mask from the record.
 __global__ void __launch_bounds__(256)
     k_sum_partials(const int64_t *__restrict__ cnt, int64_t RS, int TW, int TH, int tiles_x,
                    int tiles_per_view, const float4 *__restrict__ rec,
-                   const uint32_t *__restrict__ count, const uint32_t *__restrict__ pair_off,
-                   const uint32_t *__restrict__ rank_of, const uint64_t *__restrict__ tmask,
+                   const uint32_t *__restrict__ count, const uint32_t *__restrict__ seg_off,
+                   const uint32_t *__restrict__ rank_of,
                    const int *__restrict__ frontier, const float2 *__restrict__ partial,
                    float *__restrict__ s2d, int zero_undrawn) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1520,14 +1596,14 @@ __global__ void __launch_bounds__(256)
   // planes are written (as zeros) only for a caller's own output buffer
   if (count[r] == 0 && !zero_undrawn) return;
   if (count[r] > 0) {
-    const float4 C = rec[4 * r + 2];
+    const float4 C = rec[4 * r + 2], D = rec[4 * r + 3];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
     const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
     const int ty0 = (int)(by & 0xFFFF) / TH, ty1 = (int)(by >> 16) / TH;
     const int wc = tx1 - tx0 + 1, n_rect = wc * (ty1 - ty0 + 1);
-    const uint64_t m = tmask[r];
+    const uint64_t m = (uint64_t)__float_as_uint(D.y) | ((uint64_t)__float_as_uint(D.z) << 32);
     const int tile_base = (int)(r / n) * tiles_per_view;
-    const uint32_t slot = pair_off[r];
+    const uint32_t slot = slot_base(seg_off, D);
     const int rank = (int)rank_of[r];
     const uint32_t c = count[r];  // kept tiles: popcount(m), or n_rect beyond 64
     uint64_t mm = m;
@@ -1765,7 +1841,7 @@ void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const flo
                      s->pairs.p, s->ranges.p, s->witem.p, counters(s, st), s->rec.p, s->rs, s->W,
                      s->H, s->tiles_x, nt, s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2],
                      s->T_final.p, s->last.p, dl_drgb, dl_ddepth, s->rank_of.p, s->partial.p,
-                     s->frontier.p, s->bslot.p, s->bound.p);
+                     s->frontier.p, s->bslot.p, s->bound.p, s->seg_off.p);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1839,7 +1915,8 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   s->key_tmp.need(2 * (size_t)nr + 2);
   s->val_tmp.need(nr + 1);
   s->rank_of.need(nr + 1);
-  s->pair_off.need(nr + 1);
+  s->seg_tot.need((size_t)V * blocks_for(n_grid, kPrepThreads) + 1);
+  s->seg_off.need((size_t)V * blocks_for(n_grid, kPrepThreads) + 2);
   s->tmask.need(nr + 1);
   s->scan.need(nr + 2);
   s->ranges.need(nt + 1);
@@ -1871,7 +1948,8 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
     hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(n_grid, kPrepThreads)), dim3(kPrepThreads),
                        0, st, params,
                        cnt, stride, s->sh_degree, dc, V, gmask, mask_shift, s->TW, s->TH,
-                       s->rec.p, RS, s->zkey.p, sortkey, order, s->count.p, s->tmask.p);
+                       s->rec.p, RS, s->zkey.p, sortkey, order, s->count.p, s->tmask.p,
+                       s->seg_tot.p);
     DCGS_LAUNCH_CHECK();
   }
   if (nr > 0) {
@@ -1889,6 +1967,10 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
   hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(kTotalThreads), 0, st, s->rank_part.p, cnt,
                      pcap);
   DCGS_LAUNCH_CHECK();
+  // gradient slot bases of the projection's segments
+  if (n_grid > 0)
+    scan_u32(s->seg_tot.p, nullptr, s->seg_off.p, (int64_t)V * blocks_for(n_grid, kPrepThreads),
+             s->scan_part.p, st);
 }
 
 // Pair emission, tile sort, ranges and the forward raster for pcap pair
@@ -1903,9 +1985,9 @@ void enqueue_back(dcgs_state *s, int64_t n_grid, int64_t pcap, hipStream_t st, f
   int64_t *cnt = counters(s, st);
   if (nr > 0) {
     StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
-    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, 256)), dim3(256), 0, st, s->rank_of.p,
-                       s->count.p, s->scan.p, s->rec.p, s->tmask.p, cnt, s->TW,
-                       s->TH, s->tiles_x, tpv, s->pairs.p, s->pair_off.p);
+    hipLaunchKernelGGL(k_emit, dim3(blocks_for(nr, kEmitThreads)), dim3(kEmitThreads), 0, st,
+                       s->order.p, s->key_tmp.p + s->rs + 1, s->scan.p, s->rec.p, s->tmask.p,
+                       cnt, s->TW, s->TH, s->tiles_x, tpv, s->pairs.p);
     DCGS_LAUNCH_CHECK();
   }
   int tile_bits = 0;
@@ -2042,8 +2124,8 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
     int64_t *cnt = counters(s, st);
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, cnt,
                        s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p, s->count.p,
-                       s->pair_off.p, s->rank_of.p, s->tmask.p, s->frontier.p, s->partial.p,
-                       s2d, grad2d ? 1 : 0);
+                       s->seg_off.p, s->rank_of.p, s->frontier.p, s->partial.p, s2d,
+                       grad2d ? 1 : 0);
     DCGS_LAUNCH_CHECK();
 #define DCGS_PBWD(D)                                                                        \
   hipLaunchKernelGGL(k_preprocess_bwd<D>, dim3(blocks_for(n_grid, 256)), dim3(256), 0, st,   \
