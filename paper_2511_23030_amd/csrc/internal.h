@@ -141,7 +141,6 @@ struct dcgs_state {
   dcgs::DevBuf<uint32_t> zkey;     // [n]
   dcgs::DevBuf<uint32_t> count;    // [n]
   dcgs::DevBuf<uint32_t> order;    // [n] depth order -> Gaussian
-  dcgs::DevBuf<uint32_t> rank_of;  // [n] Gaussian -> depth rank
   dcgs::DevBuf<uint32_t> key_tmp, val_tmp;
   dcgs::DevBuf<uint32_t> scan;      // [n + 1] pair offsets in depth order
   dcgs::DevBuf<uint32_t> seg_tot;   // pair count per projection segment (view, workgroup)
@@ -158,7 +157,7 @@ struct dcgs_state {
   int64_t n_grid = 0, rs = 0, pcap = 0;
   // per tile
   dcgs::DevBuf<int2> ranges;
-  dcgs::DevBuf<int> frontier;
+  dcgs::DevBuf<uint64_t> frontier;
   dcgs::DevBuf<uint32_t> torder;  // raster launch order (tile per workgroup), longest lists first
   // backward work list: long lists split into segments (render.hip)
   dcgs::DevBuf<uint32_t> segc, segs, segpart;  // per-order counts, their scans, scan partials
@@ -175,7 +174,7 @@ struct dcgs_state {
   dcgs::DevBuf<uint32_t> hist;
   dcgs::DevBuf<float> grad2d;  // [10][n] when the caller passes none
   dcgs::DevBuf<uint32_t> scan_part;  // block totals of the pair-count scan
-  dcgs::DevBuf<unsigned long long> rank_part;  // 64-bit pair-count sums per k_rank workgroup
+  dcgs::DevBuf<unsigned long long> count_part;  // 64-bit pair-count sums per k_depth_counts workgroup
 };
 
 struct HostChunk {

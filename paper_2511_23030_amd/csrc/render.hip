@@ -356,6 +356,14 @@ __device__ __forceinline__ uint32_t slot_base(const uint32_t *__restrict__ seg_o
   return seg_off[__float_as_uint(D.w)] + __float_as_uint(D.x);
 }
 
+// A drawn record's place in the depth order as one 64-bit key: the depth
+// sort is stable on the float32 depth bits with records in index order, so
+// record a precedes record b exactly when (depth bits, index) of a is
+// smaller.  Depths are positive, so every key exceeds 0 (0: nothing).
+__device__ __forceinline__ uint64_t depth_order_key(const float4 *__restrict__ rec, uint32_t r) {
+  return ((uint64_t)__float_as_uint(rec[4 * (int64_t)r + 2].y) << 32) | r;
+}
+
 // One thread per Gaussian; it projects the Gaussian into every view whose
 // bit is set in its chunk's view mask.  Record r = v * n + g is the float4s
 // rec[4 r .. 4 r + 3] (64 contiguous bytes, one gather per record: geometry,
@@ -445,23 +453,21 @@ __global__ void __launch_bounds__(kPrepThreads) __attribute__((amdgpu_waves_per_
   }
 }
 
-// Depth rank of every record, and the records' pair counts in depth order
-// (what the pair-offset scan sums, read once here instead of gathered by it).
+// The records' pair counts in depth order (what the pair-offset scan sums,
+// gathered once here instead of by it).
 // Each workgroup also writes the 64-bit sum of its counts; k_pairs_total
 // adds those up: the 32-bit scan of the counts wraps beyond 2^32 pairs, and
 // the overflow decision must see the true count.
-constexpr int kRankThreads = 256;
-__global__ void __launch_bounds__(kRankThreads)
-    k_rank(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
-           const int64_t *__restrict__ cnt, uint32_t *__restrict__ rank_of,
-           uint32_t *__restrict__ count_sorted, unsigned long long *__restrict__ part_sum) {
-  __shared__ unsigned long long part[kRankThreads / kWave];
+constexpr int kCountThreads = 256;
+__global__ void __launch_bounds__(kCountThreads)
+    k_depth_counts(const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
+           const int64_t *__restrict__ cnt, uint32_t *__restrict__ count_sorted,
+           unsigned long long *__restrict__ part_sum) {
+  __shared__ unsigned long long part[kCountThreads / kWave];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   unsigned long long c = 0;
   if (j < cnt[1]) {
-    const uint32_t r = order[j];
-    rank_of[r] = (uint32_t)j;
-    const uint32_t k = count[r];
+    const uint32_t k = count[order[j]];
     count_sorted[j] = k;
     c = k;
   }
@@ -470,12 +476,12 @@ __global__ void __launch_bounds__(kRankThreads)
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long s = 0;
-    for (int w = 0; w < kRankThreads / kWave; ++w) s += part[w];
+    for (int w = 0; w < kCountThreads / kWave; ++w) s += part[w];
     part_sum[blockIdx.x] = s;
   }
 }
 
-// One workgroup: cnt[5] = the 64-bit pair total (the sum of k_rank's
+// One workgroup: cnt[5] = the 64-bit pair total (the sum of k_depth_counts'
 // per-workgroup sums, in a fixed order); cnt[2] = pairs to process; cnt[3] =
 // the total when it overflows (pairs_overflow: beyond the pair capacity or
 // 2^31 - 1, or any earlier window of this state overflowed, cnt[4] sticky),
@@ -485,7 +491,7 @@ __global__ void __launch_bounds__(kTotalThreads)
     k_pairs_total(const unsigned long long *__restrict__ part_sum, int64_t *__restrict__ cnt,
                   int64_t pcap) {
   __shared__ unsigned long long wsum[kTotalThreads / kWave];
-  const int64_t nb = (cnt[1] + kRankThreads - 1) / kRankThreads;
+  const int64_t nb = (cnt[1] + kCountThreads - 1) / kCountThreads;
   unsigned long long s = 0;
   for (int64_t b = threadIdx.x; b < nb; b += kTotalThreads) s += part_sum[b];
   for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -1241,8 +1247,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                  int n_tiles, int tiles_per_view, float bg0, float bg1, float bg2,
                  const float *__restrict__ Tstate, const int *__restrict__ last_in,
                  const float *__restrict__ dl_drgb, const float *__restrict__ dl_ddepth,
-                 const uint32_t *__restrict__ rank_of, float2 *__restrict__ partial,
-                 int *__restrict__ frontier, const int *__restrict__ bslot,
+                 float2 *__restrict__ partial, uint64_t *__restrict__ frontier,
+                 const int *__restrict__ bslot,
                  const float *__restrict__ bound, const uint32_t *__restrict__ seg_off) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
@@ -1329,7 +1335,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
   // segment holding it (segment 0 when there is none) records the frontier
   const int top = max_last;
   if (threadIdx.x == 0 && ((top >= s_lo && top < s_hi) || (top < rg.x && seg == 0)))
-    frontier[gt] = top < rg.x ? -1 : (int)rank_of[(uint32_t)pairs[top]];
+    frontier[gt] = top < rg.x ? 0 : depth_order_key(rec, (uint32_t)pairs[top]);
   const int seg_top = min(top, s_hi - 1);
   for (int end = seg_top + 1; end > s_lo; end -= BS) {
     const int beg = max(s_lo, end - BS);
@@ -1585,8 +1591,7 @@ __global__ void __launch_bounds__(256)
     k_sum_partials(const int64_t *__restrict__ cnt, int64_t RS, int TW, int TH, int tiles_x,
                    int tiles_per_view, const float4 *__restrict__ rec,
                    const uint32_t *__restrict__ count, const uint32_t *__restrict__ seg_off,
-                   const uint32_t *__restrict__ rank_of,
-                   const int *__restrict__ frontier, const float2 *__restrict__ partial,
+                   const uint64_t *__restrict__ frontier, const float2 *__restrict__ partial,
                    float *__restrict__ s2d, int zero_undrawn) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
@@ -1604,7 +1609,8 @@ __global__ void __launch_bounds__(256)
     const uint64_t m = (uint64_t)__float_as_uint(D.y) | ((uint64_t)__float_as_uint(D.z) << 32);
     const int tile_base = (int)(r / n) * tiles_per_view;
     const uint32_t slot = slot_base(seg_off, D);
-    const int rank = (int)rank_of[r];
+    // the record's place in the depth order (depth_order_key, from C)
+    const uint64_t key = ((uint64_t)__float_as_uint(C.y) << 32) | (uint32_t)r;
     const uint32_t c = count[r];  // kept tiles: popcount(m), or n_rect beyond 64
     uint64_t mm = m;
     // the kept tiles in slot order (lowest mask bit first), four at a time:
@@ -1627,16 +1633,16 @@ __global__ void __launch_bounds__(256)
         }
         t[i] = tile_base + (ty0 + k / wc) * tiles_x + tx0 + k % wc;
       }
-      int f[4];
+      uint64_t f[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) f[i] = ok[i] ? frontier[t[i]] : -1;
+      for (int i = 0; i < 4; ++i) f[i] = ok[i] ? frontier[t[i]] : 0;
       float2 q[4][5];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const float2 *pp = partial + 5 * (int64_t)(slot + b + i);
 #pragma unroll
         for (int j = 0; j < 5; ++j) q[i][j] = make_float2(0.0f, 0.0f);
-        if (ok[i] && f[i] >= rank) {  // that tile's backward reached the record
+        if (ok[i] && f[i] >= key) {  // that tile's backward reached the record
 #pragma unroll
           for (int j = 0; j < 5; ++j) q[i][j] = pp[j];
         }
@@ -1840,8 +1846,8 @@ void launch_bwd_t(dcgs_state *s, hipStream_t st, const float *dl_drgb, const flo
   hipLaunchKernelGGL((k_raster_bwd<TW, TH, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, st,
                      s->pairs.p, s->ranges.p, s->witem.p, counters(s, st), s->rec.p, s->rs, s->W,
                      s->H, s->tiles_x, nt, s->tiles_x * s->tiles_y, s->bg[0], s->bg[1], s->bg[2],
-                     s->T_final.p, s->last.p, dl_drgb, dl_ddepth, s->rank_of.p, s->partial.p,
-                     s->frontier.p, s->bslot.p, s->bound.p, s->seg_off.p);
+                     s->T_final.p, s->last.p, dl_drgb, dl_ddepth, s->partial.p, s->frontier.p,
+                     s->bslot.p, s->bound.p, s->seg_off.p);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -1914,7 +1920,6 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   s->order.need(nr + 1);
   s->key_tmp.need(2 * (size_t)nr + 2);
   s->val_tmp.need(nr + 1);
-  s->rank_of.need(nr + 1);
   s->seg_tot.need((size_t)V * blocks_for(n_grid, kPrepThreads) + 1);
   s->seg_off.need((size_t)V * blocks_for(n_grid, kPrepThreads) + 2);
   s->tmask.need(nr + 1);
@@ -1930,7 +1935,7 @@ void size_buffers(dcgs_state *s, int64_t n_grid) {
   s->T_final.need(V * HW + 1);
   s->last.need(V * HW + 1);
   s->scan_part.need(scan_part_size(nr) + 2);
-  s->rank_part.need(nr / 256 + 2);
+  s->count_part.need(nr / 256 + 2);
 }
 
 // Projection, depth order and pair count for a grid of n_grid Gaussians
@@ -1957,14 +1962,14 @@ void enqueue_front(dcgs_state *s, const float *params, int64_t n_grid, int64_t s
     // depth order of all records: stable sort of the float32 depth bits
     sort_u32_pairs(sortkey, order, sortkey + RS + 1, s->val_tmp.p, nr, 32, s->hist, st,
                    cnt + 1);
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(nr, kRankThreads)), dim3(kRankThreads), 0, st,
-                       order, s->count.p, cnt, s->rank_of.p, sortkey + RS + 1, s->rank_part.p);
+    hipLaunchKernelGGL(k_depth_counts, dim3(blocks_for(nr, kCountThreads)), dim3(kCountThreads),
+                       0, st, order, s->count.p, cnt, sortkey + RS + 1, s->count_part.p);
     DCGS_LAUNCH_CHECK();
   }
   StageTimer te(ctx, DCGS_STAGE_SCAN_EMIT, st);
   // the depth sort's second key buffer holds the counts in depth order now
   scan_u32(sortkey + RS + 1, nullptr, s->scan.p, nr, s->scan_part.p, st, cnt + 1);
-  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(kTotalThreads), 0, st, s->rank_part.p, cnt,
+  hipLaunchKernelGGL(k_pairs_total, dim3(1), dim3(kTotalThreads), 0, st, s->count_part.p, cnt,
                      pcap);
   DCGS_LAUNCH_CHECK();
   // gradient slot bases of the projection's segments
@@ -2124,7 +2129,7 @@ void render_backward(dcgs_state *s, const float *params, int64_t n, int64_t stri
     int64_t *cnt = counters(s, st);
     hipLaunchKernelGGL(k_sum_partials, dim3(blocks_for(nr, 256)), dim3(256), 0, st, cnt,
                        s->rs, s->TW, s->TH, s->tiles_x, tpv, s->rec.p, s->count.p,
-                       s->seg_off.p, s->rank_of.p, s->frontier.p, s->partial.p, s2d,
+                       s->seg_off.p, s->frontier.p, s->partial.p, s2d,
                        grad2d ? 1 : 0);
     DCGS_LAUNCH_CHECK();
 #define DCGS_PBWD(D)                                                                        \

@@ -151,11 +151,16 @@ __global__ void __launch_bounds__(kSortThreads)
   for (int t = threadIdx.x; t < 256; t += kSortThreads) h[t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
-#pragma unroll 4
+  // all of the thread's keys in flight at once, then the counts
+  K key[kSortRounds];
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
-    int64_t i = base + r * kSortThreads + threadIdx.x;
-    if (i < n) atomicAdd(&h[digit_of(keys[i], shift, mask)], 1u);
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    key[r] = i < n ? keys[i] : K(0);
   }
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r)
+    if (base + r * kSortThreads + threadIdx.x < n) atomicAdd(&h[digit_of(key[r], shift, mask)], 1u);
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < bins; d += kSortThreads)
     hist[(int64_t)d * nb + blockIdx.x] = h[d];
