@@ -115,7 +115,10 @@ int dcgs_chunk_ids(dcgs_ctx *ctx, const float *mean, int64_t n, int64_t stride,
  *   ids:  device [n_chunks] ascending EncodedIDs of the occupied chunks
  *   out_ids: device [n_chunks] visible ids, ascending (union over views)
  *   out_mask: device [n_chunks] bit v set when view v sees the chunk
- *   out_count: device int32, number of visible ids written. */
+ *   out_count: device int32, number of visible ids written.
+ * Asynchronous on `stream`.  Its scratch belongs to the stream: calls on
+ * different streams of one context may overlap (a look-ahead selection on
+ * a side stream while the compute stream selects its own view). */
 int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views,
                        const uint64_t *ids, int n_chunks, double chunk_size,
                        uint64_t *out_ids, uint16_t *out_mask,

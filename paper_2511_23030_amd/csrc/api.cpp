@@ -159,7 +159,13 @@ int dcgs_select_chunks(dcgs_ctx *ctx, const dcgs_camera *cams, int n_views, cons
     DCGS_CHECK(n_chunks >= 0 && chunk_size > 0 && out_count &&
                    (n_chunks == 0 || (ids && out_ids && out_mask)),
                DCGS_E_INVALID, "select_chunks: bad buffers");
-    uint16_t *tmp = ctx->sel_mask.need((size_t)n_chunks + 1);
+    uint16_t *tmp;
+    {
+      std::lock_guard<std::mutex> lock(ctx->sel_mu);
+      auto &buf = ctx->sel_mask[stream];
+      if (!buf) buf = std::make_unique<dcgs::DevBuf<uint16_t>>();
+      tmp = buf->need((size_t)n_chunks + 1);
+    }
     dcgs::StageTimer tm(ctx, DCGS_STAGE_SELECT, S(stream));
     dcgs::launch_select(cams, n_views, ids, n_chunks, chunk_size, tmp, out_ids, out_mask,
                         out_count, S(stream));

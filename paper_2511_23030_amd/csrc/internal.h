@@ -7,6 +7,8 @@
 #include <array>
 #include <cstdint>
 #include <cstdio>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -101,7 +103,10 @@ struct dcgs_ctx {
   };
   std::vector<Mark> marks;
   std::vector<hipEvent_t> spare_events;
-  dcgs::DevBuf<uint16_t> sel_mask;
+  // chunk selection's per-chunk masks, one buffer per stream (selections on
+  // different streams may run at once)
+  std::mutex sel_mu;
+  std::unordered_map<void *, std::unique_ptr<dcgs::DevBuf<uint16_t>>> sel_mask;
   dcgs::DevBuf<uint8_t> kf_buf;   // keyframe selection: cameras, active ids, outputs
   uint16_t *noalloc_scratch = nullptr;  // this device's copy of the static selection scratch
   dcgs::DevBuf<int> flag;

@@ -62,9 +62,12 @@ class MappingLoop:
         view mask (host copies).  Runs on `stream` (default: the current
         stream) and waits for that stream only."""
         addr, n = self.pool.device_ids()
-        ids_t, mask_t, count_t = self._sel_buffers(n, stream is not None)
         arr = (D.Camera * len(cams))(*[D.Camera.of(c) for c in cams])
         with torch.cuda.stream(stream) if stream is not None else _nullctx():
+            # buffers of a side-stream selection come from that stream's
+            # allocations: memory the compute stream released may still be
+            # written by its queued kernels
+            ids_t, mask_t, count_t = self._sel_buffers(n, stream is not None)
             self.ctx.check(D.lib().dcgs_select_chunks(
                 self.ctx.h, C.cast(arr, C.c_void_p), len(cams), addr, n, self.s, D.ptr(ids_t),
                 D.ptr(mask_t), D.ptr(count_t), D.stream_handle(stream)))

@@ -123,15 +123,18 @@ class PrefetchNet:
         """EncodedIDs of the cells with P(visible in the next frames) >= tau,
         from the last 8 cameras (history[0] = current).  One sync of
         `stream`."""
-        if not hasattr(self, "_pick"):
-            self._pick = torch.empty(N_CAND, dtype=torch.int64, device="cuda")
-            self._pick_n = torch.zeros(1, dtype=torch.int32, device="cuda")
-            self._pick_logit = torch.empty(N_CAND, dtype=torch.float32, device="cuda")
         hist = list(history)[:HIST]
         hist += [hist[-1]] * (HIST - len(hist))
         arr, p = _cams(hist)
         thr = math.log(tau / (1.0 - tau))
         with torch.cuda.stream(stream) if stream is not None else _null():
+            # output buffers from the stream the prediction runs on (memory
+            # released on another stream may still be written by its queue)
+            if not hasattr(self, "_pick") or self._pick_stream is not stream:
+                self._pick = torch.empty(N_CAND, dtype=torch.int64, device="cuda")
+                self._pick_n = torch.zeros(1, dtype=torch.int32, device="cuda")
+                self._pick_logit = torch.empty(N_CAND, dtype=torch.float32, device="cuda")
+                self._pick_stream = stream
             self.ctx.check(D.lib().dcgs_prefetch_predict(
                 self.ctx.h, D.ptr(self.theta), D.ptr(self.wb), p, chunk_size, pos_unit, thr,
                 D.ptr(self._pick), D.ptr(self._pick_n), D.ptr(self._pick_logit),

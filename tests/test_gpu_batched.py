@@ -133,3 +133,28 @@ def test_window_with_ssim_and_depth_equals_sequential(ctx, room):
             assert (x == y).all()
     pool_a.close()
     pool_b.close()
+
+
+def test_side_stream_selection_while_compute_stream_is_busy(ctx, room):
+    """The look-ahead selection runs on a side stream while the compute
+    stream still has queued kernels, some writing small tensors that were
+    already released to the allocator: its buffers must not come from those
+    blocks (a queued write would land in the selection's count or ids)."""
+    params, cams_all = room
+    cams = cams_all[::12][:16]
+    pool, loop = _loop(ctx, params, 16)
+    ids_ref, masks_ref = loop.select_window(cams)
+    big = torch.ones(1 << 24, device="cuda")
+    for trial in range(3):
+        small = [torch.zeros(4, dtype=torch.float64, device="cuda") for _ in range(8)]
+        for _ in range(30):
+            big.mul_(1.0000001)           # a few ms of queued work
+        for x in small:
+            x += big[:4].double()         # queued writes into the small blocks ...
+        del small, x                      # ... which return to the allocator now
+        ids, masks = loop.prefetch_window(cams)
+        print(f"case side-stream selection trial {trial}: {ids.size} chunks", flush=True)
+        assert np.array_equal(ids, ids_ref) and np.array_equal(masks, masks_ref)
+        loop._side_sel = None             # the next trial allocates again
+    torch.cuda.synchronize()
+    pool.close()
