@@ -701,7 +701,11 @@ def main():
         Es.append(inbox)
     N, NV, Pp, E = (float(np.mean(x)) for x in (Ns, NVs, Ps, Es))
     Npx = w["W"] * w["H"] * V
-    stages = {k: v[0] / max(v[1], 1) for k, v in prof.items() if v[1] > 0}
+    # per window: a stage may time several spans in one window (scan and
+    # emission are two, the look-ahead selection adds one); the forward
+    # raster runs once per window
+    n_win = max(prof.get("raster_fwd", (0.0, 0))[1], 1)
+    stages = {k: v[0] / n_win for k, v in prof.items() if v[1] > 0}
     dominant = max(stages, key=stages.get)
     avg_ms = stages[dominant]
     # pixels per lane of the forward (bits 0-3) and backward (bits 4-7) rasters
