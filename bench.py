@@ -469,6 +469,8 @@ def main():
                     help="run warmup + profile-steps batched windows only (counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device copy (the HBM counter calibration)")
+    ap.add_argument("--no-equal-psnr", action="store_true",
+                    help="skip the time-to-equal-PSNR comparison of batched and plain")
     ap.add_argument("--no-prefetch-mlp", action="store_true",
                     help="skip the learned-prefetch study of the driving workloads")
     args = ap.parse_args()
@@ -569,7 +571,7 @@ def main():
             else:
                 wi = k % len(windows)
                 cams = [w["cams"][i] for i in windows[wi]]
-                if kind == "batched":
+                if kind.startswith("batched"):
                     loop.window_step(cams, tstack[wi], sel=sel)
                 elif kind == "graph":
                     loop.window_step_graph(cams, tstack[wi], sel=sel)
@@ -636,8 +638,9 @@ def main():
     n_timed = n_views
     dt = t_g
     # equal-PSNR check: every pool received the same windows, so the same update
-    psnrs = {}
-    for name, loop_ in (("graph", loop_g), ("batched", loop_b), ("sequential", loop_s)):
+    def window_psnr(loop_) -> float:
+        """Mean PSNR of the loop's Gaussians over every window's keyframes."""
+        loop_._window_buffers(V)
         acc = []
         for wi in range(len(windows)):
             cams = [w["cams"][i] for i in windows[wi]]
@@ -650,7 +653,11 @@ def main():
                               norm=3.0 * w["W"] * w["H"])
             s = loop_.stats.cpu().numpy()
             acc.append(10 * math.log10(1.0 / (s[1] / (V * 3 * w["W"] * w["H"]))))
-        psnrs[name] = float(np.mean(acc))
+        return float(np.mean(acc))
+
+    psnrs = {}
+    for name, loop_ in (("graph", loop_g), ("batched", loop_b), ("sequential", loop_s)):
+        psnrs[name] = window_psnr(loop_)
     psnr_b, psnr_s, psnr_g = psnrs["batched"], psnrs["sequential"], psnrs["graph"]
     log(f"graph {n_timed / t_g:.1f} views/s, batched {n_timed / t_b:.1f} views/s, sequential "
         f"{n_timed / t_s:.1f} views/s, PSNR {psnr_g:.4f} / {psnr_b:.4f} / {psnr_s:.4f} dB")
@@ -665,6 +672,42 @@ def main():
     t_p = run(loop_b, "plain", n_plain)
     plain_rate = n_plain / t_p
     l1, psnr = loop_b.loss_psnr(3 * w["W"] * w["H"])
+    equal_psnr = None
+    if not args.no_equal_psnr and len(windows) <= 16:  # a cheap evaluation set
+        # time to an equal PSNR from the same start: the plain schedule (one
+        # Adam step per keyframe) over n_plain keyframes, then batched
+        # windows (one Adam step per window) until their PSNR on the same
+        # keyframes reaches the plain run's, or 16 n_plain views
+        pool_e, loop_e = make_loop()
+        if tuned1 is not None:
+            loop_e.tile, loop_e.ppt = tuned1[:2], tuned1[2]
+        t_pe = run(loop_e, "plain_equal", n_plain)
+        if tuned is not None:
+            loop_e.tile, loop_e.ppt = tuned[:2], tuned[2]
+        psnr_pe = window_psnr(loop_e)
+        pool_e.close()
+        del loop_e
+        pool_e, loop_e = make_loop()
+        if tuned is not None:
+            loop_e.tile, loop_e.ppt = tuned[:2], tuned[2]
+        t_be, views_be, psnr_be = 0.0, 0, window_psnr(loop_e)
+        while psnr_be < psnr_pe and views_be < 16 * n_plain:
+            t_be += run(loop_e, "batched_equal", V)
+            views_be += V
+            psnr_be = window_psnr(loop_e)
+        pool_e.close()
+        del loop_e
+        equal_psnr = {"plain": {"views": n_plain, "seconds": round(t_pe, 3),
+                                "views_per_s": round(n_plain / t_pe, 2),
+                                "psnr_db": round(psnr_pe, 4)},
+                      "batched": {"views": views_be, "seconds": round(t_be, 3),
+                                  "views_per_s": round(views_be / max(t_be, 1e-9), 2),
+                                  "psnr_db": round(psnr_be, 4),
+                                  "reached": bool(psnr_be >= psnr_pe)},
+                      "delta_db": round(psnr_be - psnr_pe, 4),
+                      "time_ratio_batched_over_plain": round(t_be / t_pe, 3)}
+        log(f"equal PSNR: plain {n_plain} views in {t_pe:.2f} s to {psnr_pe:.4f} dB; batched "
+            f"{views_be} views in {t_be:.2f} s to {psnr_be:.4f} dB")
     prefetch_report = None
     if walk and not args.no_prefetch_mlp:
         prefetch_report, net = prefetch_study(ctx, w, make_loop, targets, max(n_plain, 400), log)
@@ -782,6 +825,7 @@ def main():
                    "psnr_batched_db": round(psnr_b, 4), "psnr_sequential_db": round(psnr_s, 4),
                    "psnr_graph_db": round(psnr_g, 4),
                    "psnr_delta_db": round(max(abs(psnr_b - psnr_s), abs(psnr_g - psnr_s)), 6),
+                   "equal_psnr": equal_psnr,
                    "prefetch": prefetch_report,
                    "keyframe_schedule": schedule_report,
                    "next_rows": extra_rows,
