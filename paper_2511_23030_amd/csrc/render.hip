@@ -1252,7 +1252,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                  const float *__restrict__ bound, const uint32_t *__restrict__ seg_off) {
   constexpr int NT = TW * TH / PPT;
   constexpr int NW = NT / kWave;
-  constexpr int BS = NT < 128 ? NT : 128;  // records per batch
+  // records per batch: at most 64, so a tile of several wavefronts keeps
+  // its LDS (records, masks, per-wavefront reductions) small enough for
+  // eight workgroups per CU
+  constexpr int BS = NT < 64 ? NT : 64;
   constexpr int NC = 10;
   __shared__ float4 sA[BS], sB[BS], sC[BS];
   __shared__ uint32_t sP[BS], sM[BS];  // gradient slot base of the record, cell mask
