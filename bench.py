@@ -119,7 +119,7 @@ def stage_bytes(stage: str, N: float, P: float, Npx: float, R: int) -> float:
         "preprocess": (g + 64) * N,
         "depth_sort": 64 * N,
         "tile_sort": 32 * P,
-        "preprocess_bwd": (2 * g + 48 * 0) * N,
+        "preprocess_bwd": 2 * g * N,
         "adam": (g + 4 + 3 * g + 4 + 3 * g + 4) * N,
         "loss": 36 * Npx,
     }.get(stage, 0.0)
