@@ -127,3 +127,47 @@ def test_split_lists_batched_equals_per_view(ctx, shape, kind):
     assert torch.equal(grad_b[:, :n], grad_s[:, :n])
     st_b.close()
     st_s.close()
+
+
+def test_graph_replays_with_split_lists_match_eager(ctx):
+    """The graph-captured window on the mixed scene at 8x8 tiles (forward-
+    split lists of about 8 segments beside lists split for the backward
+    only): images, loss and the pool after each replay equal the eager
+    window bit for bit (the split work lists, their counts and the
+    forward-split grids live on the device)."""
+    from paper_2511_23030_amd import mapping
+    P = _scene("mixed", 56)
+    V = 3
+    pools, loops = [], []
+    for _ in range(2):
+        pool = D.Pool(ctx, 0, budget=10**9)
+        pool.ingest(P, 2.0)
+        loop = mapping.MappingLoop(ctx, pool, 0, 2.0, 300_000, W, H, (8, 8), ppt=1)
+        loop._window_buffers(V)
+        pools.append(pool)
+        loops.append(loop)
+    loop_a, loop_b = loops
+    loop_b.build_graph(V, pair_capacity=2_000_000)
+    rng = np.random.default_rng(57)
+    for w in range(3):
+        cams = [_cam(0.01 * (w * V + v)) for v in range(V)]
+        tg = torch.from_numpy(rng.uniform(0.0, 1.0, (V, 3, H, W)).astype(np.float32)).cuda()
+        print(f"case graph split lists window {w}", flush=True)
+        loop_a.window_step(cams, tg)
+        loop_b.window_step_graph(cams, tg)
+        loop_b.sync_graph()
+        torch.cuda.synchronize()
+        lens = loop_a.state.export(loop_a.rgb_v.device, H, W)["ranges"].cpu().numpy()
+        lens = lens[:, 1] - lens[:, 0]
+        assert lens.max() > (FWD_SPLIT - 1) * SEG_PER_PIXEL * 64   # some forward-split tiles
+        assert torch.equal(loop_a.rgb_v, loop_b.rgb_v)
+        assert torch.equal(loop_a.depth_v, loop_b.depth_v)
+        assert torch.equal(loop_a.stats, loop_b.stats)
+    for pool_a, pool_b in [pools]:
+        ids, counts = pool_a.chunks()
+        for cid, c in zip(ids, counts):
+            for x, y in zip(pool_a.read_chunk(cid, c), pool_b.read_chunk(cid, c)):
+                assert (x == y).all(), cid
+    loop_b.win.close()
+    for pool in pools:
+        pool.close()
