@@ -781,12 +781,13 @@ __device__ __forceinline__ Box uniform_box(const float4 &C) {
 
 // Long lists are split for the backward into segments of 64 list positions
 // per pixel of the tile (4096 for 8x8 tiles, 16384 for 16x16; a multiple of
-// every raster batch size): one workgroup per (tile, segment).  The forward walks the whole list as before and, for a
-// split tile, stores each pixel's compositing state (T, colour, depth) at
-// every segment end (the list's end included), so a segment's backward
+// every raster batch size): one workgroup per (tile, segment).  For a split
+// tile the forward stores each pixel's compositing state (T, colour, depth)
+// at every segment end (the list's end included), so a segment's backward
 // starts where the reverse sweep of the whole list would be at that
 // position: T from the stored state, and the colour and depth composited
-// behind it as the final values minus those stored.
+// behind it as the final values minus those stored.  (A list of kFwdSplit
+// or more segments is split in the forward as well; see k_raster_fwd.)
 constexpr int kSegPerPixel = 64;
 constexpr int kStateVals = 5;  // T, colour r, g, b, depth
 
