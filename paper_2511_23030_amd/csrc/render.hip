@@ -1588,34 +1588,55 @@ __device__ inline void param_grads(const float *__restrict__ P, int64_t stride, 
 }
 
 // Per record (view v, Gaussian g) with a non-empty tile rect: the sum of its
-// per-tile partials in slot order (only tiles whose backward reached it),
-// written as ten planes s2d[c][r].  Integer box, slot base and kept-tile
-// mask from the record.
+// per-tile partials (only tiles whose backward reached it), written as ten
+// planes s2d[c][r].  Integer box, slot base and kept-tile mask from the
+// record.  A record of at most kSumBig kept tiles is summed by its own
+// thread in slot order; a wavefront's larger records are then summed one at
+// a time by the whole wavefront (slot s on lane s mod 64, each lane in slot
+// order, then the butterfly), so one record with hundreds of tiles no longer
+// holds 63 idle lanes for hundreds of steps.  Which way a record goes, and
+// so its additions, depends on the record alone.
+constexpr uint32_t kSumBig = 16;
+
+__device__ __forceinline__ uint32_t lane_u32(uint32_t x, int src) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, src);
+}
+__device__ __forceinline__ uint64_t lane_u64(uint64_t x, int src) {
+  return (uint64_t)lane_u32((uint32_t)x, src) | ((uint64_t)lane_u32((uint32_t)(x >> 32), src) << 32);
+}
+
 __global__ void __launch_bounds__(256)
     k_sum_partials(const int64_t *__restrict__ cnt, int64_t RS, int TW, int TH, int tiles_x,
                    int tiles_per_view, const float4 *__restrict__ rec,
                    const uint32_t *__restrict__ count, const uint32_t *__restrict__ seg_off,
                    const uint64_t *__restrict__ frontier, const float2 *__restrict__ partial,
                    float *__restrict__ s2d, int zero_undrawn) {
+  if (cnt[3] != 0) return;  // uniform: the window overflowed
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = cnt[0], nr = cnt[1];
-  if (r >= nr || cnt[3] != 0) return;
-  float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  // the projection backward reads only drawn records: an undrawn one's
-  // planes are written (as zeros) only for a caller's own output buffer
-  if (count[r] == 0 && !zero_undrawn) return;
-  if (count[r] > 0) {
+  const int lane = threadIdx.x & (kWave - 1);
+  // no early exit below: every lane of a wavefront takes part in summing
+  // its large records
+  const bool valid = r < nr;
+  const uint32_t c = valid ? count[r] : 0u;  // kept tiles: popcount(m), or n_rect beyond 64
+  int tx0 = 0, ty0 = 0, wc = 1, n_rect = 0, tile_base = 0;
+  uint64_t m = 0, key = 0;
+  uint32_t slot = 0;
+  if (c > 0) {
     const float4 C = rec[4 * r + 2], D = rec[4 * r + 3];
     const uint32_t bx = __float_as_uint(C.z), by = __float_as_uint(C.w);
-    const int tx0 = (int)(bx & 0xFFFF) / TW, tx1 = (int)(bx >> 16) / TW;
-    const int ty0 = (int)(by & 0xFFFF) / TH, ty1 = (int)(by >> 16) / TH;
-    const int wc = tx1 - tx0 + 1, n_rect = wc * (ty1 - ty0 + 1);
-    const uint64_t m = (uint64_t)__float_as_uint(D.y) | ((uint64_t)__float_as_uint(D.z) << 32);
-    const int tile_base = (int)(r / n) * tiles_per_view;
-    const uint32_t slot = slot_base(seg_off, D);
+    tx0 = (int)(bx & 0xFFFF) / TW;
+    ty0 = (int)(by & 0xFFFF) / TH;
+    wc = (int)(bx >> 16) / TW - tx0 + 1;
+    n_rect = wc * ((int)(by >> 16) / TH - ty0 + 1);
+    m = (uint64_t)__float_as_uint(D.y) | ((uint64_t)__float_as_uint(D.z) << 32);
+    tile_base = (int)(r / n) * tiles_per_view;
+    slot = slot_base(seg_off, D);
     // the record's place in the depth order (depth_order_key, from C)
-    const uint64_t key = ((uint64_t)__float_as_uint(C.y) << 32) | (uint32_t)r;
-    const uint32_t c = count[r];  // kept tiles: popcount(m), or n_rect beyond 64
+    key = ((uint64_t)__float_as_uint(C.y) << 32) | (uint32_t)r;
+  }
+  if (c <= kSumBig) {
+    float s[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     uint64_t mm = m;
     // the kept tiles in slot order (lowest mask bit first), four at a time:
     // their frontier reads, then the partial reads of the reached ones, are
@@ -1660,9 +1681,41 @@ __global__ void __launch_bounds__(256)
           s[2 * j + 1] += q[i][j].y;
         }
     }
-  }
+    // the projection backward reads only drawn records: an undrawn one's
+    // planes are written (as zeros) only for a caller's own output buffer
+    if (valid && (c > 0 || zero_undrawn)) {
 #pragma unroll
-  for (int c = 0; c < 10; ++c) s2d[c * RS + r] = s[c];
+      for (int j = 0; j < 10; ++j) s2d[j * RS + r] = s[j];
+    }
+  }
+  const int c_red = bitrev4(lane & 15);  // the value a reduction leaves in this lane
+  for (uint64_t big = __ballot(c > kSumBig); big != 0; big &= big - 1) {
+    const int src = __builtin_ctzll(big);
+    const uint32_t bc = lane_u32(c, src), bslot = lane_u32(slot, src);
+    const int btx0 = (int)lane_u32((uint32_t)tx0, src), bty0 = (int)lane_u32((uint32_t)ty0, src);
+    const int bwc = (int)lane_u32((uint32_t)wc, src), bn_rect = (int)lane_u32((uint32_t)n_rect, src);
+    const int btile_base = (int)lane_u32((uint32_t)tile_base, src);
+    const uint64_t bm = lane_u64(m, src), bkey = lane_u64(key, src);
+    const int64_t br = (int64_t)lane_u64((uint64_t)r, src);
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = 0.0f;
+    for (uint32_t sl = (uint32_t)lane; sl < bc; sl += kWave) {
+      const int k = bn_rect > 64 ? (int)sl : nth_set_bit(bm, (int)sl);
+      const int t = btile_base + (bty0 + k / bwc) * tiles_x + btx0 + k % bwc;
+      if (frontier[t] >= bkey) {
+        const float2 *pp = partial + 5 * (int64_t)(bslot + sl);
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          const float2 q = pp[j];
+          v[2 * j] += q.x;
+          v[2 * j + 1] += q.y;
+        }
+      }
+    }
+    const float sum = wave_reduce10(v);
+    if (lane < 16 && c_red < 10) s2d[c_red * RS + br] = sum;
+  }
 }
 
 // Projection backward over all views: one thread per Gaussian; record
