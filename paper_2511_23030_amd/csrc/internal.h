@@ -86,7 +86,7 @@ inline void digit_plan(int bits, int *passes, int *width) {
     *width = 0;
     return;
   }
-  *passes = (bits + 7) / 8;
+  *passes = (bits + 8) / 9;  // digits of at most 9 bits (16 bits: two of 8; 17: 9 + 8)
   *width = (bits + *passes - 1) / *passes;
 }
 

@@ -141,14 +141,16 @@ __device__ inline uint32_t digit_of(K key, int shift, uint32_t mask) {
   return (uint32_t)(key >> shift) & mask;
 }
 
-template <typename K>
+// Digits of up to 8 bits take 256-bin tables, of 9 bits 512 (a 17- or
+// 18-bit key then sorts in two passes instead of three).
+template <typename K, int kBins>
 __global__ void __launch_bounds__(kSortThreads)
     k_rs_hist(const K *__restrict__ keys, const int64_t *__restrict__ n_dev, int64_t n,
               int shift, int width, uint32_t *__restrict__ hist, int64_t nb) {
-  __shared__ uint32_t h[256];
+  __shared__ uint32_t h[kBins];
   n = count_of(n_dev, n);
   const uint32_t bins = 1u << width, mask = bins - 1;
-  for (int t = threadIdx.x; t < 256; t += kSortThreads) h[t] = 0;
+  for (int t = threadIdx.x; t < kBins; t += kSortThreads) h[t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   // all of the thread's keys in flight at once, then the counts
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__(kSortThreads)
 // after the equal digits of the wavefront's earlier steps.  One scan of the
 // per-wavefront counts, digit-major, then gives every key its slot: the
 // workgroup synchronises a fixed number of times, not once per step.
-template <typename K, bool kVals>
+template <typename K, bool kVals, int kBins>
 __global__ void __launch_bounds__(kSortThreads)
     k_rs_scatter(const K *__restrict__ kin, const uint32_t *__restrict__ vin,
                  K *__restrict__ kout, uint32_t *__restrict__ vout,
@@ -188,18 +190,20 @@ __global__ void __launch_bounds__(kSortThreads)
   constexpr int kSteps = kPerWave / kWave;           // 16
   __shared__ K sk[kSortTile];
   __shared__ uint32_t sv[kVals ? kSortTile : 1];
-  __shared__ uint32_t gofs[256];  // global offset of the block's run of digit d
-  __shared__ uint32_t lofs[256];  // start of digit d's run in sk
-  __shared__ uint32_t wcnt[kSortWaves][256];  // per wavefront: count, then slot base
+  static_assert(kBins % kSortThreads == 0, "whole digits per thread");
+  constexpr int kPer = kBins / kSortThreads;  // digits per thread in the slot scan
+  __shared__ uint32_t gofs[kBins];  // global offset of the block's run of digit d
+  __shared__ uint32_t lofs[kBins];  // start of digit d's run in sk
+  __shared__ uint32_t wcnt[kSortWaves][kBins];  // per wavefront: count, then slot base
   n = count_of(n_dev, n);
   const uint32_t bins = 1u << width, mask = bins - 1;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= n) return;  // uniform across the block
   const int cnt = (int)min<int64_t>(kSortTile, n - base);
-  for (int t = threadIdx.x; t < kSortWaves * 256; t += kSortThreads) (&wcnt[0][0])[t] = 0;
-  if (threadIdx.x < 256) gofs[threadIdx.x] = threadIdx.x < bins ?
-      offs[(int64_t)threadIdx.x * nb + blockIdx.x] : 0u;
+  for (int t = threadIdx.x; t < kSortWaves * kBins; t += kSortThreads) (&wcnt[0][0])[t] = 0;
+  for (int d = threadIdx.x; d < kBins; d += kSortThreads)
+    gofs[d] = (uint32_t)d < bins ? offs[(int64_t)d * nb + blockIdx.x] : 0u;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
   K key[kSteps];
@@ -232,24 +236,35 @@ __global__ void __launch_bounds__(kSortThreads)
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  {  // slot bases: exclusive scan over (digit, wavefront), digit-major
-    const uint32_t d = threadIdx.x;
-    uint32_t c[kSortWaves], tot = 0;
+  {  // slot bases: exclusive scan over (digit, wavefront), digit-major;
+     // thread t takes digits kPer t .. kPer t + kPer - 1
+    uint32_t c[kPer][kSortWaves], tot[kPer], all = 0;
 #pragma unroll
-    for (int k = 0; k < kSortWaves; ++k) {
-      c[k] = d < bins ? wcnt[k][d] : 0u;
-      tot += c[k];
-    }
-    uint32_t excl;
-    block_exclusive_scan(tot, &excl);
-    if (d < bins) {
-      lofs[d] = excl;
-      uint32_t run = excl;
+    for (int p = 0; p < kPer; ++p) {
+      const uint32_t d = threadIdx.x * kPer + p;
+      tot[p] = 0;
 #pragma unroll
       for (int k = 0; k < kSortWaves; ++k) {
-        wcnt[k][d] = run;
-        run += c[k];
+        c[p][k] = d < bins ? wcnt[k][d] : 0u;
+        tot[p] += c[p][k];
       }
+      all += tot[p];
+    }
+    uint32_t excl;
+    block_exclusive_scan(all, &excl);
+#pragma unroll
+    for (int p = 0; p < kPer; ++p) {
+      const uint32_t d = threadIdx.x * kPer + p;
+      if (d < bins) {
+        lofs[d] = excl;
+        uint32_t run = excl;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+          wcnt[k][d] = run;
+          run += c[p][k];
+        }
+      }
+      excl += tot[p];
     }
   }
   __syncthreads();
@@ -304,13 +319,21 @@ void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
   uint32_t *h = hist.need(radix_scratch_bins(n, bins));
   uint32_t *scanned = h + tab + 1;
   uint32_t *part = scanned + tab + 1;
-  hipLaunchKernelGGL(k_rs_hist<K>, dim3((unsigned)nb), dim3(kSortThreads), 0,
-                     st, kin, n_dev, n, shift, width, h, nb);
+  DCGS_CHECK(width >= 1 && width <= 9, DCGS_E_INVALID, "radix pass: 1..9-bit digits");
+  if (width <= 8)
+    hipLaunchKernelGGL((k_rs_hist<K, 256>), dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin,
+                       n_dev, n, shift, width, h, nb);
+  else
+    hipLaunchKernelGGL((k_rs_hist<K, 512>), dim3((unsigned)nb), dim3(kSortThreads), 0, st, kin,
+                       n_dev, n, shift, width, h, nb);
   DCGS_LAUNCH_CHECK();
   scan_u32(h, nullptr, scanned, tab, part, st);
-  hipLaunchKernelGGL((k_rs_scatter<K, kVals>), dim3((unsigned)nb),
-                     dim3(kSortThreads), 0, st, kin, vin, kout, vout, n_dev, n, shift,
-                     width, h, scanned, nb);
+  if (width <= 8)
+    hipLaunchKernelGGL((k_rs_scatter<K, kVals, 256>), dim3((unsigned)nb), dim3(kSortThreads), 0,
+                       st, kin, vin, kout, vout, n_dev, n, shift, width, h, scanned, nb);
+  else
+    hipLaunchKernelGGL((k_rs_scatter<K, kVals, 512>), dim3((unsigned)nb), dim3(kSortThreads), 0,
+                       st, kin, vin, kout, vout, n_dev, n, shift, width, h, scanned, nb);
   DCGS_LAUNCH_CHECK();
 }
 
@@ -320,7 +343,7 @@ size_t scan_part_size(int64_t n) {
   return (size_t)((n + kScanTile - 1) / kScanTile) + 2;
 }
 
-size_t radix_scratch(int64_t n) { return radix_scratch_bins(n, 256); }
+size_t radix_scratch(int64_t n) { return radix_scratch_bins(n, 512); }
 
 void scan_u32(const uint32_t *in, const uint32_t *gather, uint32_t *out,
               int64_t n, uint32_t *part, hipStream_t st, const int64_t *n_dev) {
